@@ -1,0 +1,308 @@
+/*
+ * chebtd -- Chebyshev time propagation of quantum states on one AMD MI355X
+ * (gfx950) GPU.  C ABI.
+ *
+ * Method: Fehske, Schleede, Schubert, Wellein, Filinov, Bishop, "Numerical
+ * approaches to time evolution of complex quantum systems", arXiv:0907.3022,
+ * Sect. 2.2.  One time step applies
+ *     U(dt) = e^{-i b dt} [ c_0 + 2 sum_{k=1}^{M} c_k T_k(H~) ],  eq. (U_1)
+ * with H~ = (H - b)/a, c_k = (-i)^k J_k(a dt), computed through the
+ * recursion v_{k+1} = 2 H~ v_k - v_{k-1}, v_1 = H~ v_0, v_0 = psi, and
+ * truncated at the order M beyond which every |J_k(a dt)| < tol
+ * (eq. (dec_Bessel)).  hbar = 1.
+ *
+ * Conventions shared by every entry point
+ *  - Complex vectors are complex128, interleaved (re, im), contiguous, passed
+ *    as double* pointing at the first real part.  Real vectors are float64.
+ *  - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *    tensors on the context's device); *_host are host pointers.
+ *  - The caller owns every array it passes.  Builders borrow device arrays
+ *    (potentials, CSR): they must stay alive and unchanged until the next
+ *    builder call on the context or chebtd_destroy.
+ *  - All GPU work is enqueued on the context's stream (chebtd_create) and is
+ *    asynchronous unless a function says it synchronises.
+ *  - Every function returns a status (0 = CHEBTD_OK, negative = error) and
+ *    never throws; chebtd_last_error() describes the last failure.  A
+ *    failing call leaves the context usable unless it returns CHEBTD_E_HIP.
+ *  - One context must not be used from two host threads at once.
+ */
+#ifndef CHEBTD_H
+#define CHEBTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define CHEBTD_OK 0
+#define CHEBTD_E_ARG (-1)      /* bad argument: null pointer, size, range  */
+#define CHEBTD_E_HIP (-2)      /* a HIP runtime call failed                 */
+#define CHEBTD_E_DIVERGED (-3) /* norm changed or became non-finite: the   */
+                               /* spectral bounds do not enclose H          */
+#define CHEBTD_E_OOM (-4)      /* device or host allocation failed          */
+#define CHEBTD_E_STATE (-5)    /* call out of order (no H, no plan, ...)    */
+#define CHEBTD_E_TIMEOUT (-6)  /* a persistent kernel's bounded wait ran   */
+                               /* out; its results are invalid              */
+
+/* ---- honeycomb ribbon edges ------------------------------------------- */
+#define CHEBTD_ZIGZAG 0
+#define CHEBTD_ARMCHAIR 1
+
+/* ---- chebtd_propagate flags ------------------------------------------- */
+#define CHEBTD_KEEP_CHECKPOINTS 1u /* store psi at every step for adjoint  */
+#define CHEBTD_NO_CHECK 2u         /* skip the end-of-call norm check (no  */
+                                   /* host synchronisation)                 */
+#define CHEBTD_GRAPH 4u            /* replay each pair of steps from a     */
+                                   /* captured hipGraph                     */
+#define CHEBTD_NO_PERSISTENT 8u    /* small chains: one launch per          */
+                                   /* iteration instead of the one-         */
+                                   /* workgroup persistent kernel           */
+
+typedef struct chebtd_ctx chebtd_ctx;
+
+/* ======================================================================= */
+/* Context                                                                  */
+/* ======================================================================= */
+
+/* Create a context bound to the current HIP device and `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+int chebtd_create(chebtd_ctx **out, void *hip_stream);
+
+/* Release every device buffer the context owns.  NULL is a no-op. */
+int chebtd_destroy(chebtd_ctx *ctx);
+
+/* Re-bind the context to another stream of the same device. */
+int chebtd_set_stream(chebtd_ctx *ctx, void *hip_stream);
+
+/* Text of the last error on `ctx` (or of the last failed chebtd_create when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char *chebtd_last_error(const chebtd_ctx *ctx);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int chebtd_version(void);
+
+/* ======================================================================= */
+/* Hamiltonians (Sect. 3).  Each call replaces the context's Hamiltonian    */
+/* and invalidates its bounds and plan.                                     */
+/* ======================================================================= */
+
+/* 1D finite-difference Hamiltonian of Sect. 3.1: H = -(1/2) d^2/dx^2 + V(x)
+ * on n points with spacing dx (m = hbar = 1), three-point Laplacian,
+ * Dirichlet ends: H_jj = 1/dx^2 + V_j, H_{j,j+-1} = -1/(2 dx^2).
+ * V_dev: float64[n] device array (borrowed).  n >= 1, dx > 0. */
+int chebtd_h_chain1d(chebtd_ctx *ctx, int64_t n, double dx, const double *V_dev);
+
+/* Honeycomb ribbon, eq. (model): H = -t sum_<ij> (c_i^+ c_j + h.c.)
+ * + sum_j eps_j n_j, drawn as a brick wall on a width x length grid, site
+ * index y*length + x.  CHEBTD_ZIGZAG: sites bond to (x+-1, y) and to
+ * (x, y+1) if x+y is even, (x, y-1) if odd (zigzag edges at y = 0 and
+ * y = width-1).  CHEBTD_ARMCHAIR: sites bond to (x, y+-1) and to (x+1, y)
+ * if x+y is even, (x-1, y) if odd (armchair edges along x).  Open
+ * boundaries.  eps_dev: float64[width*length] device array (borrowed). */
+int chebtd_h_honeycomb(chebtd_ctx *ctx, int64_t width, int64_t length, int edge,
+                       double t_hop, const double *eps_dev);
+
+/* General Hermitian sparse H in CSR form (rows sorted or not, each entry
+ * once): rowptr_dev int64[n+1], col_dev int32[nnz], val_dev complex128[nnz]
+ * (interleaved), all device arrays (borrowed).  The structure is checked on
+ * the device (synchronises): CHEBTD_E_ARG if rowptr does not run from 0 to
+ * nnz without decreasing or a column lies outside [0, n).  The values must
+ * describe a Hermitian matrix; that is not checked. */
+int chebtd_h_csr(chebtd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr_dev,
+                 const int32_t *col_dev, const double *val_dev);
+
+/* Generalised Holstein Hamiltonian, eq. (ghm), one spinless electron on L
+ * sites (ring if periodic != 0, which needs L >= 3; open chain otherwise)
+ * times phonon states with total phonon number <= nph (Sect. 3.3):
+ *   H = sum_i Delta_i n_i - t sum_i (c_i^+ c_{i+1} + h.c.)
+ *       - sum_i g_i w0 (b_i^+ + b_i) n_i + w0 sum_i b_i^+ b_i.
+ * Basis: phonon configurations ordered by total phonon number, then
+ * lexicographically ascending in (n_1..n_L) (n_1 most significant); state
+ * index = rank * L + electron site.  g_host, Delta_host: float64[L] host
+ * arrays (copied).  The context builds the matrix on the host and owns the
+ * device copy, plus the occupation tables used by chebtd_holstein_obs. */
+int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0,
+                      const double *g_host, const double *Delta_host, int periodic);
+
+/* Host-side builder of the same Holstein matrix as CSR.  Call once with
+ * rowptr/col/val = NULL to receive *n_out and *nnz_out, then again with
+ * arrays of those sizes (rowptr int64[n+1], col int32[nnz], val complex128
+ * [nnz]).  Entries of a row are sorted by column.  Needs no GPU. */
+int chebtd_holstein_csr_host(int L, int nph, double t, double w0, const double *g_host,
+                             const double *Delta_host, int periodic, int64_t *n_out,
+                             int64_t *nnz_out, int64_t *rowptr, int32_t *col, double *val);
+
+/* Occupation table of the Holstein basis above: occ[r*L + j] = phonons on
+ * site j in configuration r (uint8[count*L]).  occ = NULL returns only
+ * *count_out.  Needs no GPU. */
+int chebtd_holstein_occupations(int L, int nph, int64_t *count_out, uint8_t *occ);
+
+/* Dimension of the current Hamiltonian (0 if none). */
+int64_t chebtd_dim(const chebtd_ctx *ctx);
+
+/* ======================================================================= */
+/* Spectral bounds and plan (Sect. 2.2)                                     */
+/* ======================================================================= */
+
+/* Gershgorin bounds of the current H: emin = min_i (H_ii - sum_{j!=i}|H_ij|),
+ * emax = max_i (H_ii + sum_{j!=i}|H_ij|), computed on the device.
+ * Synchronises the stream.  Does not change the context's bounds. */
+int chebtd_gershgorin(chebtd_ctx *ctx, double *emin, double *emax);
+
+/* Set the bounds used for H~ = (H-b)/a: b = (emax+emin)/2,
+ * a = (emax - emin + alpha (emax-emin))/2 (the paper uses alpha = 0.01).
+ * CHEBTD_E_ARG unless emax > emin and alpha >= 0. */
+int chebtd_set_bounds(chebtd_ctx *ctx, double emin, double emax, double alpha);
+
+/* Compute the weights of eq. (U_1) for step dt on the host (Miller's
+ * backward recurrence for J_k) and upload them: gamma_0 = e^{-ib dt} J_0,
+ * gamma_k = 2 e^{-ib dt} (-i)^k J_k(a dt), k = 1..M, where M is the last
+ * order kept: |J_k(a dt)| < tol for every k > M (tol = 1e-15 in the
+ * paper's spirit; tol <= 0 selects 1e-15).  Needs bounds.  Allocates the
+ * context's work vectors; no later call allocates except where stated. */
+int chebtd_plan(chebtd_ctx *ctx, double dt, double tol, int *M_out);
+
+/* Like chebtd_plan but with a caller-chosen order M >= 0. */
+int chebtd_plan_order(chebtd_ctx *ctx, double dt, int M);
+
+/* Copy out the current plan: gamma_host complex128[M+1] (may be NULL),
+ * a, b, dt and M (each may be NULL). */
+int chebtd_get_plan(const chebtd_ctx *ctx, double *gamma_host, double *a, double *b,
+                    double *dt, int *M);
+
+/* ======================================================================= */
+/* Propagation                                                              */
+/* ======================================================================= */
+
+/* Advance psi_dev (complex128[n], in/out) by K steps of dt.
+ * norm_dev / energy_dev (float64[K] device arrays, or NULL) receive, for
+ * s = 0..K-1, <psi_s|psi_s> and <psi_s|H|psi_s> of the state entering step
+ * s (psi_s = state after s steps).  Unless CHEBTD_NO_CHECK is set the call
+ * synchronises at the end and returns CHEBTD_E_DIVERGED if the final norm
+ * is not finite or differs from the initial one by more than the check
+ * tolerance (chebtd_set_check_tol, default 1e-6 relative).
+ * CHEBTD_KEEP_CHECKPOINTS stores psi_s for the adjoint; it needs
+ * chebtd_reserve_adjoint with K <= its max_steps. */
+int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_dev,
+                     double *energy_dev, unsigned flags);
+
+/* Relative norm tolerance of the end-of-call check (default 1e-6). */
+int chebtd_set_check_tol(chebtd_ctx *ctx, double rel_tol);
+
+/* ======================================================================= */
+/* Observables (Sect. 3.1 densities, Fig. 3 polaron quantities)             */
+/* ======================================================================= */
+
+/* rho_dev[i] = |psi_i|^2 (float64[n]). */
+int chebtd_density(chebtd_ctx *ctx, const double *psi_dev, double *rho_dev);
+
+/* out_dev[0] = sum_i mask_i |psi_i|^2 with mask_dev uint8[n] (0 or 1),
+ * e.g. the transmission into x > 0.  Deterministic reduction. */
+int chebtd_region_sum(chebtd_ctx *ctx, const double *psi_dev, const uint8_t *mask_dev,
+                      double *out_dev);
+
+/* out2_dev[0] = <psi|psi>, out2_dev[1] = <psi|H|psi> (needs bounds). */
+int chebtd_norm_energy(chebtd_ctx *ctx, const double *psi_dev, double *out2_dev);
+
+/* Holstein observables of Fig. 3 for the Hamiltonian built by
+ * chebtd_h_holstein: n_dev[i] = <n_i>, nph_dev[i] = <b_i^+ b_i>,
+ * chi_dev[i] = <n_i (b_i + b_i^+)> (each float64[L]). */
+int chebtd_holstein_obs(chebtd_ctx *ctx, const double *psi_dev, double *n_dev,
+                        double *nph_dev, double *chi_dev);
+
+/* ======================================================================= */
+/* Batched propagation of many independent ribbons                          */
+/* ======================================================================= */
+
+/* One ribbon of a batch (a disorder realisation with its own packet). */
+typedef struct {
+    int64_t width, length; /* grid, as chebtd_h_honeycomb               */
+    int edge;              /* CHEBTD_ZIGZAG or CHEBTD_ARMCHAIR          */
+    double t_hop;          /* hopping t                                 */
+    const double *eps_dev; /* float64[width*length], borrowed           */
+    double emin, emax;     /* spectral bounds (e.g. Gershgorin)         */
+    double *psi_dev;       /* complex128[width*length], propagated in   */
+                           /* place, borrowed                           */
+} chebtd_sys_desc;
+
+/* Prepare a batch of nsys ribbons stepped by the same dt (each with its
+ * own a, b, M and weights; alpha and tol as chebtd_set_bounds/plan).
+ * Allocates the batch's work vectors (two per system) and schedule tables.
+ * Replaces any previous batch on the context. */
+int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs, double dt,
+                        double alpha, double tol);
+
+/* Schedules for chebtd_batch_propagate. */
+#define CHEBTD_SCHED_LEVELS 0     /* one launch per recursion level over   */
+                                  /* every system                           */
+#define CHEBTD_SCHED_PERSISTENT 1 /* one persistent launch per step: a     */
+                                  /* work queue of (level, system, tile)    */
+                                  /* with per-system completion counters    */
+
+/* Fix the schedule: mode, rows per tile (multiple of block, >= block),
+ * threads per block (64..1024, multiple of 64), and for the persistent
+ * mode the number of resident workgroups per CU (1..8). */
+int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int block,
+                              int wg_per_cu);
+
+/* Time candidate schedules on the real batch (a few steps each, the
+ * systems' psi are saved and restored) and keep the fastest.  If
+ * cache_path is non-NULL the choice is read from / appended to that text
+ * file, keyed by the batch's shape.  Synchronises.  best_out (int[4], may be
+ * NULL) receives mode, tile_rows, block, wg_per_cu. */
+int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out);
+
+/* Advance every system of the batch by K steps.  flags: CHEBTD_GRAPH
+ * replays a captured hipGraph per pair of steps; CHEBTD_NO_CHECK skips the
+ * final synchronisation that reports CHEBTD_E_TIMEOUT. */
+int chebtd_batch_propagate(chebtd_ctx *ctx, int64_t K, unsigned flags);
+
+/* Number of systems and, per system, its order M (int[nsys], may be NULL). */
+int chebtd_batch_info(const chebtd_ctx *ctx, int *nsys, int *M_host);
+
+/* ======================================================================= */
+/* Adjoint: dL/dV for the on-site potential (V of chebtd_h_chain1d, eps of  */
+/* chebtd_h_honeycomb).  Reverse mode of the recursion above with (a, b)    */
+/* held fixed:  u_M = conj(g_M) gbar,                                       */
+/*   u_k = conj(g_k) gbar + 2 H~ u_{k+1} - u_{k+2}   (1 <= k < M),          */
+/*   u_0 = conj(g_0) gbar + H~ u_1 - u_2,                                   */
+/*   dL/dV_i += (1/a) Re[conj(u_1,i) v_0,i + 2 sum_{k=1}^{M-1}              */
+/*                        conj(u_{k+1},i) v_k,i],                           */
+/* per step in reverse, gbar <- u_0.  gbar follows the convention           */
+/* dL = Re sum_i conj(gbar_i) dpsi_i (the gradient torch reports for a     */
+/* complex tensor under a real loss).                                       */
+/* ======================================================================= */
+
+/* Adjoint memory schedules. */
+#define CHEBTD_ADJ_STEP 0  /* recompute each step's M+1 vectors into a     */
+                           /* buffer, then sweep back                       */
+#define CHEBTD_ADJ_SQRTM 1 /* keep (v_{j-1}, v_j) every ceil(sqrt(M))      */
+                           /* orders and recompute segment by segment       */
+
+/* Allocate the adjoint's storage: psi checkpoints for up to max_steps steps
+ * and the recompute buffers of `mode`.  Needs a plan (chain or honeycomb). */
+int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode);
+
+/* After chebtd_propagate(..., K, ..., CHEBTD_KEEP_CHECKPOINTS): gbar_dev
+ * (complex128[n]) holds dL/dpsi_K on entry and the adjoint of psi_0 on
+ * return; dLdV_dev (float64[n]) is accumulated into (+=). */
+int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev);
+
+/* ======================================================================= */
+/* Measurement helpers                                                      */
+/* ======================================================================= */
+
+/* Launch the current Hamiltonian's recursion kernel (the hot loop) `launches`
+ * times on the context's stream between two hipEvents, on the context's own
+ * work vectors, and return the mean time per launch in milliseconds and the
+ * kernel's name.  Needs a plan.  Synchronises.  name_out may be NULL. */
+int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, double *ms_per_launch,
+                                 const char **name_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBTD_H */

@@ -1,0 +1,217 @@
+// Host side of the adjoint: storage schedules and the reverse sweep over
+// time steps.  The forward run keeps psi at the start of every step; the
+// backward run rebuilds that step's Chebyshev vectors from it (all M+1 of
+// them, or in segments of ceil(sqrt(M)) orders from (v_{j-1}, v_j) pairs)
+// and runs the reverse recursion level by level (adjoint.hip).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace chebtd {
+int fail(Ctx *c, int code, const std::string &msg);
+int hip_fail(Ctx *c, hipError_t e, const char *what);
+int ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what);
+void release(DevBuf &b);
+
+struct AdjState {
+    int64_t max_steps = 0;
+    int mode = CHEBTD_ADJ_STEP;
+    int seg = 1;          // orders per segment (sqrt mode)
+    int M = 0;            // order the buffers were sized for
+    int64_t plan_version = -1;
+    int64_t last_K = 0;   // steps stored by the last checkpointing run
+    int64_t ckpt_version = -1;
+    DevBuf ckpt;   // psi_s, s < max_steps
+    DevBuf vbuf;   // recompute buffer
+    DevBuf pairs;  // (v_{j-1}, v_j) per segment (sqrt mode)
+    DevBuf u;      // two adjoint vectors
+};
+
+void adj_destroy(Ctx *c)
+{
+    if (!c->adj) return;
+    release(c->adj->ckpt);
+    release(c->adj->vbuf);
+    release(c->adj->pairs);
+    release(c->adj->u);
+    delete c->adj;
+    c->adj = nullptr;
+}
+
+// Checkpoint slot of `step` for a run of K steps, or null if the storage is
+// missing or too small.  Calling it for step 0 marks a checkpointing run.
+double2 *adj_checkpoint(Ctx *c, int64_t step, int64_t K)
+{
+    AdjState *a = c->adj;
+    if (!a || K > a->max_steps || a->plan_version != c->plan_version) return nullptr;
+    if (step == 0) {
+        a->last_K = K;
+        a->ckpt_version = c->plan_version;
+    }
+    return static_cast<double2 *>(a->ckpt.p) + (size_t)step * (size_t)c->n;
+}
+
+}  // namespace chebtd
+
+using namespace chebtd;
+struct chebtd_ctx : public Ctx {};
+
+namespace {
+
+double2 conj_weight(const Ctx *c, int k)
+{
+    return make_double2(c->gamma[2 * (size_t)k], -c->gamma[2 * (size_t)k + 1]);
+}
+
+// Reverse sweep of one step for levels k = kend-1 .. kbeg, with the forward
+// vectors v_k available as vk(k).  U[0], U[1] hold u_{k+1}, u_{k+2}
+// alternately; u_k for k >= 1 goes to U[(M-k) & 1]; level 0 writes gbar.
+template <class VK>
+hipError_t sweep_levels(Ctx *c, hipStream_t s, int kbeg, int kend, VK vk, double2 *gbar, double *grad,
+                        double2 *U0, double2 *U1)
+{
+    const int M = c->M;
+    double2 *U[2] = {U0, U1};
+    hipError_t e = hipSuccess;
+    for (int k = kend - 1; k >= kbeg && e == hipSuccess; --k) {
+        double2 *u1 = U[(M - (k + 1)) & 1];  // u_{k+1}
+        double2 *u2 = U[(M - (k + 2)) & 1];  // u_{k+2} (absent when k+2 > M)
+        const int has_u2 = (k + 2 <= M);
+        if (k >= 1)
+            e = launch_adj_level(*c, s, u1, u2, gbar, u2, vk(k), conj_weight(c, k), 2.0, has_u2, grad);
+        else
+            e = launch_adj_level(*c, s, u1, u2, gbar, gbar, vk(0), conj_weight(c, 0), 1.0, has_u2, grad);
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (!c->has_plan || (c->kind != HKind::Chain && c->kind != HKind::Honeycomb))
+        return fail(c, CHEBTD_E_STATE, "chebtd_reserve_adjoint: needs a plan for a chain or honeycomb H");
+    if (max_steps < 1 || (mode != CHEBTD_ADJ_STEP && mode != CHEBTD_ADJ_SQRTM))
+        return fail(c, CHEBTD_E_ARG, "chebtd_reserve_adjoint: need max_steps >= 1 and a known mode");
+    if (!c->adj) c->adj = new (std::nothrow) AdjState();
+    if (!c->adj) return fail(c, CHEBTD_E_OOM, "adjoint state");
+    AdjState *a = c->adj;
+    const size_t vb = (size_t)c->n * sizeof(double2);
+    const int M = c->M;
+    a->mode = mode;
+    a->max_steps = max_steps;
+    a->M = M;
+    a->seg = std::max(1, (int)std::ceil(std::sqrt((double)std::max(M, 1))));
+    int rc;
+    if ((rc = ensure(c, a->ckpt, vb * (size_t)max_steps, "adjoint checkpoints"))) return rc;
+    if ((rc = ensure(c, a->u, 2 * vb, "adjoint vectors"))) return rc;
+    if (mode == CHEBTD_ADJ_STEP) {
+        release(a->pairs);
+        if ((rc = ensure(c, a->vbuf, vb * (size_t)(M + 1), "recompute buffer"))) return rc;
+    } else {
+        const int nseg = (M + a->seg - 1) / a->seg;
+        if ((rc = ensure(c, a->pairs, vb * 2 * (size_t)std::max(nseg, 1), "segment pairs"))) return rc;
+        if ((rc = ensure(c, a->vbuf, vb * (size_t)(a->seg + 1), "segment buffer"))) return rc;
+    }
+    a->plan_version = c->plan_version;
+    a->last_K = 0;
+    a->ckpt_version = -1;
+    return CHEBTD_OK;
+}
+
+int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    AdjState *a = c->adj;
+    if (!gbar_dev || !dLdV_dev) return fail(c, CHEBTD_E_ARG, "chebtd_adjoint: null pointer");
+    if (!a || !c->has_plan || a->plan_version != c->plan_version || a->ckpt_version != c->plan_version ||
+        a->last_K < 1)
+        return fail(c, CHEBTD_E_STATE,
+                    "chebtd_adjoint: run chebtd_propagate with CHEBTD_KEEP_CHECKPOINTS on the current plan first");
+    hipStream_t s = c->stream;
+    const int M = c->M;
+    const int64_t n = c->n;
+    double2 *gbar = reinterpret_cast<double2 *>(gbar_dev);
+    double2 *ck = static_cast<double2 *>(a->ckpt.p);
+    double2 *vb = static_cast<double2 *>(a->vbuf.p);
+    double2 *U0 = static_cast<double2 *>(a->u.p), *U1 = U0 + n;
+    hipError_t e = hipSuccess;
+    for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {
+        double2 *psi_s = ck + (size_t)st * n;
+        if (M == 0) {
+            e = launch_scale_copy(s, gbar, gbar, conj_weight(c, 0), n);
+            continue;
+        }
+        // u_M = conj(gamma_M) gbar
+        e = launch_adj_init(s, gbar, conj_weight(c, M), U0, n);
+        if (e != hipSuccess) break;
+        if (a->mode == CHEBTD_ADJ_STEP) {
+            // v_0 = psi_s (the checkpoint itself), v_1 .. v_M into the buffer
+            auto vk = [&](int k) -> double2 * { return k == 0 ? psi_s : vb + (size_t)k * n; };
+            for (int k = 0; k + 1 <= M - 1 && e == hipSuccess; ++k)
+                e = launch_recompute(*c, s, vk(k), k ? vk(k - 1) : nullptr, vk(k + 1), k == 0);
+            if (e == hipSuccess) e = sweep_levels(c, s, 0, M, vk, gbar, dLdV_dev, U0, U1);
+        } else {
+            // forward pass keeping (v_{qS-1}, v_{qS}) for segments q >= 1
+            const int S = a->seg, nseg = (M + S - 1) / S;
+            double2 *pairs = static_cast<double2 *>(a->pairs.p);
+            double2 *w0 = vb, *w1 = vb + n, *w2 = vb + 2 * (size_t)n;  // rotating scratch
+            // v_0 = psi_s; compute up to v_{(nseg-1) S}
+            const int kmax = (nseg - 1) * S;
+            const double2 *km1 = nullptr, *kc = psi_s;
+            double2 *rot[3] = {w0, w1, w2};
+            for (int k = 0; k < kmax && e == hipSuccess; ++k) {
+                double2 *dst = rot[k % 3];
+                e = launch_recompute(*c, s, kc, km1, dst, k == 0);
+                km1 = kc;
+                kc = dst;
+                const int kk = k + 1;  // order just formed
+                if (kk % S == 0 && e == hipSuccess) {
+                    const int q = kk / S;
+                    e = hipMemcpyAsync(pairs + (size_t)(2 * q) * n, km1, n * sizeof(double2),
+                                       hipMemcpyDeviceToDevice, s);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(pairs + (size_t)(2 * q + 1) * n, kc, n * sizeof(double2),
+                                           hipMemcpyDeviceToDevice, s);
+                }
+            }
+            // segments in reverse: rebuild v_{qS} .. v_{min(qS+S, M)-1}
+            for (int q = nseg - 1; q >= 0 && e == hipSuccess; --q) {
+                const int k0 = q * S, k1 = std::min(k0 + S, M);
+                // buffer slot j holds v_{k0 + j}; slot S holds v_{k0-1}
+                auto vk = [&](int k) -> double2 * {
+                    if (k == 0) return psi_s;
+                    return vb + (size_t)(k - k0) * n;
+                };
+                double2 *prev = nullptr;
+                if (q > 0) {
+                    e = hipMemcpyAsync(vb + (size_t)S * n, pairs + (size_t)(2 * q) * n, n * sizeof(double2),
+                                       hipMemcpyDeviceToDevice, s);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(vb, pairs + (size_t)(2 * q + 1) * n, n * sizeof(double2),
+                                           hipMemcpyDeviceToDevice, s);
+                    prev = vb + (size_t)S * n;
+                }
+                for (int k = k0; k + 1 <= k1 - 1 && e == hipSuccess; ++k) {
+                    const double2 *cur = vk(k);
+                    const double2 *km = (k == k0) ? prev : vk(k - 1);
+                    e = launch_recompute(*c, s, cur, km, vb + (size_t)(k + 1 - k0) * n, k == 0);
+                }
+                if (e == hipSuccess) e = sweep_levels(c, s, k0, k1, vk, gbar, dLdV_dev, U0, U1);
+            }
+        }
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_adjoint");
+    return CHEBTD_OK;
+}
+
+}  // extern "C"

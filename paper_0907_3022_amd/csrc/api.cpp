@@ -1,0 +1,414 @@
+// C ABI of chebtd: context, Hamiltonian builders, bounds, plan, propagation
+// and observables.  The time step is the Chebyshev expansion of Sect. 2.2 of
+// arXiv:0907.3022; every arithmetic step of it runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+using namespace chebtd;
+
+struct chebtd_ctx : public Ctx {};
+
+namespace chebtd {
+thread_local std::string g_create_err;
+
+int fail(Ctx *c, int code, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_create_err = msg;
+    return code;
+}
+
+int hip_fail(Ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, CHEBTD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const char *hip_err_name(hipError_t e) { return hipGetErrorName(e); }
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+int ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what)
+{
+    if (b.bytes >= bytes && b.p) return CHEBTD_OK;
+    release(b);
+    if (bytes == 0) return CHEBTD_OK;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, CHEBTD_E_OOM, std::string("device allocation failed: ") + what + " (" +
+                                         std::to_string(bytes) + " bytes)");
+    }
+    b.bytes = bytes;
+    return CHEBTD_OK;
+}
+
+void drop_graphs(Ctx *c)
+{
+    for (auto &g : c->graph_exec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    for (auto &k : c->graph_key) k = nullptr;
+}
+
+// partial-sum buffer big enough for every reduction of the current H
+int ensure_partials(Ctx *c)
+{
+    int64_t nb = (c->n + kBlock - 1) / kBlock;
+    nb = std::max<int64_t>(nb, grid_blocks(*c));
+    size_t bytes = (size_t)std::max<int64_t>(nb, 1) * 2 * sizeof(double);
+    if (c->holstein) {
+        size_t hb = (size_t)holstein_obs_blocks(c->hol_nconf) * 3 * c->hol_L * sizeof(double);
+        bytes = std::max(bytes, hb);
+    }
+    return ensure(c, c->partials, bytes, "partials");
+}
+
+void invalidate_h(Ctx *c)
+{
+    c->has_bounds = false;
+    c->has_plan = false;
+    c->holstein = false;
+    drop_graphs(c);
+}
+
+void adj_destroy(Ctx *c);    // adjoint.cpp
+void batch_destroy(Ctx *c);  // batch.cpp
+
+}  // namespace chebtd
+
+static Ctx *as_ctx(chebtd_ctx *c) { return static_cast<Ctx *>(c); }
+
+extern "C" {
+
+int chebtd_version(void) { return 10000; }
+
+int chebtd_create(chebtd_ctx **out, void *hip_stream)
+{
+    if (!out) return fail(nullptr, CHEBTD_E_ARG, "chebtd_create: out is null");
+    *out = nullptr;
+    chebtd_ctx *c = new (std::nothrow) chebtd_ctx();
+    if (!c) return fail(nullptr, CHEBTD_E_OOM, "chebtd_create: out of host memory");
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->results.p, 16 * sizeof(double));
+    if (e == hipSuccess) {
+        c->results.bytes = 16 * sizeof(double);
+        e = hipMalloc(&c->counter.p, 4 * sizeof(int64_t));
+    }
+    if (e == hipSuccess) {
+        c->counter.bytes = 4 * sizeof(int64_t);
+        e = hipHostMalloc((void **)&c->pinned, 16 * sizeof(double), hipHostMallocDefault);
+    }
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_a);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_b);
+    if (e != hipSuccess) {
+        std::string msg = std::string("chebtd_create: ") + hipGetErrorString(e);
+        (void)hipGetLastError();
+        chebtd_destroy(c);
+        return fail(nullptr, CHEBTD_E_HIP, msg);
+    }
+    *out = c;
+    return CHEBTD_OK;
+}
+
+int chebtd_destroy(chebtd_ctx *ctx)
+{
+    if (!ctx) return CHEBTD_OK;
+    Ctx *c = as_ctx(ctx);
+    (void)hipStreamSynchronize(c->stream);
+    adj_destroy(c);
+    batch_destroy(c);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (DevBuf *b : {&c->vA, &c->vB, &c->partials, &c->results, &c->counter, &c->gamma_dev,
+                      &c->hol_rowptr, &c->hol_col, &c->hol_val, &c->hol_occ, &c->hol_up})
+        release(*b);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->ev_a) (void)hipEventDestroy(c->ev_a);
+    if (c->ev_b) (void)hipEventDestroy(c->ev_b);
+    delete ctx;
+    return CHEBTD_OK;
+}
+
+int chebtd_set_stream(chebtd_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "chebtd_set_stream: null context");
+    as_ctx(ctx)->stream = static_cast<hipStream_t>(hip_stream);
+    return CHEBTD_OK;
+}
+
+const char *chebtd_last_error(const chebtd_ctx *ctx)
+{
+    if (!ctx) return g_create_err.c_str();
+    return static_cast<const Ctx *>(ctx)->err.c_str();
+}
+
+int64_t chebtd_dim(const chebtd_ctx *ctx) { return ctx ? static_cast<const Ctx *>(ctx)->n : 0; }
+
+// ---------------------------------------------------------------------------
+// builders
+// ---------------------------------------------------------------------------
+int chebtd_h_chain1d(chebtd_ctx *ctx, int64_t n, double dx, const double *V_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (n < 1 || !(dx > 0.0) || !std::isfinite(dx) || !V_dev)
+        return fail(c, CHEBTD_E_ARG, "chebtd_h_chain1d: need n >= 1, finite dx > 0, V non-null");
+    if (n > ((int64_t)1 << 40)) return fail(c, CHEBTD_E_ARG, "chebtd_h_chain1d: n too large");
+    invalidate_h(c);
+    c->kind = HKind::Chain;
+    c->n = n;
+    c->dx = dx;
+    c->V = V_dev;
+    return ensure_partials(c);
+}
+
+int chebtd_h_honeycomb(chebtd_ctx *ctx, int64_t width, int64_t length, int edge, double t_hop,
+                       const double *eps_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (width < 1 || length < 1 || !eps_dev || !std::isfinite(t_hop) ||
+        (edge != CHEBTD_ZIGZAG && edge != CHEBTD_ARMCHAIR))
+        return fail(c, CHEBTD_E_ARG,
+                    "chebtd_h_honeycomb: need width, length >= 1, a known edge, eps non-null");
+    // row and column indices and the block grid are 32-bit in the kernels
+    if (width * length >= ((int64_t)1 << 31) || width > 65535 * 4096)
+        return fail(c, CHEBTD_E_ARG, "chebtd_h_honeycomb: grid exceeds 2^31 sites");
+    invalidate_h(c);
+    c->kind = HKind::Honeycomb;
+    c->W = width;
+    c->L = length;
+    c->n = width * length;
+    c->edge = edge;
+    c->t_hop = t_hop;
+    c->eps = eps_dev;
+    return ensure_partials(c);
+}
+
+int chebtd_h_csr(chebtd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr_dev,
+                 const int32_t *col_dev, const double *val_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (n < 1 || nnz < 0 || !rowptr_dev || (nnz > 0 && (!col_dev || !val_dev)))
+        return fail(c, CHEBTD_E_ARG, "chebtd_h_csr: need n >= 1, nnz >= 0 and non-null arrays");
+    if (n >= (int64_t)INT32_MAX)
+        return fail(c, CHEBTD_E_ARG, "chebtd_h_csr: n must fit int32 column indices");
+    // reject malformed structure here: the kernels index v with these columns
+    int64_t *flag = static_cast<int64_t *>(c->counter.p) + 1;
+    hipError_t e = launch_csr_check(c->stream, rowptr_dev, col_dev, n, nnz, flag);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->pinned, flag, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_h_csr structure check");
+    int64_t bad = 0;
+    std::memcpy(&bad, c->pinned, sizeof(int64_t));
+    if (bad)
+        return fail(c, CHEBTD_E_ARG,
+                    "chebtd_h_csr: rowptr must run from 0 to nnz without decreasing and every column "
+                    "must lie in [0, n)");
+    invalidate_h(c);
+    c->kind = HKind::Csr;
+    c->n = n;
+    c->nnz = nnz;
+    c->rowptr = rowptr_dev;
+    c->col = col_dev;
+    c->val = val_dev;
+    return ensure_partials(c);
+}
+
+int chebtd_holstein_csr_host(int L, int nph, double t, double w0, const double *g_host,
+                             const double *Delta_host, int periodic, int64_t *n_out,
+                             int64_t *nnz_out, int64_t *rowptr, int32_t *col, double *val)
+{
+    HolsteinCsr h;
+    std::string err;
+    int rc = holstein_build(L, nph, t, w0, g_host, Delta_host, periodic, false, h, err);
+    if (rc) return fail(nullptr, rc, err);
+    if (n_out) *n_out = h.n;
+    if (nnz_out) *nnz_out = h.nnz;
+    if (rowptr) std::memcpy(rowptr, h.rowptr.data(), h.rowptr.size() * sizeof(int64_t));
+    if (col) std::memcpy(col, h.col.data(), h.col.size() * sizeof(int32_t));
+    if (val) std::memcpy(val, h.val.data(), h.val.size() * sizeof(double));
+    return CHEBTD_OK;
+}
+
+int chebtd_holstein_occupations(int L, int nph, int64_t *count_out, uint8_t *occ)
+{
+    if (!count_out) return fail(nullptr, CHEBTD_E_ARG, "count_out is null");
+    if (holstein_count(L, nph, count_out)) return fail(nullptr, CHEBTD_E_ARG, "bad L or nph");
+    if (!occ) return CHEBTD_OK;
+    std::vector<double> z((size_t)L, 0.0);
+    HolsteinCsr h;
+    std::string err;
+    // open chain, no couplings: only the occupation table is used
+    int rc = holstein_build(L, nph, 0.0, 0.0, z.data(), z.data(), 0, true, h, err);
+    if (rc) return fail(nullptr, rc, err);
+    std::memcpy(occ, h.occ.data(), h.occ.size());
+    return CHEBTD_OK;
+}
+
+int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0, const double *g_host,
+                      const double *Delta_host, int periodic)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    HolsteinCsr h;
+    std::string err;
+    int rc = holstein_build(L, nph, t, w0, g_host, Delta_host, periodic, true, h, err);
+    if (rc) return fail(c, rc, err);
+    invalidate_h(c);
+    c->kind = HKind::None;
+    if ((rc = ensure(c, c->hol_rowptr, h.rowptr.size() * sizeof(int64_t), "holstein rowptr")) ||
+        (rc = ensure(c, c->hol_col, h.col.size() * sizeof(int32_t), "holstein col")) ||
+        (rc = ensure(c, c->hol_val, h.val.size() * sizeof(double), "holstein val")) ||
+        (rc = ensure(c, c->hol_occ, h.occ.size(), "holstein occupations")) ||
+        (rc = ensure(c, c->hol_up, h.up.size() * sizeof(int32_t), "holstein raise table")))
+        return rc;
+    hipError_t e = hipMemcpy(c->hol_rowptr.p, h.rowptr.data(), h.rowptr.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->hol_col.p, h.col.data(), h.col.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->hol_val.p, h.val.data(), h.val.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->hol_occ.p, h.occ.data(), h.occ.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->hol_up.p, h.up.data(), h.up.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_h_holstein upload");
+    c->kind = HKind::Csr;
+    c->n = h.n;
+    c->nnz = h.nnz;
+    c->rowptr = static_cast<const int64_t *>(c->hol_rowptr.p);
+    c->col = static_cast<const int32_t *>(c->hol_col.p);
+    c->val = static_cast<const double *>(c->hol_val.p);
+    c->holstein = true;
+    c->hol_L = L;
+    c->hol_nph = nph;
+    c->hol_nconf = h.nconf;
+    return ensure_partials(c);
+}
+
+// ---------------------------------------------------------------------------
+// bounds and plan
+// ---------------------------------------------------------------------------
+int chebtd_gershgorin(chebtd_ctx *ctx, double *emin, double *emax)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (!emin || !emax) return fail(c, CHEBTD_E_ARG, "chebtd_gershgorin: null output");
+    if (c->kind == HKind::None) return fail(c, CHEBTD_E_STATE, "chebtd_gershgorin: no Hamiltonian");
+    double *res = static_cast<double *>(c->results.p);
+    hipError_t e = launch_gershgorin(*c, c->stream, static_cast<double *>(c->partials.p), res);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->pinned, res, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_gershgorin");
+    *emin = c->pinned[0];
+    *emax = c->pinned[1];
+    return CHEBTD_OK;
+}
+
+int chebtd_set_bounds(chebtd_ctx *ctx, double emin, double emax, double alpha)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (!(emax > emin) || !std::isfinite(emin) || !std::isfinite(emax) || !(alpha >= 0.0) ||
+        !std::isfinite(alpha))
+        return fail(c, CHEBTD_E_ARG, "chebtd_set_bounds: need finite emax > emin and alpha >= 0");
+    c->emin = emin;
+    c->emax = emax;
+    c->alpha = alpha;
+    shift_scale(emin, emax, alpha, &c->a, &c->b);
+    c->has_bounds = true;
+    c->has_plan = false;
+    drop_graphs(c);
+    return CHEBTD_OK;
+}
+
+static int plan_common(Ctx *c, double dt, int M)
+{
+    step_weights(c->a, c->b, dt, M, c->gamma);
+    int rc;
+    if ((rc = ensure(c, c->gamma_dev, c->gamma.size() * sizeof(double), "weights"))) return rc;
+    hipError_t e = hipMemcpy(c->gamma_dev.p, c->gamma.data(), c->gamma.size() * sizeof(double),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_plan upload");
+    const size_t vbytes = (size_t)c->n * 2 * sizeof(double);
+    if ((rc = ensure(c, c->vA, vbytes, "work vector A")) || (rc = ensure(c, c->vB, vbytes, "work vector B")))
+        return rc;
+    if ((rc = ensure_partials(c))) return rc;
+    c->dt = dt;
+    c->M = M;
+    c->has_plan = true;
+    c->plan_version++;
+    drop_graphs(c);
+    return CHEBTD_OK;
+}
+
+int chebtd_plan(chebtd_ctx *ctx, double dt, double tol, int *M_out)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (c->kind == HKind::None) return fail(c, CHEBTD_E_STATE, "chebtd_plan: no Hamiltonian");
+    if (!c->has_bounds) return fail(c, CHEBTD_E_STATE, "chebtd_plan: set the spectral bounds first");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(c, CHEBTD_E_ARG, "chebtd_plan: need finite dt >= 0");
+    if (!(tol > 0.0)) tol = 1e-15;
+    const int M = truncation_order(c->a * dt, tol);
+    if (M < 0) return fail(c, CHEBTD_E_ARG, "chebtd_plan: bad a*dt or tol");
+    int rc = plan_common(c, dt, M);
+    if (rc) return rc;
+    if (M_out) *M_out = M;
+    return CHEBTD_OK;
+}
+
+int chebtd_plan_order(chebtd_ctx *ctx, double dt, int M)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = as_ctx(ctx);
+    if (c->kind == HKind::None) return fail(c, CHEBTD_E_STATE, "chebtd_plan_order: no Hamiltonian");
+    if (!c->has_bounds) return fail(c, CHEBTD_E_STATE, "chebtd_plan_order: set bounds first");
+    if (!(dt >= 0.0) || !std::isfinite(dt) || M < 0 || M > 10000000)
+        return fail(c, CHEBTD_E_ARG, "chebtd_plan_order: need dt >= 0 and 0 <= M <= 1e7");
+    return plan_common(c, dt, M);
+}
+
+int chebtd_get_plan(const chebtd_ctx *ctx, double *gamma_host, double *a, double *b, double *dt,
+                    int *M)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    const Ctx *c = static_cast<const Ctx *>(ctx);
+    if (!c->has_plan) return fail(const_cast<Ctx *>(c), CHEBTD_E_STATE, "chebtd_get_plan: no plan");
+    if (gamma_host) std::memcpy(gamma_host, c->gamma.data(), c->gamma.size() * sizeof(double));
+    if (a) *a = c->a;
+    if (b) *b = c->b;
+    if (dt) *dt = c->dt;
+    if (M) *M = c->M;
+    return CHEBTD_OK;
+}
+
+int chebtd_set_check_tol(chebtd_ctx *ctx, double rel_tol)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    if (!(rel_tol > 0.0)) return fail(as_ctx(ctx), CHEBTD_E_ARG, "check tolerance must be > 0");
+    as_ctx(ctx)->check_tol = rel_tol;
+    return CHEBTD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+// Device-side building blocks shared by the HIP kernels: complex helpers,
+// deterministic wavefront/block sums, and the row mapping plus 2 H~
+// application of each Hamiltonian form (chain, honeycomb brick wall, CSR).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace chebtd {
+
+// ---------------------------------------------------------------------------
+// complex helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+// a += g * v
+__device__ __forceinline__ double2 cfma(double2 g, double2 v, double2 a)
+{
+    a.x = fma(g.x, v.x, fma(-g.y, v.y, a.x));
+    a.y = fma(g.x, v.y, fma(g.y, v.x, a.y));
+    return a;
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Sum (a, b) over the block; thread 0 receives the totals.  lds: 2 * nwaves.
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        lds[2 * w] = a;
+        lds[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) {
+            sa += lds[2 * i];
+            sb += lds[2 * i + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row mapping and 2 H~ application per operator
+// ---------------------------------------------------------------------------
+struct ChainRow {
+    __device__ static __forceinline__ int64_t row(const OpChain &op)
+    {
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        return i < op.n ? i : -1;
+    }
+    __device__ static __forceinline__ double2 apply2(const OpChain &op, int64_t i, const double2 *v,
+                                                     double2 vi)
+    {
+        const double d = op.s2 * (op.V[i] + op.dsh);
+        double2 s = make_double2(0.0, 0.0);
+        if (i > 0) s = v[i - 1];
+        if (i + 1 < op.n) s = cadd(s, v[i + 1]);
+        return make_double2(fma(d, vi.x, op.off2 * s.x), fma(d, vi.y, op.off2 * s.y));
+    }
+};
+
+// Logical block index; with xcd_remap the blocks that one XCD receives under
+// round-robin dispatch cover one contiguous range of the grid, so vertical
+// neighbours of a tile are mostly cached in the same L2.
+__device__ __forceinline__ int32_t logical_block(int32_t remap)
+{
+    const int32_t b = blockIdx.x, nb = gridDim.x;
+    if (!remap) return b;
+    const int32_t xcd = b & 7, slot = b >> 3;
+    const int32_t per = nb >> 3, rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + slot;
+}
+
+template <int EDGE>
+struct HoneyRow {
+    __device__ static __forceinline__ int64_t row_xy(const OpHoney &op, int32_t &x, int32_t &y)
+    {
+        const int32_t lb = logical_block(op.xcd_remap);
+        y = lb / op.xblocks;
+        x = (lb - y * op.xblocks) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+        if (x >= op.L) return -1;
+        return (int64_t)y * op.L + x;
+    }
+    __device__ static __forceinline__ double2 apply2(const OpHoney &op, int64_t i, int32_t x,
+                                                     int32_t y, const double2 *v, double2 vi)
+    {
+        const double d = op.s2 * (op.eps[i] - op.b);
+        double2 s = make_double2(0.0, 0.0);
+        const bool even = ((x + y) & 1) == 0;
+        if (EDGE == CHEBTD_ZIGZAG) {
+            if (x > 0) s = v[i - 1];
+            if (x + 1 < op.L) s = cadd(s, v[i + 1]);
+            if (even) {
+                if (y + 1 < op.W) s = cadd(s, v[i + op.L]);
+            } else {
+                if (y > 0) s = cadd(s, v[i - op.L]);
+            }
+        } else {
+            if (y > 0) s = v[i - op.L];
+            if (y + 1 < op.W) s = cadd(s, v[i + op.L]);
+            if (even) {
+                if (x + 1 < op.L) s = cadd(s, v[i + 1]);
+            } else {
+                if (x > 0) s = cadd(s, v[i - 1]);
+            }
+        }
+        return make_double2(fma(d, vi.x, op.off2 * s.x), fma(d, vi.y, op.off2 * s.y));
+    }
+};
+
+struct CsrRow {
+    __device__ static __forceinline__ int64_t row(const OpCsr &op)
+    {
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        return i < op.n ? i : -1;
+    }
+    __device__ static __forceinline__ double2 apply2(const OpCsr &op, int64_t i, const double2 *v,
+                                                     double2 vi)
+    {
+        const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
+        double sx = 0.0, sy = 0.0;
+        for (int64_t p = p0; p < p1; ++p) {
+            const double2 h = op.val[p];
+            const double2 x = v[op.col[p]];
+            sx = fma(h.x, x.x, fma(-h.y, x.y, sx));
+            sy = fma(h.x, x.y, fma(h.y, x.x, sy));
+        }
+        // (2/a) (H v - b v)
+        return make_double2(op.s2 * fma(-op.b, vi.x, sx), op.s2 * fma(-op.b, vi.y, sy));
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Host-side construction of the operator parameters from the context
+// ---------------------------------------------------------------------------
+inline OpChain make_chain(const Ctx &c)
+{
+    OpChain op;
+    op.V = c.V;
+    op.dsh = 1.0 / (c.dx * c.dx) - c.b;
+    op.s2 = 2.0 / c.a;
+    op.off2 = 2.0 * (-0.5 / (c.dx * c.dx)) / c.a;
+    op.n = c.n;
+    return op;
+}
+
+inline OpHoney make_honey(const Ctx &c)
+{
+    OpHoney op;
+    op.eps = c.eps;
+    op.b = c.b;
+    op.s2 = 2.0 / c.a;
+    op.off2 = -2.0 * c.t_hop / c.a;
+    op.W = (int32_t)c.W;
+    op.L = (int32_t)c.L;
+    op.xblocks = (int32_t)((c.L + kBlock - 1) / kBlock);
+    op.xcd_remap = 1;
+    return op;
+}
+
+inline OpCsr make_csr(const Ctx &c)
+{
+    OpCsr op;
+    op.rowptr = c.rowptr;
+    op.col = c.col;
+    op.val = reinterpret_cast<const double2 *>(c.val);
+    op.b = c.b;
+    op.s2 = 2.0 / c.a;
+    op.n = c.n;
+    return op;
+}
+
+}  // namespace chebtd

@@ -1,0 +1,184 @@
+// Internal declarations of the chebtd library (host runtime + HIP kernels).
+// Not part of the public ABI; see include/chebtd.h for the contract.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "chebtd.h"
+
+namespace chebtd {
+
+// ---------------------------------------------------------------------------
+// Operators: each applies 2 H~ = (2/a)(H - b) to row i of a complex vector.
+// The step head needs H~ itself and takes exactly half (a power-of-two
+// scaling, so no rounding is added).
+// ---------------------------------------------------------------------------
+struct OpChain {
+    const double *V;  // on-site potential, float64[n]
+    double dsh;       // 1/dx^2 - b  (diagonal without V)
+    double s2;        // 2/a
+    double off2;      // 2 * (-1/(2 dx^2)) / a
+    int64_t n;
+};
+
+struct OpHoney {
+    const double *eps;  // on-site energies, float64[W*L]
+    double b;           // shift
+    double s2;          // 2/a
+    double off2;        // -2 t / a
+    int32_t W, L;       // grid (rows, columns)
+    int32_t xblocks;    // ceil(L / block)
+    int32_t xcd_remap;  // 1: map blocks XCD-contiguously
+};
+
+struct OpCsr {
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double2 *val;
+    double b;
+    double s2;  // 2/a
+    int64_t n;
+};
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+enum class HKind { None = 0, Chain, Honeycomb, Csr };
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct BatchState;  // batched ribbons (batch.cpp)
+struct AdjState;    // adjoint storage (adjoint.cpp)
+
+struct Ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cus = 256;
+    std::string err;
+
+    // Hamiltonian
+    HKind kind = HKind::None;
+    int64_t n = 0;
+    // chain
+    double dx = 0.0;
+    const double *V = nullptr;
+    // honeycomb
+    int64_t W = 0, L = 0;
+    int edge = 0;
+    double t_hop = 1.0;
+    const double *eps = nullptr;
+    // csr
+    int64_t nnz = 0;
+    const int64_t *rowptr = nullptr;
+    const int32_t *col = nullptr;
+    const double *val = nullptr;
+    // Holstein (owned device copies)
+    bool holstein = false;
+    int hol_L = 0, hol_nph = 0;
+    int64_t hol_nconf = 0;
+    DevBuf hol_rowptr, hol_col, hol_val, hol_occ, hol_up;
+
+    // bounds and plan
+    bool has_bounds = false;
+    double emin = 0.0, emax = 0.0, alpha = 0.01, a = 1.0, b = 0.0;
+    bool has_plan = false;
+    double dt = 0.0;
+    int M = 0;
+    std::vector<double> gamma;  // interleaved complex, M+1 entries
+    DevBuf gamma_dev;           // device copy of gamma
+
+    // work vectors: two complex vectors of length n
+    DevBuf vA, vB;
+    // reduction scratch: partial sums, step counter, results
+    DevBuf partials;   // double[2 * max_blocks]
+    DevBuf results;    // double[16]
+    DevBuf counter;    // int64[4]
+    double *pinned = nullptr;  // host pinned double[16]
+    double check_tol = 1e-6;
+    int64_t plan_version = 0;  // bumped by every plan
+
+    // graph cache for CHEBTD_GRAPH
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    const void *graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+
+    BatchState *batch = nullptr;
+    AdjState *adj = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Host helpers (plan.cpp, holstein.cpp)
+// ---------------------------------------------------------------------------
+int bessel_miller(double z, int kmax, std::vector<double> &J);
+int truncation_order(double z, double tol);
+void step_weights(double a, double b, double dt, int M, std::vector<double> &gamma);
+void shift_scale(double emin, double emax, double alpha, double *a, double *b);
+
+struct HolsteinCsr {
+    int64_t n = 0, nnz = 0, nconf = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;  // complex interleaved
+    std::vector<uint8_t> occ;
+    std::vector<int32_t> up;  // rank of n + e_i, or -1
+};
+int holstein_count(int L, int nph, int64_t *count);
+int holstein_build(int L, int nph, double t, double w0, const double *g, const double *Delta,
+                   int periodic, bool want_tables, HolsteinCsr &out, std::string &err);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All enqueue on `s` and return hipError_t.
+// ---------------------------------------------------------------------------
+constexpr int kBlock = 256;
+int64_t grid_blocks(const Ctx &c);
+
+hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *v1, double2 *acc,
+                       double2 g0, double2 g1, double2 *ckpt, double *partials);
+hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *vprev,
+                       double2 *acc, double2 g);
+hipError_t launch_finalize_ne(hipStream_t s, const double *partials, int nparts, double a, double b,
+                              double *norm_out, double *energy_out, int64_t *step_counter,
+                              double *dst2);
+hipError_t launch_reset_counter(hipStream_t s, int64_t *counter);
+hipError_t launch_norm(const Ctx &c, hipStream_t s, const double2 *psi, double *partials);
+hipError_t launch_sum_partials(hipStream_t s, const double *partials, int nparts, int stride,
+                               double *out);
+hipError_t launch_copy(hipStream_t s, const double2 *src, double2 *dst, int64_t n);
+hipError_t launch_scale_copy(hipStream_t s, const double2 *src, double2 *dst, double2 g, int64_t n);
+hipError_t launch_density(hipStream_t s, const double2 *psi, double *rho, int64_t n);
+hipError_t launch_region(hipStream_t s, const double2 *psi, const uint8_t *mask, int64_t n,
+                         double *partials, double *out);
+hipError_t launch_gershgorin(const Ctx &c, hipStream_t s, double *partials, double *out2);
+hipError_t launch_holstein_obs(hipStream_t s, const double2 *psi, const uint8_t *occ,
+                               const int32_t *up, int64_t nconf, int L, double *partials,
+                               double *n_out, double *nph_out, double *chi_out);
+int holstein_obs_blocks(int64_t nconf);
+// one-workgroup persistent chain kernel: whole K-step run in one launch
+bool chain_small_fits(int64_t n);
+hipError_t launch_chain_small(const Ctx &c, hipStream_t s, double2 *psi, double2 *out,
+                              const double2 *gamma_dev, int64_t K, double *norm_out,
+                              double *energy_out, double2 *ckpt);
+hipError_t launch_fill_zero(hipStream_t s, double *p, int64_t count);
+hipError_t launch_csr_check(hipStream_t s, const int64_t *rowptr, const int32_t *col, int64_t n,
+                            int64_t nnz, int64_t *flag);
+
+// adjoint kernels (adjoint.hip)
+hipError_t launch_recompute(const Ctx &c, hipStream_t s, const double2 *vk, const double2 *vkm1,
+                            double2 *vkp1, int first);
+hipError_t launch_adj_init(hipStream_t s, const double2 *gbar, double2 g, double2 *u, int64_t n);
+hipError_t launch_adj_level(const Ctx &c, hipStream_t s, const double2 *u1, double2 *u2_in,
+                            const double2 *gbar_in, double2 *out, const double2 *vk, double2 gk,
+                            double gscale, int has_u2, double *grad);
+
+// small helpers
+const char *hip_err_name(hipError_t e);
+
+}  // namespace chebtd

@@ -1,0 +1,747 @@
+// HIP kernels of the single-system Chebyshev path (gfx950, wave64).
+//
+// The hot loop is the fused recursion step of Sect. 2.2 (arXiv:0907.3022):
+//   v_{k+1} = 2 H~ v_k - v_{k-1}   (written over v_{k-1}),
+//   acc    += gamma_{k+1} v_{k+1},
+// one row per thread, complex128 throughout.  Per row it moves 88 bytes for
+// the stencils (v_k, v_{k-1}, v_{k+1}, acc read and write, on-site term) and
+// the neighbour values of v_k come from the caches.  Reductions (norm,
+// energy, region sums, bounds) are deterministic: a fixed butterfly inside
+// each wavefront, fixed-order sums across wavefronts and blocks, no
+// floating-point atomics.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+#include "device_ops.h"
+
+namespace chebtd {
+
+// ---------------------------------------------------------------------------
+// Step head: v1 = H~ v0, acc = g0 v0 + g1 v1, partial <v0|v0>, <v0|H~ v0>
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void head_body(int64_t i, bool valid, double2 vi, double2 h2, double2 *v1,
+                                          double2 *acc, double2 g0, double2 g1, double2 *ckpt,
+                                          double *partials)
+{
+    __shared__ double red[2 * (1024 / 64)];
+    double nrm = 0.0, e = 0.0;
+    if (valid) {
+        const double2 h = cscale(0.5, h2);
+        if (v1) {  // null: reduction only (norm and energy of v0)
+            v1[i] = h;
+            double2 a = make_double2(0.0, 0.0);
+            a = cfma(g0, vi, a);
+            a = cfma(g1, h, a);
+            acc[i] = a;
+        }
+        if (ckpt) ckpt[i] = vi;
+        nrm = vi.x * vi.x + vi.y * vi.y;
+        e = vi.x * h.x + vi.y * h.y;
+    }
+    block_sum2(nrm, e, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = nrm;
+        partials[2 * blockIdx.x + 1] = e;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_head_chain(OpChain op, const double2 *__restrict__ v0,
+                                                       double2 *__restrict__ v1,
+                                                       double2 *__restrict__ acc, double2 g0,
+                                                       double2 g1, double2 *ckpt, double *partials)
+{
+    const int64_t i = ChainRow::row(op);
+    double2 vi = make_double2(0.0, 0.0), h2 = vi;
+    if (i >= 0) {
+        vi = v0[i];
+        h2 = ChainRow::apply2(op, i, v0, vi);
+    }
+    head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
+}
+
+template <int EDGE>
+__global__ __launch_bounds__(kBlock) void k_head_honey(OpHoney op, const double2 *__restrict__ v0,
+                                                       double2 *__restrict__ v1,
+                                                       double2 *__restrict__ acc, double2 g0,
+                                                       double2 g1, double2 *ckpt, double *partials)
+{
+    int32_t x, y;
+    const int64_t i = HoneyRow<EDGE>::row_xy(op, x, y);
+    double2 vi = make_double2(0.0, 0.0), h2 = vi;
+    if (i >= 0) {
+        vi = v0[i];
+        h2 = HoneyRow<EDGE>::apply2(op, i, x, y, v0, vi);
+    }
+    head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_head_csr(OpCsr op, const double2 *__restrict__ v0,
+                                                     double2 *__restrict__ v1,
+                                                     double2 *__restrict__ acc, double2 g0,
+                                                     double2 g1, double2 *ckpt, double *partials)
+{
+    const int64_t i = CsrRow::row(op);
+    double2 vi = make_double2(0.0, 0.0), h2 = vi;
+    if (i >= 0) {
+        vi = v0[i];
+        h2 = CsrRow::apply2(op, i, v0, vi);
+    }
+    head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Hot loop: v_{k+1} = 2 H~ v_k - v_{k-1} over v_{k-1}; acc += g v_{k+1}
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void iter_body(int64_t i, double2 h2, double2 *vprev, double2 *acc,
+                                          double2 g)
+{
+    const double2 p = vprev[i];
+    const double2 nv = csub(h2, p);
+    vprev[i] = nv;
+    acc[i] = cfma(g, nv, acc[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_iter_chain(OpChain op, const double2 *__restrict__ vk,
+                                                       double2 *vprev, double2 *__restrict__ acc,
+                                                       double2 g)
+{
+    const int64_t i = ChainRow::row(op);
+    if (i < 0) return;
+    const double2 vi = vk[i];
+    iter_body(i, ChainRow::apply2(op, i, vk, vi), vprev, acc, g);
+}
+
+template <int EDGE>
+__global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2 *__restrict__ vk,
+                                                       double2 *vprev, double2 *__restrict__ acc,
+                                                       double2 g)
+{
+    int32_t x, y;
+    const int64_t i = HoneyRow<EDGE>::row_xy(op, x, y);
+    if (i < 0) return;
+    const double2 vi = vk[i];
+    iter_body(i, HoneyRow<EDGE>::apply2(op, i, x, y, vk, vi), vprev, acc, g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_iter_csr(OpCsr op, const double2 *__restrict__ vk,
+                                                     double2 *vprev, double2 *__restrict__ acc,
+                                                     double2 g)
+{
+    const int64_t i = CsrRow::row(op);
+    if (i < 0) return;
+    const double2 vi = vk[i];
+    iter_body(i, CsrRow::apply2(op, i, vk, vi), vprev, acc, g);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+// One block: fixed-order sums of (norm, <v0|H~v0>) partials; writes the
+// values for step counter[0] and advances the counter.
+__global__ __launch_bounds__(256) void k_finalize_ne(const double *__restrict__ partials, int nparts,
+                                                     double a, double b, double *norm_out,
+                                                     double *energy_out, int64_t *counter,
+                                                     double *dst2)
+{
+    __shared__ double red[2 * 4];
+    double s0 = 0.0, s1 = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+        s0 += partials[2 * p];
+        s1 += partials[2 * p + 1];
+    }
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+        const double energy = a * s1 + b * s0;
+        if (counter) {
+            const int64_t s = counter[0];
+            if (norm_out) norm_out[s] = s0;
+            if (energy_out) energy_out[s] = energy;
+            counter[0] = s + 1;
+        }
+        if (dst2) {
+            dst2[0] = s0;
+            dst2[1] = energy;
+        }
+    }
+}
+
+__global__ void k_reset_counter(int64_t *counter) { counter[0] = 0; }
+
+__global__ __launch_bounds__(kBlock) void k_norm(const double2 *__restrict__ psi, int64_t n,
+                                                 double *partials)
+{
+    __shared__ double red[2 * (kBlock / 64)];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0, z = 0.0;
+    if (i < n) {
+        const double2 v = psi[i];
+        s = v.x * v.x + v.y * v.y;
+    }
+    block_sum2(s, z, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s;
+        partials[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_region(const double2 *__restrict__ psi,
+                                                   const uint8_t *__restrict__ mask, int64_t n,
+                                                   double *partials)
+{
+    __shared__ double red[2 * (kBlock / 64)];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0, z = 0.0;
+    if (i < n && mask[i]) {
+        const double2 v = psi[i];
+        s = v.x * v.x + v.y * v.y;
+    }
+    block_sum2(s, z, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s;
+        partials[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// out[0] = sum of partials[2p], out[1] = sum of partials[2p+1] (fixed order)
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ partials,
+                                                      int nparts, double *out)
+{
+    __shared__ double red[2 * 4];
+    double s0 = 0.0, s1 = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+        s0 += partials[2 * p];
+        s1 += partials[2 * p + 1];
+    }
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_density(const double2 *__restrict__ psi,
+                                                    double *__restrict__ rho, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const double2 v = psi[i];
+        rho[i] = v.x * v.x + v.y * v.y;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(double *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.0;
+}
+
+// dst = g src (src may equal dst)
+__global__ __launch_bounds__(kBlock) void k_scale_copy(const double2 *src, double2 *dst, double2 g,
+                                                       int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        double2 a = make_double2(0.0, 0.0);
+        dst[i] = cfma(g, src[i], a);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR structure check (run once when a caller hands in a matrix): flag[0] is
+// set if rowptr is not a non-decreasing map from [0, n] onto [0, nnz] or a
+// column index falls outside [0, n).  Columns are read only inside a row
+// whose bounds were verified first.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_csr_check(const int64_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ col, int64_t n,
+                                                      int64_t nnz, int64_t *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p0 = rowptr[i], p1 = rowptr[i + 1];
+    bool bad = p0 < 0 || p1 < p0 || p1 > nnz;
+    if (i == 0 && p0 != 0) bad = true;
+    if (i == n - 1 && p1 != nnz) bad = true;
+    if (!bad) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const int32_t c = col[p];
+            if (c < 0 || (int64_t)c >= n) bad = true;
+        }
+    }
+    if (bad) flag[0] = 1;
+}
+
+__global__ void k_clear_flag(int64_t *flag) { flag[0] = 0; }
+
+hipError_t launch_csr_check(hipStream_t s, const int64_t *rowptr, const int32_t *col, int64_t n,
+                            int64_t nnz, int64_t *flag)
+{
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, s, flag);
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_csr_check, dim3((unsigned)nb), dim3(kBlock), 0, s, rowptr, col, n, nnz, flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gershgorin discs: per block (min(H_ii - R_i), max(H_ii + R_i))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_minmax(double &lo, double &hi, double *lds)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        lds[2 * w] = lo;
+        lds[2 * w + 1] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 0; i < nw; ++i) {
+            lo = fmin(lo, lds[2 * i]);
+            hi = fmax(hi, lds[2 * i + 1]);
+        }
+    }
+}
+
+struct GershSrc {
+    int kind;  // 0 chain, 1 honeycomb zigzag, 2 honeycomb armchair, 3 csr
+    int64_t n;
+    const double *onsite;  // V or eps
+    double dx;
+    double t;
+    int32_t W, L;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double2 *val;
+};
+
+__global__ __launch_bounds__(kBlock) void k_gersh(GershSrc g, double *partials)
+{
+    __shared__ double red[2 * (kBlock / 64)];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lo = INFINITY, hi = -INFINITY;
+    if (i < g.n) {
+        double d = 0.0, r = 0.0;
+        if (g.kind == 0) {
+            const double inv = 1.0 / (g.dx * g.dx), h = 0.5 / (g.dx * g.dx);
+            d = inv + g.onsite[i];
+            if (i > 0) r += h;
+            if (i + 1 < g.n) r += h;
+        } else if (g.kind == 1 || g.kind == 2) {
+            const int32_t y = (int32_t)(i / g.L), x = (int32_t)(i - (int64_t)y * g.L);
+            const bool even = ((x + y) & 1) == 0;
+            int nb = 0;
+            if (g.kind == 1) {
+                nb += (x > 0) + (x + 1 < g.L);
+                nb += even ? (y + 1 < g.W) : (y > 0);
+            } else {
+                nb += (y > 0) + (y + 1 < g.W);
+                nb += even ? (x + 1 < g.L) : (x > 0);
+            }
+            d = g.onsite[i];
+            for (int q = 0; q < nb; ++q) r += fabs(g.t);
+        } else {
+            for (int64_t p = g.rowptr[i]; p < g.rowptr[i + 1]; ++p) {
+                const double2 h = g.val[p];
+                if (g.col[p] == i)
+                    d += h.x;
+                else
+                    r += sqrt(h.x * h.x + h.y * h.y);
+            }
+        }
+        lo = d - r;
+        hi = d + r;
+    }
+    block_minmax(lo, hi, red);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = lo;
+        partials[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_minmax_final(const double *partials, int nparts,
+                                                      double *out2)
+{
+    __shared__ double red[2 * 4];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+        lo = fmin(lo, partials[2 * p]);
+        hi = fmax(hi, partials[2 * p + 1]);
+    }
+    block_minmax(lo, hi, red);
+    if (threadIdx.x == 0) {
+        out2[0] = lo;
+        out2[1] = hi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Holstein observables (Fig. 3): one thread per phonon configuration r with
+// its L electron sites contiguous in psi.  Per site s the block reduces
+//   <n_s>        += |psi(r,s)|^2
+//   <b_s^+ b_s>  += n_s(r) * sum_j |psi(r,j)|^2
+//   chi_ss       += 2 Re[conj(psi(r,s)) sqrt(n_s(r)+1) psi(up_s(r), s)]
+// into partials[block][3L].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_holstein_obs(const double2 *__restrict__ psi,
+                                                         const uint8_t *__restrict__ occ,
+                                                         const int32_t *__restrict__ up,
+                                                         int64_t nconf, int L, double *partials)
+{
+    __shared__ double red[2 * (kBlock / 64)];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = r < nconf;
+    double w = 0.0;
+    if (valid) {
+        for (int j = 0; j < L; ++j) {
+            const double2 v = psi[r * L + j];
+            w += v.x * v.x + v.y * v.y;
+        }
+    }
+    for (int s = 0; s < L; ++s) {
+        double dn = 0.0, dph = 0.0, dchi = 0.0;
+        if (valid) {
+            const double2 v = psi[r * L + s];
+            const int ns = occ[r * L + s];
+            dn = v.x * v.x + v.y * v.y;
+            dph = ns * w;
+            const int32_t ru = up[r * L + s];
+            if (ru >= 0) {
+                const double2 u = psi[(int64_t)ru * L + s];
+                dchi = 2.0 * sqrt((double)ns + 1.0) * (v.x * u.x + v.y * u.y);
+            }
+        }
+        block_sum2(dn, dph, red);
+        __syncthreads();
+        double z = 0.0;
+        block_sum2(dchi, z, red);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double *dst = partials + (size_t)blockIdx.x * 3 * L;
+            dst[s] = dn;
+            dst[L + s] = dph;
+            dst[2 * L + s] = dchi;
+        }
+    }
+}
+
+__global__ void k_holstein_obs_final(const double *partials, int nparts, int L, double *n_out,
+                                     double *nph_out, double *chi_out)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= 3 * L) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += partials[(size_t)p * 3 * L + o];
+    if (o < L)
+        n_out[o] = s;
+    else if (o < 2 * L)
+        nph_out[o - L] = s;
+    else
+        chi_out[o - 2 * L] = s;
+}
+
+// ---------------------------------------------------------------------------
+// One-workgroup persistent kernel for short chains (n <= 1024 R): the whole
+// K-step run stays in registers.  Thread t owns rows [t R, t R + R); the
+// neighbour rows of its block come from lanes t-1 and t+1 (cross-lane
+// shuffles) and, at wavefront edges, from LDS slots written once per order.
+// One barrier per recursion order; the LDS slots alternate between two
+// banks so that a slot is never rewritten before every wavefront read it.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(1024) void k_chain_small(OpChain op, const double2 *psi_in,
+                                                      double2 *psi_out,
+                                                      const double2 *__restrict__ gamma, int M,
+                                                      int64_t K, double a, double b,
+                                                      double *norm_out, double *energy_out,
+                                                      double2 *ckpt)
+{
+    __shared__ double2 edge_lo[2][16];  // first row of each wavefront
+    __shared__ double2 edge_hi[2][16];  // last row of each wavefront
+    __shared__ double red[2 * 16];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const int64_t row0 = (int64_t)tid * R;
+
+    double d[R];
+    double2 cur[R], prev[R], acc[R];
+    bool ok[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = row0 + r;
+        ok[r] = i < op.n;
+        d[r] = ok[r] ? op.s2 * (op.V[i] + op.dsh) : 0.0;
+        cur[r] = ok[r] ? psi_in[i] : make_double2(0.0, 0.0);
+    }
+    int bank = 0;
+
+    // (2 H~ x) for this thread's rows, x given in registers
+    auto apply2 = [&](const double2 (&x)[R], double2 (&y)[R]) {
+        // neighbours across lanes
+        double2 left, right;
+        left.x = __shfl_up(x[R - 1].x, 1, 64);
+        left.y = __shfl_up(x[R - 1].y, 1, 64);
+        right.x = __shfl_down(x[0].x, 1, 64);
+        right.y = __shfl_down(x[0].y, 1, 64);
+        if (lane == 0) edge_lo[bank][wave] = x[0];
+        if (lane == 63) edge_hi[bank][wave] = x[R - 1];
+        __syncthreads();
+        if (lane == 0) left = wave > 0 ? edge_hi[bank][wave - 1] : make_double2(0.0, 0.0);
+        if (lane == 63) right = wave + 1 < nwave ? edge_lo[bank][wave + 1] : make_double2(0.0, 0.0);
+        bank ^= 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double2 l = r == 0 ? left : x[r - 1];
+            const double2 rr = r == R - 1 ? right : x[r + 1];
+            const double sx = l.x + rr.x, sy = l.y + rr.y;
+            y[r] = ok[r] ? make_double2(fma(d[r], x[r].x, op.off2 * sx), fma(d[r], x[r].y, op.off2 * sy))
+                         : make_double2(0.0, 0.0);
+        }
+    };
+
+    for (int64_t s = 0; s < K; ++s) {
+        // step head
+        double2 h[R];
+        apply2(cur, h);
+        double nrm = 0.0, e = 0.0;
+        const double2 g0 = gamma[0];
+        const double2 g1 = M >= 1 ? gamma[1] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            h[r] = cscale(0.5, h[r]);
+            if (ckpt && ok[r]) ckpt[(size_t)s * op.n + row0 + r] = cur[r];
+            nrm += cur[r].x * cur[r].x + cur[r].y * cur[r].y;
+            e += cur[r].x * h[r].x + cur[r].y * h[r].y;
+            double2 z = make_double2(0.0, 0.0);
+            z = cfma(g0, cur[r], z);
+            acc[r] = cfma(g1, h[r], z);
+            prev[r] = cur[r];
+            cur[r] = h[r];
+        }
+        block_sum2(nrm, e, red);
+        if (tid == 0) {
+            if (norm_out) norm_out[s] = nrm;
+            if (energy_out) energy_out[s] = a * e + b * nrm;
+        }
+        // hot loop
+        for (int k = 1; k <= M - 1; ++k) {
+            const double2 g = gamma[k + 1];
+            double2 y[R];
+            apply2(cur, y);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double2 nv = csub(y[r], prev[r]);
+                acc[r] = cfma(g, nv, acc[r]);
+                prev[r] = cur[r];
+                cur[r] = ok[r] ? nv : make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) cur[r] = acc[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (ok[r]) psi_out[row0 + r] = cur[r];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int64_t grid_blocks(const Ctx &c)
+{
+    if (c.kind == HKind::Honeycomb) return c.W * ((c.L + kBlock - 1) / kBlock);
+    return (c.n + kBlock - 1) / kBlock;
+}
+
+hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *v1, double2 *acc,
+                       double2 g0, double2 g1, double2 *ckpt, double *partials)
+{
+    const dim3 grid((unsigned)grid_blocks(c)), block(kBlock);
+    switch (c.kind) {
+    case HKind::Chain:
+        hipLaunchKernelGGL(k_head_chain, grid, block, 0, s, make_chain(c), v0, v1, acc, g0, g1, ckpt,
+                           partials);
+        break;
+    case HKind::Honeycomb:
+        if (c.edge == CHEBTD_ZIGZAG)
+            hipLaunchKernelGGL(k_head_honey<CHEBTD_ZIGZAG>, grid, block, 0, s, make_honey(c), v0, v1,
+                               acc, g0, g1, ckpt, partials);
+        else
+            hipLaunchKernelGGL(k_head_honey<CHEBTD_ARMCHAIR>, grid, block, 0, s, make_honey(c), v0,
+                               v1, acc, g0, g1, ckpt, partials);
+        break;
+    case HKind::Csr:
+        hipLaunchKernelGGL(k_head_csr, grid, block, 0, s, make_csr(c), v0, v1, acc, g0, g1, ckpt,
+                           partials);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *vprev,
+                       double2 *acc, double2 g)
+{
+    const dim3 grid((unsigned)grid_blocks(c)), block(kBlock);
+    switch (c.kind) {
+    case HKind::Chain:
+        hipLaunchKernelGGL(k_iter_chain, grid, block, 0, s, make_chain(c), vk, vprev, acc, g);
+        break;
+    case HKind::Honeycomb:
+        if (c.edge == CHEBTD_ZIGZAG)
+            hipLaunchKernelGGL(k_iter_honey<CHEBTD_ZIGZAG>, grid, block, 0, s, make_honey(c), vk,
+                               vprev, acc, g);
+        else
+            hipLaunchKernelGGL(k_iter_honey<CHEBTD_ARMCHAIR>, grid, block, 0, s, make_honey(c), vk,
+                               vprev, acc, g);
+        break;
+    case HKind::Csr:
+        hipLaunchKernelGGL(k_iter_csr, grid, block, 0, s, make_csr(c), vk, vprev, acc, g);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_ne(hipStream_t s, const double *partials, int nparts, double a, double b,
+                              double *norm_out, double *energy_out, int64_t *step_counter,
+                              double *dst2)
+{
+    hipLaunchKernelGGL(k_finalize_ne, dim3(1), dim3(256), 0, s, partials, nparts, a, b, norm_out,
+                       energy_out, step_counter, dst2);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(hipStream_t s, int64_t *counter)
+{
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(const Ctx &c, hipStream_t s, const double2 *psi, double *partials)
+{
+    const int64_t nb = (c.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_norm, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, c.n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(hipStream_t s, const double *partials, int nparts, int stride,
+                               double *out)
+{
+    (void)stride;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t s, const double2 *src, double2 *dst, int64_t n)
+{
+    return hipMemcpyAsync(dst, src, (size_t)n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t launch_scale_copy(hipStream_t s, const double2 *src, double2 *dst, double2 g, int64_t n)
+{
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_scale_copy, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst, g, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(hipStream_t s, const double2 *psi, double *rho, int64_t n)
+{
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_density, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, rho, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_region(hipStream_t s, const double2 *psi, const uint8_t *mask, int64_t n,
+                         double *partials, double *out)
+{
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_region, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, mask, n, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, (int)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gershgorin(const Ctx &c, hipStream_t s, double *partials, double *out2)
+{
+    GershSrc g{};
+    g.n = c.n;
+    switch (c.kind) {
+    case HKind::Chain:
+        g.kind = 0;
+        g.onsite = c.V;
+        g.dx = c.dx;
+        break;
+    case HKind::Honeycomb:
+        g.kind = c.edge == CHEBTD_ZIGZAG ? 1 : 2;
+        g.onsite = c.eps;
+        g.t = c.t_hop;
+        g.W = (int32_t)c.W;
+        g.L = (int32_t)c.L;
+        break;
+    case HKind::Csr:
+        g.kind = 3;
+        g.rowptr = c.rowptr;
+        g.col = c.col;
+        g.val = reinterpret_cast<const double2 *>(c.val);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    const int64_t nb = (c.n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_gersh, dim3((unsigned)nb), dim3(kBlock), 0, s, g, partials);
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, partials, (int)nb, out2);
+    return hipGetLastError();
+}
+
+int holstein_obs_blocks(int64_t nconf) { return (int)((nconf + kBlock - 1) / kBlock); }
+
+hipError_t launch_holstein_obs(hipStream_t s, const double2 *psi, const uint8_t *occ,
+                               const int32_t *up, int64_t nconf, int L, double *partials,
+                               double *n_out, double *nph_out, double *chi_out)
+{
+    const int nb = holstein_obs_blocks(nconf);
+    hipLaunchKernelGGL(k_holstein_obs, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, occ, up, nconf, L,
+                       partials);
+    hipLaunchKernelGGL(k_holstein_obs_final, dim3((3 * L + 63) / 64), dim3(64), 0, s, partials, nb, L,
+                       n_out, nph_out, chi_out);
+    return hipGetLastError();
+}
+
+bool chain_small_fits(int64_t n) { return n >= 1 && n <= 4096; }
+
+hipError_t launch_chain_small(const Ctx &c, hipStream_t s, double2 *psi, double2 *out,
+                              const double2 *gamma_dev, int64_t K, double *norm_out,
+                              double *energy_out, double2 *ckpt)
+{
+    const OpChain op = make_chain(c);
+    if (c.n <= 1024)
+        hipLaunchKernelGGL(k_chain_small<1>, dim3(1), dim3(1024), 0, s, op, psi, out, gamma_dev, c.M,
+                           K, c.a, c.b, norm_out, energy_out, ckpt);
+    else if (c.n <= 2048)
+        hipLaunchKernelGGL(k_chain_small<2>, dim3(1), dim3(1024), 0, s, op, psi, out, gamma_dev, c.M,
+                           K, c.a, c.b, norm_out, energy_out, ckpt);
+    else if (c.n <= 4096)
+        hipLaunchKernelGGL(k_chain_small<4>, dim3(1), dim3(1024), 0, s, op, psi, out, gamma_dev, c.M,
+                           K, c.a, c.b, norm_out, energy_out, ckpt);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(hipStream_t s, double *p, int64_t count)
+{
+    const int64_t nb = (count + kBlock - 1) / kBlock;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(kBlock), 0, s, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace chebtd

@@ -1,0 +1,274 @@
+// Time stepping and observables of chebtd (Sect. 2.2 and Sect. 3 of
+// arXiv:0907.3022).  One step: the head kernel forms v_1 = H~ psi and
+// acc = gamma_0 psi + gamma_1 v_1, then M-1 fused recursion kernels form
+// v_{k+1} = 2 H~ v_k - v_{k-1} and acc += gamma_{k+1} v_{k+1}; acc is the
+// next state.  Buffers rotate so that no copy is made inside the K steps.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+
+namespace chebtd {
+int fail(Ctx *c, int code, const std::string &msg);
+int hip_fail(Ctx *c, hipError_t e, const char *what);
+int ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what);
+void release(DevBuf &b);
+void drop_graphs(Ctx *c);
+double2 *adj_checkpoint(Ctx *c, int64_t step, int64_t K);  // adjoint.cpp
+}  // namespace chebtd
+
+using namespace chebtd;
+struct chebtd_ctx : public Ctx {};
+
+namespace {
+
+double2 weight(const Ctx *c, int k)
+{
+    if (k > c->M) return make_double2(0.0, 0.0);
+    return make_double2(c->gamma[2 * (size_t)k], c->gamma[2 * (size_t)k + 1]);
+}
+
+// Enqueue one time step: cur -> nxt.  cur is overwritten with v_2, v_4, ...
+hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt,
+                        double *norm_out, double *energy_out)
+{
+    double2 *A = static_cast<double2 *>(c->vA.p);
+    double *partials = static_cast<double *>(c->partials.p);
+    hipError_t e = launch_head(*c, s, cur, A, nxt, weight(c, 0), weight(c, 1), ckpt, partials);
+    if (e != hipSuccess) return e;
+    if (norm_out || energy_out) {
+        e = launch_finalize_ne(s, partials, (int)grid_blocks(*c), c->a, c->b, norm_out, energy_out,
+                               static_cast<int64_t *>(c->counter.p), nullptr);
+        if (e != hipSuccess) return e;
+    }
+    for (int k = 1; k <= c->M - 1; ++k) {
+        double2 *vk = (k & 1) ? A : cur;
+        double2 *vprev = (k & 1) ? cur : A;
+        e = launch_iter(*c, s, vk, vprev, nxt, weight(c, k + 1));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// norm of psi into results[slot]
+hipError_t enqueue_norm(Ctx *c, hipStream_t s, const double2 *psi, int slot)
+{
+    double *partials = static_cast<double *>(c->partials.p);
+    hipError_t e = launch_norm(*c, s, psi, partials);
+    if (e != hipSuccess) return e;
+    return launch_sum_partials(s, partials, (int)((c->n + kBlock - 1) / kBlock), 2,
+                               static_cast<double *>(c->results.p) + slot);
+}
+
+// Two steps (psi -> B -> psi) captured once into a graph and replayed.
+int get_pair_graph(Ctx *c, double2 *psi, double *norm_out, double *energy_out, hipGraphExec_t *out)
+{
+    const void *key[4] = {psi, norm_out, energy_out, c->vA.p};
+    if (c->graph_exec[0] && key[0] == c->graph_key[0] && key[1] == c->graph_key[1] &&
+        key[2] == c->graph_key[2] && key[3] == c->graph_key[3]) {
+        *out = c->graph_exec[0];
+        return CHEBTD_OK;
+    }
+    drop_graphs(c);
+    hipError_t e = hipSuccess;
+    if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(c, e, "graph stream");
+    double2 *B = static_cast<double2 *>(c->vB.p);
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+    hipError_t e1 = enqueue_step(c, c->cap_stream, psi, B, nullptr, norm_out, energy_out);
+    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, c->cap_stream, B, psi, nullptr, norm_out, energy_out)
+                                     : e1;
+    e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(c, e2, "graph capture of a step");
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->graph_exec[0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph_exec[0] = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    for (int i = 0; i < 4; ++i) c->graph_key[i] = key[i];
+    *out = c->graph_exec[0];
+    return CHEBTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_dev,
+                     double *energy_dev, unsigned flags)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (!c->has_plan) return fail(c, CHEBTD_E_STATE, "chebtd_propagate: no plan");
+    if (!psi_dev || K < 0) return fail(c, CHEBTD_E_ARG, "chebtd_propagate: need psi and K >= 0");
+    if (K == 0) return CHEBTD_OK;
+    const bool keep = (flags & CHEBTD_KEEP_CHECKPOINTS) != 0;
+    if (keep && !adj_checkpoint(c, 0, K))
+        return fail(c, CHEBTD_E_STATE,
+                    "chebtd_propagate: checkpoints need chebtd_reserve_adjoint with max_steps >= K");
+    const bool check = (flags & CHEBTD_NO_CHECK) == 0;
+    hipStream_t s = c->stream;
+    double2 *P = reinterpret_cast<double2 *>(psi_dev);
+    double2 *B = static_cast<double2 *>(c->vB.p);
+    hipError_t e = hipSuccess;
+
+    if (check) {
+        e = enqueue_norm(c, s, P, 0);
+        if (e != hipSuccess) return hip_fail(c, e, "initial norm");
+    }
+    if (norm_dev || energy_dev) {
+        e = launch_reset_counter(s, static_cast<int64_t *>(c->counter.p));
+        if (e != hipSuccess) return hip_fail(c, e, "counter reset");
+    }
+
+    const bool small = c->kind == HKind::Chain && chain_small_fits(c->n) &&
+                       !(flags & CHEBTD_NO_PERSISTENT);
+    if (small) {
+        e = launch_chain_small(*c, s, P, P, static_cast<const double2 *>(c->gamma_dev.p), K, norm_dev,
+                               energy_dev, keep ? adj_checkpoint(c, 0, K) : nullptr);
+        if (e != hipSuccess) return hip_fail(c, e, "persistent chain kernel");
+    } else if ((flags & CHEBTD_GRAPH) && !keep) {
+        hipGraphExec_t ge = nullptr;
+        int rc = get_pair_graph(c, P, norm_dev, energy_dev, &ge);
+        if (rc) return rc;
+        for (int64_t s2 = 0; s2 + 1 < K; s2 += 2) {
+            e = hipGraphLaunch(ge, s);
+            if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+        }
+        if (K & 1) {
+            e = enqueue_step(c, s, P, B, nullptr, norm_dev, energy_dev);
+            if (e == hipSuccess) e = launch_copy(s, B, P, c->n);
+            if (e != hipSuccess) return hip_fail(c, e, "last step");
+        }
+    } else {
+        for (int64_t st = 0; st < K; ++st) {
+            double2 *cur = (st & 1) ? B : P;
+            double2 *nxt = (st & 1) ? P : B;
+            e = enqueue_step(c, s, cur, nxt, keep ? adj_checkpoint(c, st, K) : nullptr, norm_dev,
+                             energy_dev);
+            if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        }
+        if (K & 1) {
+            e = launch_copy(s, B, P, c->n);
+            if (e != hipSuccess) return hip_fail(c, e, "final copy");
+        }
+    }
+
+    if (!check) return CHEBTD_OK;
+    e = enqueue_norm(c, s, P, 2);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->pinned, c->results.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "norm check");
+    const double n0 = c->pinned[0], n1 = c->pinned[2];
+    if (!std::isfinite(n1) || !std::isfinite(n0) || std::fabs(n1 - n0) > c->check_tol * n0) {
+        return fail(c, CHEBTD_E_DIVERGED,
+                    "chebtd_propagate: norm went from " + std::to_string(n0) + " to " +
+                        std::to_string(n1) + "; the spectral bounds do not enclose H");
+    }
+    return CHEBTD_OK;
+}
+
+int chebtd_density(chebtd_ctx *ctx, const double *psi_dev, double *rho_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (c->kind == HKind::None) return fail(c, CHEBTD_E_STATE, "chebtd_density: no Hamiltonian");
+    if (!psi_dev || !rho_dev) return fail(c, CHEBTD_E_ARG, "chebtd_density: null pointer");
+    hipError_t e = launch_density(c->stream, reinterpret_cast<const double2 *>(psi_dev), rho_dev, c->n);
+    return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, "chebtd_density");
+}
+
+int chebtd_region_sum(chebtd_ctx *ctx, const double *psi_dev, const uint8_t *mask_dev,
+                      double *out_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (c->kind == HKind::None) return fail(c, CHEBTD_E_STATE, "chebtd_region_sum: no Hamiltonian");
+    if (!psi_dev || !mask_dev || !out_dev) return fail(c, CHEBTD_E_ARG, "chebtd_region_sum: null pointer");
+    // out_dev receives the sum; partials go to the context's scratch
+    double *res = static_cast<double *>(c->results.p) + 8;
+    hipError_t e = launch_region(c->stream, reinterpret_cast<const double2 *>(psi_dev), mask_dev, c->n,
+                                 static_cast<double *>(c->partials.p), res);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out_dev, res, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, "chebtd_region_sum");
+}
+
+int chebtd_norm_energy(chebtd_ctx *ctx, const double *psi_dev, double *out2_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (c->kind == HKind::None || !c->has_bounds)
+        return fail(c, CHEBTD_E_STATE, "chebtd_norm_energy: needs a Hamiltonian and bounds");
+    if (!psi_dev || !out2_dev) return fail(c, CHEBTD_E_ARG, "chebtd_norm_energy: null pointer");
+    double *partials = static_cast<double *>(c->partials.p);
+    hipError_t e = launch_head(*c, c->stream, reinterpret_cast<const double2 *>(psi_dev), nullptr,
+                               nullptr, make_double2(0, 0), make_double2(0, 0), nullptr, partials);
+    if (e == hipSuccess)
+        e = launch_finalize_ne(c->stream, partials, (int)grid_blocks(*c), c->a, c->b, nullptr, nullptr,
+                               nullptr, out2_dev);
+    return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, "chebtd_norm_energy");
+}
+
+int chebtd_holstein_obs(chebtd_ctx *ctx, const double *psi_dev, double *n_dev, double *nph_dev,
+                        double *chi_dev)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (!c->holstein) return fail(c, CHEBTD_E_STATE, "chebtd_holstein_obs: H is not a Holstein model");
+    if (!psi_dev || !n_dev || !nph_dev || !chi_dev)
+        return fail(c, CHEBTD_E_ARG, "chebtd_holstein_obs: null pointer");
+    hipError_t e = launch_holstein_obs(
+        c->stream, reinterpret_cast<const double2 *>(psi_dev), static_cast<const uint8_t *>(c->hol_occ.p),
+        static_cast<const int32_t *>(c->hol_up.p), c->hol_nconf, c->hol_L,
+        static_cast<double *>(c->partials.p), n_dev, nph_dev, chi_dev);
+    return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, "chebtd_holstein_obs");
+}
+
+int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, double *ms_per_launch,
+                                 const char **name_out)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (!c->has_plan) return fail(c, CHEBTD_E_STATE, "chebtd_time_recursion_kernel: no plan");
+    if (launches < 1 || !ms_per_launch) return fail(c, CHEBTD_E_ARG, "need launches >= 1 and an output");
+    static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr"};
+    const char *nm = c->kind == HKind::Chain ? names[0]
+                     : c->kind == HKind::Csr ? names[3]
+                     : (c->edge == CHEBTD_ZIGZAG ? names[1] : names[2]);
+    if (name_out) *name_out = nm;
+    DevBuf acc;
+    int rc = ensure(c, acc, (size_t)c->n * sizeof(double2), "timing accumulator");
+    if (rc) return rc;
+    hipStream_t s = c->stream;
+    double2 *A = static_cast<double2 *>(c->vA.p), *B = static_cast<double2 *>(c->vB.p);
+    hipError_t e = hipMemsetAsync(acc.p, 0, acc.bytes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(A, 0, c->vA.bytes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(B, 0, c->vB.bytes, s);
+    // one untimed launch to page in code and caches
+    if (e == hipSuccess) e = launch_iter(*c, s, A, B, static_cast<double2 *>(acc.p), weight(c, 1));
+    if (e == hipSuccess) e = hipEventRecord(c->ev_a, s);
+    for (int i = 0; i < launches && e == hipSuccess; ++i)
+        e = launch_iter(*c, s, (i & 1) ? B : A, (i & 1) ? A : B, static_cast<double2 *>(acc.p),
+                        weight(c, 1));
+    if (e == hipSuccess) e = hipEventRecord(c->ev_b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev_b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev_a, c->ev_b);
+    release(acc);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_time_recursion_kernel");
+    *ms_per_launch = (double)ms / launches;
+    return CHEBTD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,359 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every comparison feeds both sides the same seeded inputs (workloads) and the
+same spectral bounds (the oracle's Gershgorin discs), then checks the
+relative L2 error of psi against 1e-10; integer/structural results must
+match exactly and repeated GPU runs must agree bit for bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a visible GPU"
+    return T
+
+
+@pytest.fixture(scope="module")
+def cheb():
+    import paper_0907_3022_amd as P
+    P.load_library()  # fails loudly when the HIP library is missing
+    return P
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(torch, x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# helpers building the same problem on both sides
+# ---------------------------------------------------------------------------
+def chain_case(n, xmin=-20.0, xmax=20.0, a=0.05, b=5.0, x0=-5.0, sigma=1.0, k0=1.0):
+    if n == 1:  # single point: H = 1/dx^2 + V
+        V, dx, psi0 = np.array([0.3]), 1.0, np.array([1.0 + 0.0j])
+        return dict(kind="chain", n=1, dx=dx, V=V, psi0=psi0, H=O.chain1d(V, dx))
+    x, dx, V, psi0 = W.double_well_inputs(n, xmin, xmax, a, b, x0, sigma, k0)
+    return dict(kind="chain", n=n, dx=dx, V=V, psi0=psi0, H=O.chain1d(V, dx))
+
+
+def honey_case(width, length, edge="zigzag", Wd=0.5, seed=0, sigma=None, k0=1.0):
+    eps = W.anderson_disorder(width, length, Wd, seed)
+    sig = sigma if sigma is not None else min(20.0, width / 4.0)
+    psi0 = W.ribbon_packet(width, length, sig, k0)
+    return dict(kind="honey", width=width, length=length, edge=edge, eps=eps, psi0=psi0,
+                H=O.honeycomb(width, length, eps, edge=edge))
+
+
+def holstein_case(L, nph, g2, periodic=True, Delta=0.0):
+    g = math.sqrt(g2)
+    nconf = O.holstein_nconf(L, nph)
+    psi0 = W.holstein_vacuum_site(L, 0, nconf)
+    return dict(kind="holstein", L=L, nph=nph, g=g, Delta=Delta, periodic=periodic, psi0=psi0,
+                H=O.holstein(L, nph, 1.0, 1.0, g, Delta, periodic))
+
+
+def gpu_context(torch, cheb, case):
+    ctx = cheb.Context()
+    if case["kind"] == "chain":
+        case["V_dev"] = dev(torch, case["V"])
+        ctx.chain1d(case["V_dev"], case["dx"])
+    elif case["kind"] == "honey":
+        case["eps_dev"] = dev(torch, case["eps"])
+        ctx.honeycomb(case["width"], case["length"], case["eps_dev"], edge=case["edge"])
+    else:
+        ctx.holstein(case["L"], case["nph"], 1.0, 1.0, case["g"], case["Delta"], case["periodic"])
+    return ctx
+
+
+def run_both(torch, cheb, case, dt, K, flags=0, M=None):
+    H = case["H"]
+    emin, emax = H.gershgorin()
+    plan = O.Plan(emin, emax, dt, M=M)
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax, 0.01)
+    Mg = ctx.plan(dt) if M is None else (ctx.plan_order(dt, M) and M)
+    assert Mg == plan.M
+    psi = dev(torch, case["psi0"])
+    nrm = torch.zeros(K, dtype=torch.float64, device="cuda")
+    en = torch.zeros(K, dtype=torch.float64, device="cuda")
+    say(f"[gpu] propagate {case['kind']} n={ctx.n} M={Mg} K={K} flags={flags}")
+    ctx.propagate(psi, K, nrm, en, flags)
+    torch.cuda.synchronize()
+    ref, rn, re = O.propagate(H, plan, case["psi0"], K, want_obs=True)
+    return ctx, host(psi), ref, host(nrm), rn, host(en), re, plan
+
+
+# ---------------------------------------------------------------------------
+# plan
+# ---------------------------------------------------------------------------
+def test_plan_weights_match_oracle(torch, cheb):
+    case = chain_case(600)
+    emin, emax = case["H"].gershgorin()
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax)
+    for dt in (1e-3, 0.05, 0.5):
+        M = ctx.plan(dt)
+        p = ctx.get_plan()
+        ref = O.Plan(emin, emax, dt)
+        assert M == ref.M and p["a"] == ref.a and p["b"] == ref.b
+        np.testing.assert_allclose(p["gamma"], ref.gamma, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("which", ["chain", "zigzag", "armchair", "holstein"])
+def test_gershgorin_matches_oracle(torch, cheb, which):
+    case = {"chain": lambda: chain_case(5000), "zigzag": lambda: honey_case(9, 301),
+            "armchair": lambda: honey_case(9, 301, "armchair"),
+            "holstein": lambda: holstein_case(5, 4, 0.5, False, 0.3)}[which]()
+    ctx = gpu_context(torch, cheb, case)
+    lo, hi = ctx.gershgorin()
+    rlo, rhi = case["H"].gershgorin()
+    assert lo == pytest.approx(rlo, rel=1e-14, abs=1e-14)
+    assert hi == pytest.approx(rhi, rel=1e-14, abs=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# propagation parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,flags", [(1, 0), (17, 0), (700, 0), (1024, 0), (1500, 0), (4096, 0),
+                                     (4096, 8), (5003, 0), (70001, 0)])
+def test_chain_parity(torch, cheb, n, flags):
+    case = chain_case(n) if n > 64 else chain_case(n, -2.0, 2.0)
+    dt, K = (0.02, 4) if n >= 4096 else (0.05, 5)
+    if n == 1:
+        dt = 0.3
+    _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, dt, K, flags)
+    assert rel_l2(psi, ref) <= TOL
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11 * plan.a)
+
+
+@pytest.mark.parametrize("edge,width,length", [("zigzag", 6, 300), ("zigzag", 1, 513),
+                                               ("zigzag", 31, 257), ("armchair", 6, 300),
+                                               ("armchair", 10, 1000), ("zigzag", 128, 200)])
+def test_honeycomb_parity(torch, cheb, edge, width, length):
+    case = honey_case(width, length, edge)
+    _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, 1.0, 6)
+    assert rel_l2(psi, ref) <= TOL
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("L,nph,g2,periodic", [(4, 3, 0.5, True), (6, 4, 2.0, True), (5, 5, 0.5, False)])
+def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic):
+    case = holstein_case(L, nph, g2, periodic, Delta=np.linspace(0, 0.5, L))
+    ctx, psi, ref, nrm, rn, en, re, _ = run_both(torch, cheb, case, 0.1, 8)
+    assert rel_l2(psi, ref) <= TOL
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    n_i, nph_i, chi = (host(t) for t in ctx.holstein_obs(dev(torch, ref)))
+    rn_i, rnph_i, rchi = O.holstein_obs(L, nph, ref)
+    np.testing.assert_allclose(n_i, rn_i, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(nph_i, rnph_i, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(chi, rchi, rtol=1e-11, atol=1e-14)
+
+
+def test_generic_csr_parity(torch, cheb):
+    # a complex Hermitian matrix through chebtd_h_csr (device CSR from the caller)
+    rng = np.random.default_rng(3)
+    n = 777
+    A = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for j in rng.choice(n, 4, replace=False):
+            v = rng.normal() + 1j * rng.normal()
+            A[i, j] += v
+            A[j, i] += np.conj(v)
+    A[np.diag_indices(n)] = rng.normal(size=n)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i in range(n):
+        nz = np.nonzero(A[i])[0]
+        cols += list(nz)
+        vals += list(A[i, nz])
+        rowptr[i + 1] = len(cols)
+    H = O.import_csr(rowptr, np.array(cols), np.array(vals))
+    emin, emax = H.gershgorin()
+    psi0 = (rng.normal(size=n) + 1j * rng.normal(size=n))
+    psi0 /= np.linalg.norm(psi0)
+    plan = O.Plan(emin, emax, 0.7)
+    ctx = cheb.Context()
+    r_d, c_d, v_d = dev(torch, rowptr), dev(torch, np.array(cols, np.int32)), dev(torch, np.array(vals))
+    ctx.csr(r_d, c_d, v_d)
+    lo, hi = ctx.gershgorin()
+    assert lo == pytest.approx(emin, rel=1e-13) and hi == pytest.approx(emax, rel=1e-13)
+    ctx.set_bounds(emin, emax)
+    assert ctx.plan(0.7) == plan.M
+    psi = dev(torch, psi0)
+    ctx.propagate(psi, 5)
+    assert rel_l2(host(psi), O.propagate(H, plan, psi0, 5)) <= TOL
+
+
+@pytest.mark.parametrize("M", [0, 1, 2, 3])
+def test_low_orders(torch, cheb, M):
+    for case in (chain_case(300), chain_case(9000), honey_case(5, 100)):
+        _, psi, ref, *_ = run_both(torch, cheb, case, 1e-4, 3, M=M)
+        assert rel_l2(psi, ref) <= TOL
+
+
+# ---------------------------------------------------------------------------
+# launch-mode equivalence, determinism, resume
+# ---------------------------------------------------------------------------
+def test_graph_replay_matches_direct_launches(torch, cheb):
+    case = honey_case(16, 700)
+    emin, emax = case["H"].gershgorin()
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax)
+    ctx.plan(1.0)
+    outs = []
+    for flags in (0, cheb.GRAPH, cheb.GRAPH, 0):
+        for K in (7, 8):
+            psi = dev(torch, case["psi0"])
+            nrm = torch.zeros(K, dtype=torch.float64, device="cuda")
+            say(f"[gpu] graph flags={flags} K={K}")
+            ctx.propagate(psi, K, nrm, None, flags)
+            torch.cuda.synchronize()
+            outs.append((K, host(psi), host(nrm)))
+    by_k = {}
+    for K, p, n_ in outs:
+        if K in by_k:
+            np.testing.assert_array_equal(p, by_k[K][0])
+            np.testing.assert_array_equal(n_, by_k[K][1])
+        else:
+            by_k[K] = (p, n_)
+
+
+def test_bitwise_determinism_and_resume(torch, cheb):
+    for case in (honey_case(12, 400), chain_case(3000), chain_case(6000),
+                 holstein_case(5, 4, 2.0)):
+        emin, emax = case["H"].gershgorin()
+        ctx = gpu_context(torch, cheb, case)
+        ctx.set_bounds(emin, emax)
+        ctx.plan(0.3)
+        a = dev(torch, case["psi0"])
+        b = dev(torch, case["psi0"])
+        ctx.propagate(a, 9)
+        ctx.propagate(b, 4)
+        ctx.propagate(b, 5)
+        c = dev(torch, case["psi0"])
+        ctx.propagate(c, 9)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(a), host(b))
+        np.testing.assert_array_equal(host(a), host(c))
+
+
+def test_persistent_matches_per_iteration_launches(torch, cheb):
+    case = chain_case(4096)
+    emin, emax = case["H"].gershgorin()
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax)
+    ctx.plan(0.05)
+    a = dev(torch, case["psi0"])
+    b = dev(torch, case["psi0"])
+    ctx.propagate(a, 3)
+    ctx.propagate(b, 3, flags=cheb.NO_PERSISTENT)
+    torch.cuda.synchronize()
+    assert rel_l2(host(a), host(b)) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# observables and failure detection
+# ---------------------------------------------------------------------------
+def test_density_region_norm_energy(torch, cheb):
+    case = honey_case(8, 300)
+    emin, emax = case["H"].gershgorin()
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax)
+    psi = dev(torch, case["psi0"])
+    np.testing.assert_allclose(host(ctx.density(psi)), O.density(case["psi0"]), rtol=1e-15)
+    mask = W.right_half_mask_ribbon(8, 300).astype(np.uint8)
+    mask[::7] = 1
+    out = host(ctx.region_sum(psi, dev(torch, mask)))[0]
+    assert out == pytest.approx(O.region_sum(case["psi0"], mask), rel=1e-13)
+    ne = host(ctx.norm_energy(psi))
+    Hd = case["H"].dense()
+    assert ne[0] == pytest.approx(1.0, rel=1e-13)
+    assert ne[1] == pytest.approx(np.vdot(case["psi0"], Hd @ case["psi0"]).real, rel=1e-12, abs=1e-13)
+
+
+def test_divergence_is_reported(torch, cheb):
+    # bounds that miss most of the spectrum make T_k(H~) grow: the end-of-call
+    # check must report it instead of returning garbage
+    case = chain_case(2000)
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(0.0, 1.0, 0.01)
+    ctx.plan(0.5)
+    psi = dev(torch, case["psi0"])
+    with pytest.raises(cheb.ChebError) as ei:
+        ctx.propagate(psi, 3, flags=cheb.NO_PERSISTENT)
+    assert ei.value.code == -3
+
+
+def test_argument_errors_on_gpu(torch, cheb):
+    ctx = cheb.Context()
+    with pytest.raises(cheb.ChebError):
+        ctx.plan(1.0)  # no Hamiltonian
+    V = torch.zeros(10, dtype=torch.float64, device="cuda")
+    ctx.chain1d(V, 0.1)
+    with pytest.raises(cheb.ChebError):
+        ctx.plan(1.0)  # no bounds
+    with pytest.raises(cheb.ChebError):
+        ctx.set_bounds(1.0, 0.0)
+    with pytest.raises(TypeError):
+        ctx.propagate(torch.zeros(10, dtype=torch.complex64, device="cuda"), 1)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+def test_full_double_well_4096(torch, cheb):
+    p = W.DOUBLE_WELL.params
+    case = chain_case(p["n"], p["xmin"], p["xmax"], p["a"], p["b"], p["x0"], p["sigma"], p["k0"])
+    _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, p["dt"], 2)
+    assert plan.M > 7000
+    assert rel_l2(psi, ref) <= TOL
+    np.testing.assert_allclose(en, re, rtol=1e-11)
+
+
+def test_full_zigzag_ribbon_128x8192(torch, cheb):
+    p = W.GRAPHENE.params
+    case = honey_case(p["width"], p["length"], p["edge"], p["W"], p["seed"], p["sigma"], p["k0"])
+    _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, p["dt"], 3)
+    assert plan.M == 20
+    assert rel_l2(psi, ref) <= TOL
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+
+
+@pytest.mark.parametrize("g2", [0.5, 2.0])
+def test_full_holstein_ring(torch, cheb, g2):
+    p = W.HOLSTEIN.params
+    case = holstein_case(p["L"], p["nph"], g2, p["periodic"])
+    ctx, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, p["dt"], 2)
+    assert ctx.n == 1_847_560
+    assert plan.M == (13 if g2 == 0.5 else 14)
+    assert rel_l2(psi, ref) <= TOL
