@@ -96,6 +96,8 @@ def gpu_context(torch, cheb, case):
 def run_both(torch, cheb, case, dt, K, flags=0, M=None):
     H = case["H"]
     emin, emax = H.gershgorin()
+    if emax == emin:  # a 1x1 Hamiltonian: any interval around its value
+        emin, emax = emin - 1.0, emax + 1.0
     plan = O.Plan(emin, emax, dt, M=M)
     ctx = gpu_context(torch, cheb, case)
     ctx.set_bounds(emin, emax, 0.01)
@@ -124,7 +126,10 @@ def test_plan_weights_match_oracle(torch, cheb):
         p = ctx.get_plan()
         ref = O.Plan(emin, emax, dt)
         assert M == ref.M and p["a"] == ref.a and p["b"] == ref.b
-        np.testing.assert_allclose(p["gamma"], ref.gamma, rtol=0, atol=1e-15)
+        # two independent Miller recurrences: rounding grows like sqrt(z) eps
+        z = ref.a * dt
+        np.testing.assert_allclose(p["gamma"], ref.gamma, rtol=0,
+                                   atol=1e-15 + 4e-16 * np.sqrt(max(z, 1.0)))
 
 
 @pytest.mark.parametrize("which", ["chain", "zigzag", "armchair", "holstein"])
@@ -217,7 +222,8 @@ def test_generic_csr_parity(torch, cheb):
 @pytest.mark.parametrize("M", [0, 1, 2, 3])
 def test_low_orders(torch, cheb, M):
     for case in (chain_case(300), chain_case(9000), honey_case(5, 100)):
-        _, psi, ref, *_ = run_both(torch, cheb, case, 1e-4, 3, M=M)
+        # a forced low order is not unitary: skip the norm check
+        _, psi, ref, *_ = run_both(torch, cheb, case, 1e-4, 3, flags=cheb.NO_CHECK, M=M)
         assert rel_l2(psi, ref) <= TOL
 
 
