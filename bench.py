@@ -1,0 +1,300 @@
+#!/usr/bin/env python3
+"""Benchmark: Chebyshev time propagation on one MI355X.
+
+The headline line times K time steps of the 128 x 8192 zigzag graphene
+ribbon (1,048,576 sites, Anderson disorder W = 0.5, dt = 1, Chebyshev order
+M = 20 from the 1e-15 Bessel cutoff).  One step is the whole hot path: the
+step head (v_1 = H~ psi, acc = gamma_0 psi + gamma_1 v_1, norm and energy
+reductions) and M - 1 fused recursion launches
+v_{k+1} = 2 H~ v_k - v_{k-1}, acc += gamma_{k+1} v_{k+1}.  The plan (bounds,
+Bessel weights) is computed once per dt, outside the timed region, as the
+method prescribes.
+
+value = Hamiltonian applications (H~ v products) per second.
+roofline: the recursion kernel's algorithmic bytes (88 B per site and order)
+over its mean launch time measured with HIP events on the library's stream.
+cpu_baseline: the serial CPU oracle on a few steps of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+STENCIL_BYTES = 88       # per site and order: v_k, v_{k-1}, v_{k+1}, acc r/w, on-site term
+CSR_VEC_BYTES = 80       # vector traffic per row and order for CSR
+CSR_NNZ_BYTES = 20       # complex128 value + int32 column
+CSR_ROW_BYTES = 8        # rowptr
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_ops.h"):
+        with open(os.path.join(ROOT, "paper_0907_3022_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    ent = rec.get(kernel)
+    if not ent or ent.get("source_sha") != source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def ribbon_context(torch, P, width, length, Wd, seed, edge="zigzag", dt=1.0):
+    eps, psi0 = W.ribbon_inputs(width, length, Wd, seed, 20.0, 1.0)
+    eps_d = torch.from_numpy(eps).cuda()
+    psi = torch.from_numpy(psi0).cuda()
+    ctx = P.Context()
+    ctx.honeycomb(width, length, eps_d, edge=edge)
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi, 0.01)
+    M = ctx.plan(dt)
+    return ctx, eps_d, psi, M
+
+
+def timed(torch, fn, reps=1):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+# ---------------------------------------------------------------------------
+def bench_main(torch, P, steps, warmup, mode_flags):
+    p = W.GRAPHENE.params
+    ctx, eps_d, psi, M = ribbon_context(torch, P, p["width"], p["length"], p["W"], p["seed"],
+                                        p["edge"], p["dt"])
+    n = p["width"] * p["length"]
+    nrm = torch.zeros(max(steps, warmup, 1), dtype=torch.float64, device="cuda")
+    en = torch.zeros_like(nrm)
+    flags = P.NO_CHECK | mode_flags
+    if warmup:
+        ctx.propagate(psi, warmup, nrm, en, flags)
+    # timed region: exactly `steps` time steps with per-step norm and energy
+    t = timed(torch, lambda: ctx.propagate(psi, steps, nrm, en, flags))
+    nr = nrm[:steps].cpu().numpy()
+    drift = float(np.abs(nr - nr[0]).max()) if steps else 0.0
+    # dominant kernel timed alone with HIP events on the library's stream
+    ms_iter, kname = ctx.time_recursion_kernel(200)
+    return dict(ctx=ctx, n=n, M=M, seconds=t, ms_iter=ms_iter, kernel=kname, norm_drift=drift,
+                psi=psi, eps=eps_d)
+
+
+def bench_mode_choice(torch, P):
+    """Pick direct launches or hipGraph replay for the main run."""
+    p = W.GRAPHENE.params
+    ctx, eps_d, psi, M = ribbon_context(torch, P, p["width"], p["length"], p["W"], p["seed"],
+                                        p["edge"], p["dt"])
+    best = None
+    for name, fl in (("direct", 0), ("graph", P.GRAPH)):
+        ctx.propagate(psi, 10, None, None, P.NO_CHECK | fl)
+        t = timed(torch, lambda: ctx.propagate(psi, 100, None, None, P.NO_CHECK | fl))
+        log(f"[bench] launch mode {name}: {t / 100 * 1e3:.3f} ms/step")
+        if best is None or t < best[1]:
+            best = (name, t, fl)
+    ctx.close()
+    return best[0], best[2]
+
+
+def bench_double_well(torch, P, K):
+    p = W.DOUBLE_WELL.params
+    x, dx, V, psi0 = W.double_well_inputs(p["n"], p["xmin"], p["xmax"], p["a"], p["b"], p["x0"],
+                                          p["sigma"], p["k0"])
+    ctx = P.Context()
+    V_d = torch.from_numpy(V).cuda()
+    ctx.chain1d(V_d, dx)
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi, 0.01)
+    M = ctx.plan(p["dt"])
+    psi = torch.from_numpy(psi0).cuda()
+    nrm = torch.zeros(K, dtype=torch.float64, device="cuda")
+    en = torch.zeros(K, dtype=torch.float64, device="cuda")
+    ctx.propagate(psi, 2, nrm, en, P.NO_CHECK)  # warm-up
+    psi = torch.from_numpy(psi0).cuda()
+    t = timed(torch, lambda: ctx.propagate(psi, K, nrm, en, P.NO_CHECK))
+    mask = torch.from_numpy((x > 0).astype(np.uint8)).cuda()
+    T = float(ctx.region_sum(psi, mask).item())
+    nr, e = nrm.cpu().numpy(), en.cpu().numpy()
+    iters = K * M
+    return dict(workload="double_well_1d_N4096", M=M, steps=K, seconds=t,
+                orders_per_s=iters / t, us_per_order=t / iters * 1e6, transmission_x_gt_0=T,
+                norm_drift=float(np.abs(nr - nr[0]).max()),
+                energy_rel_drift=float(np.abs(e - e[0]).max() / abs(e[0])),
+                bound="one workgroup: barrier latency + one CU's fp64 rate")
+
+
+def bench_holstein(torch, P, K):
+    p = W.HOLSTEIN.params
+    out = {}
+    for g2 in p["g2"]:
+        ctx = P.Context()
+        ctx.holstein(p["L"], p["nph"], p["t"], p["w0"], np.sqrt(g2), 0.0, p["periodic"])
+        lo, hi = ctx.gershgorin()
+        ctx.set_bounds(lo, hi, 0.01)
+        M = ctx.plan(p["dt"])
+        n = ctx.n
+        nconf = n // p["L"]
+        psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
+        ctx.propagate(psi, 5, None, None, P.NO_CHECK)
+        psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
+        t = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
+        ms_iter, kname = ctx.time_recursion_kernel(100)
+        nnz_row = 4.0
+        bytes_row = CSR_VEC_BYTES + nnz_row * CSR_NNZ_BYTES + CSR_ROW_BYTES
+        n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
+        out[f"g2={g2}"] = dict(n=n, M=M, steps=K, seconds=t, hv_per_s=K * M / t,
+                               kernel=kname, kernel_ms=ms_iter,
+                               kernel_GBs=bytes_row * n / (ms_iter * 1e-3) / 1e9,
+                               bytes_per_row_order=bytes_row,
+                               total_phonons=float(nph_i.sum()), electron_density_sum=float(n_i.sum()))
+        ctx.close()
+    return out
+
+
+def bench_sweep(torch, P, sizes):
+    res = []
+    for width, length in sizes:
+        ctx, eps_d, psi, M = ribbon_context(torch, P, width, length, 0.5, 1)
+        ms, kname = ctx.time_recursion_kernel(50)
+        n = width * length
+        res.append(dict(sites=n, shape=f"{width}x{length}", kernel_ms=ms,
+                        GBs=STENCIL_BYTES * n / (ms * 1e-3) / 1e9))
+        ctx.close()
+        del eps_d, psi
+        torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(target_seconds=12.0):
+    """The serial oracle on the first steps of the headline workload."""
+    import oracle as O
+    p = W.GRAPHENE.params
+    eps, psi0 = W.ribbon_inputs(p["width"], p["length"], p["W"], p["seed"], 20.0, 1.0)
+    H = O.honeycomb(p["width"], p["length"], eps, edge=p["edge"])
+    lo, hi = H.gershgorin()
+    plan = O.Plan(lo, hi, p["dt"])
+    t0 = time.perf_counter()
+    O.propagate(H, plan, psi0, 1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, int(target_seconds / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    O.propagate(H, plan, psi0, steps)
+    t = time.perf_counter() - t0
+    cpu = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=steps * plan.M / t, unit="H·v/s", cores=1, kind="oracle",
+                sample=f"{steps} time steps (M={plan.M}) of the 128x8192 zigzag ribbon, "
+                       f"serial C oracle, {t:.1f} s; host CPU: {cpu}")
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--sections", default="main,double_well,holstein,sweep,cpu")
+    ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the design notes for how the propagation would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0907_3022_amd as P
+    P.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    sections = set(args.sections.split(","))
+
+    if args.mode == "auto":
+        mode_name, mode_flags = bench_mode_choice(torch, P)
+    else:
+        mode_name, mode_flags = args.mode, (P.GRAPH if args.mode == "graph" else 0)
+
+    log(f"[bench] main: zigzag ribbon 128x8192, {args.steps} steps, warmup {args.warmup}, mode {mode_name}")
+    r = bench_main(torch, P, args.steps, args.warmup, mode_flags)
+    hv = args.steps * r["M"]
+    value = hv / r["seconds"] if r["seconds"] > 0 else 0.0
+    achieved = STENCIL_BYTES * r["n"] / (r["ms_iter"] * 1e-3) / 1e9
+    traffic = traffic_record(r["kernel"])
+    line = {
+        "metric": "H·v Chebyshev steps/s + achieved HBM GB/s; batched & adjoint vs plain",
+        "value": value,
+        "unit": "H·v/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["seconds"] / max(args.steps, 1) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "zigzag_ribbon_128x8192", "sites": r["n"], "disorder_W": 0.5,
+                   "dt": 1.0, "chebyshev_order": r["M"], "time_steps": args.steps,
+                   "launch_mode": mode_name, "complex128": True},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": r["kernel"], "kernel_ms_per_launch": r["ms_iter"],
+                     "algorithmic_bytes_per_launch": STENCIL_BYTES * r["n"]},
+        "time_steps_per_s": args.steps / r["seconds"] if r["seconds"] > 0 else 0.0,
+        "step_GBs": STENCIL_BYTES * r["n"] * hv / r["seconds"] / 1e9 if r["seconds"] > 0 else 0.0,
+        "norm_drift": r["norm_drift"],
+    }
+    r["ctx"].close()
+    extra = {}
+    if "double_well" in sections:
+        log("[bench] double well N=4096, 200 steps")
+        extra["double_well"] = bench_double_well(torch, P, W.DOUBLE_WELL.params["K"])
+    if "holstein" in sections:
+        log("[bench] Holstein ring L=10, N_ph<=10, 500 steps")
+        extra["holstein"] = bench_holstein(torch, P, W.HOLSTEIN.params["K"])
+    if "sweep" in sections:
+        log("[bench] ribbon size sweep")
+        extra["sweep"] = bench_sweep(torch, P, [(128, 8192), (256, 16384), (512, 32768), (1024, 65536)])
+    if "cpu" in sections:
+        log("[bench] CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline()
+    else:
+        line["cpu_baseline"] = None
+    line["extra"] = extra
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
