@@ -194,6 +194,104 @@ def bench_sweep(torch, P, sizes):
     return res
 
 
+def bench_batched(torch, P, K, seq_steps=10):
+    """256 uneven ribbons: one batched propagation vs the same systems one by one."""
+    p = W.BATCHED.params
+    descs = W.batched_ribbons(p["nsys"], p["seed_base"])
+    systems, inputs = [], []
+    probe = P.Context()
+    for d in descs:
+        eps, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        eps_d = torch.from_numpy(eps).cuda()
+        probe.honeycomb(d.width, d.length, eps_d)
+        lo, hi = probe.gershgorin()
+        systems.append(dict(width=d.width, length=d.length, eps=eps_d,
+                            psi=torch.from_numpy(psi0).cuda(), emin=lo, emax=hi))
+        inputs.append(psi0)
+    probe.close()
+    ctx = P.Context()
+    ctx.batch_create(systems, p["dt"])
+    Ms = ctx.batch_info()
+    t0 = time.perf_counter()
+    best = ctx.batch_autotune(os.path.join(ROOT, "gpurun_out", "batch_tune.txt")
+                              if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    tune_s = time.perf_counter() - t0
+    site_orders = float(sum(s["width"] * s["length"] * int(M) for s, M in zip(systems, Ms)))
+    ctx.batch_propagate(2, P.GRAPH | P.NO_CHECK)  # warm-up
+    t = timed(torch, lambda: ctx.batch_propagate(K, P.GRAPH))
+    # the same systems one after another through the single-system path
+    one = P.Context()
+    seq_t = 0.0
+    for s in systems:
+        one.honeycomb(s["width"], s["length"], s["eps"])
+        one.set_bounds(s["emin"], s["emax"])
+        one.plan(p["dt"])
+        one.propagate(s["psi"], 1, None, None, P.NO_CHECK)
+        seq_t += timed(torch, lambda: one.propagate(s["psi"], seq_steps, None, None, P.NO_CHECK))
+    one.close()
+    ctx.close()
+    batched_rate = site_orders * K / t
+    seq_rate = site_orders * seq_steps / seq_t
+    return dict(workload="batched_256_ribbons", systems=len(systems),
+                sites=int(sum(s["width"] * s["length"] for s in systems)),
+                M_min=int(Ms.min()), M_max=int(Ms.max()), steps=K, seconds=t,
+                schedule=dict(mode=["levels", "persistent"][best[0]], tile=best[1], block=best[2],
+                              wg_per_cu=best[3]), autotune_seconds=tune_s,
+                site_orders_per_s=batched_rate, GBs=STENCIL_BYTES * batched_rate / 1e9,
+                sequential_site_orders_per_s=seq_rate, sequential_steps=seq_steps,
+                speedup_vs_sequential=batched_rate / seq_rate)
+
+
+def bench_adjoint(torch, P, K):
+    """dL/dV of the transmitted probability: backward time vs plain forward time."""
+    p = W.ADJOINT.params
+    out = {}
+    cases = [("ribbon_256x4096", "honeycomb"), ("chain_65536", "chain")]
+    for name, kind in cases:
+        ctx = P.Context()
+        if kind == "honeycomb":
+            V, psi0 = W.ribbon_inputs(p["width"], p["length"], p["W"], 0)
+            mask = W.right_half_mask_ribbon(p["width"], p["length"])
+            Vd = torch.from_numpy(V).cuda()
+            ctx.honeycomb(p["width"], p["length"], Vd)
+        else:
+            x, dx, V, psi0 = W.double_well_inputs(p["n1d"])
+            mask = (x > 0).astype(np.float64)
+            Vd = torch.from_numpy(V).cuda()
+            ctx.chain1d(Vd, dx)
+        lo, hi = ctx.gershgorin()
+        ctx.set_bounds(lo, hi)
+        a = 0.5 * 1.01 * (hi - lo)
+        M = ctx.plan(30.5 / a)
+        ctx.reserve_adjoint(K, P.ADJ_STEP)
+        psi = torch.from_numpy(psi0).cuda()
+        ctx.propagate(psi, 2, None, None, P.NO_CHECK)  # warm-up
+        psi.copy_(torch.from_numpy(psi0).cuda())
+        t_plain = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
+        psi.copy_(torch.from_numpy(psi0).cuda())
+        t_fwd = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK | P.KEEP_CHECKPOINTS))
+        m = torch.from_numpy(mask).cuda()
+        gbar = (2.0 * m * psi).contiguous()
+        dV = torch.zeros_like(Vd)
+        t_bwd = timed(torch, lambda: ctx.adjoint(gbar, dV))
+        # memory-lean schedule on the same run
+        ctx.reserve_adjoint(K, P.ADJ_SQRTM)
+        psi.copy_(torch.from_numpy(psi0).cuda())
+        ctx.propagate(psi, K, None, None, P.NO_CHECK | P.KEEP_CHECKPOINTS)
+        gbar2 = (2.0 * m * psi).contiguous()
+        dV2 = torch.zeros_like(Vd)
+        t_bwd2 = timed(torch, lambda: ctx.adjoint(gbar2, dV2))
+        same = bool(torch.equal(dV, dV2))
+        out[name] = dict(n=int(Vd.numel()), M=M, steps=K, forward_s=t_plain,
+                         forward_with_checkpoints_s=t_fwd, backward_s=t_bwd,
+                         backward_over_forward=t_bwd / t_plain,
+                         backward_sqrtM_s=t_bwd2, backward_sqrtM_over_forward=t_bwd2 / t_plain,
+                         schedules_agree_bitwise=same,
+                         transmission=float((m * psi.abs() ** 2).sum().item()))
+        ctx.close()
+    return out
+
+
 def cpu_baseline(target_seconds=12.0):
     """The serial oracle on the first steps of the headline workload."""
     import oracle as O
@@ -228,7 +326,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--sections", default="main,double_well,holstein,sweep,cpu")
+    ap.add_argument("--sections", default="main,double_well,holstein,batched,adjoint,sweep,cpu")
     ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -284,6 +382,12 @@ def main():
     if "holstein" in sections:
         log("[bench] Holstein ring L=10, N_ph<=10, 500 steps")
         extra["holstein"] = bench_holstein(torch, P, W.HOLSTEIN.params["K"])
+    if "batched" in sections:
+        log("[bench] batched 256 ribbons, 200 steps")
+        extra["batched"] = bench_batched(torch, P, W.BATCHED.params["K"])
+    if "adjoint" in sections:
+        log("[bench] adjoint, 100 steps, order ~64")
+        extra["adjoint"] = bench_adjoint(torch, P, W.ADJOINT.params["K"])
     if "sweep" in sections:
         log("[bench] ribbon size sweep")
         extra["sweep"] = bench_sweep(torch, P, [(128, 8192), (256, 16384), (512, 32768), (1024, 65536)])

@@ -14,3 +14,11 @@ __all__ = [
     "ZIGZAG", "ARMCHAIR", "KEEP_CHECKPOINTS", "NO_CHECK", "GRAPH", "NO_PERSISTENT",
     "SCHED_LEVELS", "SCHED_PERSISTENT", "ADJ_STEP", "ADJ_SQRTM",
 ]
+
+
+def __getattr__(name):
+    # torch is imported only when the autograd wrapper is used
+    if name in ("ChebPropagate", "Propagator"):
+        from . import autograd
+        return getattr(autograd, name)
+    raise AttributeError(name)

@@ -1,41 +1,468 @@
-// Batched propagation of many independent ribbons (placeholder until the
-// batched kernels land).
-#include <string>
+// Host side of the batched ribbon path: per-system plans, schedule tables,
+// hipGraph capture of step pairs, and the autotuner that times candidate
+// schedules on the real batch.
+#include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "batch_internal.h"
 #include "internal.h"
 
 namespace chebtd {
 int fail(Ctx *c, int code, const std::string &msg);
-struct BatchState {};
+int hip_fail(Ctx *c, hipError_t e, const char *what);
+int ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what);
+void release(DevBuf &b);
+
+struct BatchState {
+    int nsys = 0;
+    double dt = 0.0;
+    std::vector<SysDev> sys;       // indexed by system id
+    std::vector<int> M;            // order per system
+    std::vector<int64_t> nsites;   // sites per system
+    std::vector<int32_t> order;    // system ids by M descending
+    std::vector<double> gamma;     // concatenated weights (interleaved)
+    DevBuf sys_dev, gamma_dev, work;
+    // schedule
+    int mode = CHEBTD_SCHED_LEVELS, tile = 2048, block = 256, wg_per_cu = 2;
+    int nlevels = 1;
+    std::vector<int64_t> level_blocks;  // blocks launched at each level
+    DevBuf blk_sys, blk_tile, q_level_off, q_level_active, q_tile_prefix, q_order;
+    QueueDev q{};
+    int64_t nblocks = 0;
+    DevBuf head, done, flag;
+    int64_t spin_limit = (int64_t)1 << 24;
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+static void drop_graph(BatchState *b)
+{
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+}
+
 void batch_destroy(Ctx *c)
 {
-    delete c->batch;
+    BatchState *b = c->batch;
+    if (!b) return;
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (DevBuf *d : {&b->sys_dev, &b->gamma_dev, &b->work, &b->blk_sys, &b->blk_tile, &b->q_level_off,
+                      &b->q_level_active, &b->q_tile_prefix, &b->q_order, &b->head, &b->done, &b->flag})
+        release(*d);
+    delete b;
     c->batch = nullptr;
 }
+
+static int upload(Ctx *c, DevBuf &d, const void *src, size_t bytes, const char *what)
+{
+    int rc = ensure(c, d, std::max<size_t>(bytes, 8), what);
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice);
+    return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, what);
+}
+
+// Rebuild the tile tables for the current tile size.
+static int build_tables(Ctx *c, BatchState *b)
+{
+    const int ns = b->nsys;
+    std::vector<int64_t> tiles(ns);
+    for (int s = 0; s < ns; ++s) {
+        tiles[s] = (b->nsites[s] + b->tile - 1) / b->tile;
+        if (tiles[s] > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many tiles in one system");
+        b->sys[s].ntiles = (int32_t)tiles[s];
+    }
+    int Mmax = 0;
+    for (int s = 0; s < ns; ++s) Mmax = std::max(Mmax, b->M[s]);
+    b->nlevels = std::max(1, Mmax);
+    std::vector<int64_t> prefix(ns + 1, 0);
+    for (int j = 0; j < ns; ++j) prefix[j + 1] = prefix[j] + tiles[b->order[j]];
+    b->nblocks = prefix[ns];
+    if (b->nblocks > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many tiles");
+    std::vector<int32_t> bsys((size_t)b->nblocks), btile((size_t)b->nblocks);
+    for (int j = 0; j < ns; ++j)
+        for (int64_t t = 0; t < tiles[b->order[j]]; ++t) {
+            bsys[(size_t)(prefix[j] + t)] = b->order[j];
+            btile[(size_t)(prefix[j] + t)] = (int32_t)t;
+        }
+    std::vector<int32_t> active(b->nlevels);
+    std::vector<int64_t> loff(b->nlevels + 1, 0);
+    b->level_blocks.assign(b->nlevels, 0);
+    for (int k = 0; k < b->nlevels; ++k) {
+        int cnt = 0;
+        for (int j = 0; j < ns; ++j)
+            if (k == 0 || b->M[b->order[j]] > k) ++cnt;
+        active[k] = cnt;
+        b->level_blocks[k] = prefix[cnt];
+        loff[k + 1] = loff[k] + prefix[cnt];
+    }
+    int rc;
+    if ((rc = upload(c, b->blk_sys, bsys.data(), bsys.size() * 4, "batch block table")) ||
+        (rc = upload(c, b->blk_tile, btile.data(), btile.size() * 4, "batch tile table")) ||
+        (rc = upload(c, b->q_level_off, loff.data(), loff.size() * 8, "queue levels")) ||
+        (rc = upload(c, b->q_level_active, active.data(), active.size() * 4, "queue active")) ||
+        (rc = upload(c, b->q_tile_prefix, prefix.data(), prefix.size() * 8, "queue prefix")) ||
+        (rc = upload(c, b->q_order, b->order.data(), b->order.size() * 4, "queue order")) ||
+        (rc = upload(c, b->sys_dev, b->sys.data(), b->sys.size() * sizeof(SysDev), "system table")))
+        return rc;
+    b->q.level_off = static_cast<const int64_t *>(b->q_level_off.p);
+    b->q.level_active = static_cast<const int32_t *>(b->q_level_active.p);
+    b->q.tile_prefix = static_cast<const int64_t *>(b->q_tile_prefix.p);
+    b->q.order = static_cast<const int32_t *>(b->q_order.p);
+    b->q.nlevels = b->nlevels;
+    b->q.total = loff[b->nlevels];
+    drop_graph(b);
+    return CHEBTD_OK;
+}
+
+static hipError_t enqueue_step(Ctx *c, BatchState *b, hipStream_t s, int par)
+{
+    const SysDev *sys = static_cast<const SysDev *>(b->sys_dev.p);
+    const double2 *gam = static_cast<const double2 *>(b->gamma_dev.p);
+    if (b->mode == CHEBTD_SCHED_LEVELS) {
+        for (int k = 0; k < b->nlevels; ++k) {
+            hipError_t e = launch_batch_level(s, sys, gam, static_cast<const int32_t *>(b->blk_sys.p),
+                                              static_cast<const int32_t *>(b->blk_tile.p), b->level_blocks[k],
+                                              k, b->tile, par, b->block);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const int64_t grid = std::min<int64_t>((int64_t)c->num_cus * b->wg_per_cu, b->q.total);
+    return launch_batch_persistent(s, sys, gam, b->q, b->tile, par, static_cast<int64_t *>(b->head.p),
+                                   static_cast<int32_t *>(b->done.p), static_cast<int32_t *>(b->flag.p),
+                                   b->nsys, (int)std::max<int64_t>(grid, 1), b->block, b->spin_limit);
+}
+
+static int run_steps(Ctx *c, BatchState *b, int64_t K, bool use_graph)
+{
+    hipStream_t s = c->stream;
+    hipError_t e = hipMemsetAsync(b->flag.p, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return hip_fail(c, e, "batch flag reset");
+    if (use_graph && K >= 2) {
+        if (!b->graph) {
+            if (!b->cap) {
+                e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_fail(c, e, "batch capture stream");
+            }
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) return hip_fail(c, e, "batch capture");
+            hipError_t e1 = enqueue_step(c, b, b->cap, 0);
+            if (e1 == hipSuccess) e1 = enqueue_step(c, b, b->cap, 1);
+            e = hipStreamEndCapture(b->cap, &g);
+            if (e1 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(c, e1, "batch step capture");
+            }
+            if (e != hipSuccess) return hip_fail(c, e, "batch end capture");
+            e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                b->graph = nullptr;
+                return hip_fail(c, e, "batch graph instantiate");
+            }
+        }
+        for (int64_t st = 0; st + 1 < K; st += 2) {
+            e = hipGraphLaunch(b->graph, s);
+            if (e != hipSuccess) return hip_fail(c, e, "batch graph launch");
+        }
+        if (K & 1) {
+            e = enqueue_step(c, b, s, 0);
+            if (e != hipSuccess) return hip_fail(c, e, "batch last step");
+        }
+    } else {
+        for (int64_t st = 0; st < K; ++st) {
+            e = enqueue_step(c, b, s, (int)(st & 1));
+            if (e != hipSuccess) return hip_fail(c, e, "batch step");
+        }
+    }
+    if (K & 1) {
+        e = launch_batch_copy_back(s, static_cast<const SysDev *>(b->sys_dev.p),
+                                   static_cast<const int32_t *>(b->blk_sys.p),
+                                   static_cast<const int32_t *>(b->blk_tile.p), b->nblocks, b->tile, b->block);
+        if (e != hipSuccess) return hip_fail(c, e, "batch copy back");
+    }
+    return CHEBTD_OK;
+}
+
+static int check_timeout(Ctx *c, BatchState *b)
+{
+    hipError_t e = hipMemcpyAsync(c->pinned, b->flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "batch completion");
+    int32_t f = 0;
+    std::memcpy(&f, c->pinned, sizeof(int32_t));
+    if (f)
+        return fail(c, CHEBTD_E_TIMEOUT,
+                    "batch: a persistent workgroup's dependency wait ran out; results are invalid");
+    return CHEBTD_OK;
+}
+
+static uint64_t shape_key(const Ctx *c, const BatchState *b)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)b->nsys);
+    mix((uint64_t)c->num_cus);
+    for (int s = 0; s < b->nsys; ++s) {
+        mix((uint64_t)b->sys[s].W);
+        mix((uint64_t)b->sys[s].L);
+        mix((uint64_t)b->sys[s].edge);
+        mix((uint64_t)b->M[s]);
+    }
+    return h;
+}
+
 }  // namespace chebtd
 
 using namespace chebtd;
 struct chebtd_ctx : public Ctx {};
 
 extern "C" {
-int chebtd_batch_create(chebtd_ctx *ctx, int, const chebtd_sys_desc *, double, double, double)
+
+int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs, double dt, double alpha,
+                        double tol)
 {
-    return fail(ctx, CHEBTD_E_STATE, "batched propagation is not available yet");
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (nsys < 1 || !descs || !(dt >= 0.0) || !std::isfinite(dt) || !(alpha >= 0.0))
+        return fail(c, CHEBTD_E_ARG, "chebtd_batch_create: need nsys >= 1, descriptors, dt >= 0, alpha >= 0");
+    if (!(tol > 0.0)) tol = 1e-15;
+    for (int s = 0; s < nsys; ++s) {
+        const chebtd_sys_desc &d = descs[s];
+        if (d.width < 1 || d.length < 1 || d.width * d.length >= ((int64_t)1 << 31) || !d.eps_dev ||
+            !d.psi_dev || (d.edge != CHEBTD_ZIGZAG && d.edge != CHEBTD_ARMCHAIR) || !(d.emax > d.emin) ||
+            !std::isfinite(d.emin) || !std::isfinite(d.emax) || !std::isfinite(d.t_hop))
+            return fail(c, CHEBTD_E_ARG, "chebtd_batch_create: bad descriptor " + std::to_string(s));
+    }
+    batch_destroy(c);
+    BatchState *b = new (std::nothrow) BatchState();
+    if (!b) return fail(c, CHEBTD_E_OOM, "batch state");
+    c->batch = b;
+    b->nsys = nsys;
+    b->dt = dt;
+    b->sys.resize(nsys);
+    b->M.resize(nsys);
+    b->nsites.resize(nsys);
+    int64_t total = 0;
+    std::vector<double> g;
+    for (int s = 0; s < nsys; ++s) {
+        const chebtd_sys_desc &d = descs[s];
+        double a = 0, bb = 0;
+        shift_scale(d.emin, d.emax, alpha, &a, &bb);
+        const int M = truncation_order(a * dt, tol);
+        if (M < 0) {
+            batch_destroy(c);
+            return fail(c, CHEBTD_E_ARG, "chebtd_batch_create: bad a*dt for system " + std::to_string(s));
+        }
+        step_weights(a, bb, dt, M, g);
+        SysDev &sd = b->sys[s];
+        sd.eps = d.eps_dev;
+        sd.psi = reinterpret_cast<double2 *>(d.psi_dev);
+        sd.W = (int32_t)d.width;
+        sd.L = (int32_t)d.length;
+        sd.edge = d.edge;
+        sd.M = M;
+        sd.b = bb;
+        sd.s2 = 2.0 / a;
+        sd.off2 = -2.0 * d.t_hop / a;
+        sd.gamma_off = (int64_t)b->gamma.size() / 2;
+        b->gamma.insert(b->gamma.end(), g.begin(), g.end());
+        b->M[s] = M;
+        b->nsites[s] = d.width * d.length;
+        total += b->nsites[s];
+    }
+    int rc = ensure(c, b->work, (size_t)total * 2 * sizeof(double2), "batch work vectors");
+    if (rc) {
+        batch_destroy(c);
+        return rc;
+    }
+    double2 *w = static_cast<double2 *>(b->work.p);
+    for (int s = 0; s < nsys; ++s) {
+        b->sys[s].A = w;
+        b->sys[s].B = w + b->nsites[s];
+        w += 2 * b->nsites[s];
+    }
+    b->order.resize(nsys);
+    for (int s = 0; s < nsys; ++s) b->order[s] = s;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) { return b->M[x] > b->M[y]; });
+    if ((rc = upload(c, b->gamma_dev, b->gamma.data(), b->gamma.size() * sizeof(double), "batch weights")) ||
+        (rc = ensure(c, b->head, sizeof(int64_t), "queue head")) ||
+        (rc = ensure(c, b->done, (size_t)nsys * sizeof(int32_t), "completion counters")) ||
+        (rc = ensure(c, b->flag, sizeof(int32_t), "timeout flag")) || (rc = build_tables(c, b))) {
+        batch_destroy(c);
+        return rc;
+    }
+    return CHEBTD_OK;
 }
-int chebtd_batch_set_schedule(chebtd_ctx *ctx, int, int, int, int)
+
+int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int block, int wg_per_cu)
 {
-    return fail(ctx, CHEBTD_E_STATE, "batched propagation is not available yet");
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    BatchState *b = c->batch;
+    if (!b) return fail(c, CHEBTD_E_STATE, "chebtd_batch_set_schedule: no batch");
+    if ((mode != CHEBTD_SCHED_LEVELS && mode != CHEBTD_SCHED_PERSISTENT) || block < 64 || block > 1024 ||
+        block % 64 || tile_rows < block || tile_rows % block || wg_per_cu < 1 || wg_per_cu > 8)
+        return fail(c, CHEBTD_E_ARG,
+                    "chebtd_batch_set_schedule: need a known mode, block in [64,1024] (multiple of 64), "
+                    "tile_rows a multiple of block, 1 <= wg_per_cu <= 8");
+    const bool retile = tile_rows != b->tile;
+    b->mode = mode;
+    b->tile = tile_rows;
+    b->block = block;
+    b->wg_per_cu = wg_per_cu;
+    drop_graph(b);
+    return retile ? build_tables(c, b) : CHEBTD_OK;
 }
-int chebtd_batch_autotune(chebtd_ctx *ctx, const char *, int *)
+
+int chebtd_batch_propagate(chebtd_ctx *ctx, int64_t K, unsigned flags)
 {
-    return fail(ctx, CHEBTD_E_STATE, "batched propagation is not available yet");
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    BatchState *b = c->batch;
+    if (!b) return fail(c, CHEBTD_E_STATE, "chebtd_batch_propagate: no batch");
+    if (K < 0) return fail(c, CHEBTD_E_ARG, "chebtd_batch_propagate: K < 0");
+    if (K == 0) return CHEBTD_OK;
+    int rc = run_steps(c, b, K, (flags & CHEBTD_GRAPH) != 0);
+    if (rc) return rc;
+    if (flags & CHEBTD_NO_CHECK) return CHEBTD_OK;
+    return check_timeout(c, b);
 }
-int chebtd_batch_propagate(chebtd_ctx *ctx, int64_t, unsigned)
+
+int chebtd_batch_info(const chebtd_ctx *ctx, int *nsys, int *M_host)
 {
-    return fail(ctx, CHEBTD_E_STATE, "batched propagation is not available yet");
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    const Ctx *c = static_cast<const Ctx *>(ctx);
+    if (!c->batch) return fail(const_cast<Ctx *>(c), CHEBTD_E_STATE, "chebtd_batch_info: no batch");
+    if (nsys) *nsys = c->batch->nsys;
+    if (M_host)
+        for (int s = 0; s < c->batch->nsys; ++s) M_host[s] = c->batch->M[s];
+    return CHEBTD_OK;
 }
-int chebtd_batch_info(const chebtd_ctx *ctx, int *, int *)
+
+int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out)
 {
-    return fail(const_cast<chebtd_ctx *>(ctx), CHEBTD_E_STATE, "batched propagation is not available yet");
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    BatchState *b = c->batch;
+    if (!b) return fail(c, CHEBTD_E_STATE, "chebtd_batch_autotune: no batch");
+    const uint64_t key = shape_key(c, b);
+    char keystr[32];
+    std::snprintf(keystr, sizeof keystr, "%016llx", (unsigned long long)key);
+    int best[4] = {-1, 0, 0, 0};
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int m, t, bl, w;
+            if ((ls >> k >> m >> t >> bl >> w) && k == keystr) {
+                best[0] = m;
+                best[1] = t;
+                best[2] = bl;
+                best[3] = w;
+            }
+        }
+    }
+    if (best[0] < 0) {
+        // save every system's state, time each candidate on the real batch, restore
+        int64_t total = 0;
+        for (int s = 0; s < b->nsys; ++s) total += b->nsites[s];
+        DevBuf save;
+        int rc = ensure(c, save, (size_t)total * sizeof(double2), "autotune backup");
+        if (rc) return rc;
+        hipStream_t s = c->stream;
+        auto copy_all = [&](bool to_save) -> hipError_t {
+            double2 *p = static_cast<double2 *>(save.p);
+            for (int q = 0; q < b->nsys; ++q) {
+                const size_t bytes = (size_t)b->nsites[q] * sizeof(double2);
+                hipError_t e = to_save ? hipMemcpyAsync(p, b->sys[q].psi, bytes, hipMemcpyDeviceToDevice, s)
+                                       : hipMemcpyAsync(b->sys[q].psi, p, bytes, hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) return e;
+                p += b->nsites[q];
+            }
+            return hipSuccess;
+        };
+        hipError_t e = copy_all(true);
+        if (e != hipSuccess) {
+            release(save);
+            return hip_fail(c, e, "autotune backup");
+        }
+        struct Cand {
+            int mode, tile, block, wg;
+        };
+        std::vector<Cand> cands;
+        for (int tile : {1024, 2048, 4096, 8192})
+            for (int block : {256, 512}) {
+                if (tile % block) continue;
+                cands.push_back({CHEBTD_SCHED_LEVELS, tile, block, 1});
+                for (int wg : {2, 4}) cands.push_back({CHEBTD_SCHED_PERSISTENT, tile, block, wg});
+            }
+        double best_ms = 1e300;
+        for (const Cand &cd : cands) {
+            rc = chebtd_batch_set_schedule(ctx, cd.mode, cd.tile, cd.block, cd.wg);
+            if (rc) break;
+            rc = run_steps(c, b, 1, false);  // warm-up
+            if (!rc) rc = check_timeout(c, b);
+            if (rc) break;
+            e = hipEventRecord(c->ev_a, s);
+            if (e == hipSuccess) rc = run_steps(c, b, 2, false);
+            if (e == hipSuccess && !rc) e = hipEventRecord(c->ev_b, s);
+            if (e == hipSuccess && !rc) e = hipEventSynchronize(c->ev_b);
+            float ms = 0.f;
+            if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, c->ev_a, c->ev_b);
+            if (e != hipSuccess) {
+                rc = hip_fail(c, e, "autotune timing");
+                break;
+            }
+            if (!rc) rc = check_timeout(c, b);
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best[0] = cd.mode;
+                best[1] = cd.tile;
+                best[2] = cd.block;
+                best[3] = cd.wg;
+            }
+            e = copy_all(false);
+            if (e != hipSuccess) {
+                rc = hip_fail(c, e, "autotune restore");
+                break;
+            }
+        }
+        if (!rc) {
+            e = copy_all(false);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) rc = hip_fail(c, e, "autotune restore");
+        }
+        release(save);
+        if (rc) return rc;
+        if (cache_path) {
+            std::ofstream out(cache_path, std::ios::app);
+            out << keystr << ' ' << best[0] << ' ' << best[1] << ' ' << best[2] << ' ' << best[3] << '\n';
+        }
+    }
+    int rc = chebtd_batch_set_schedule(ctx, best[0], best[1], best[2], best[3]);
+    if (rc) return rc;
+    if (best_out)
+        for (int i = 0; i < 4; ++i) best_out[i] = best[i];
+    return CHEBTD_OK;
 }
-}
+
+}  // extern "C"

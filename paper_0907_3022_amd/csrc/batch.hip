@@ -1,0 +1,232 @@
+// Batched propagation of many independent honeycomb ribbons of uneven size
+// (the disorder-ensemble use of Sect. 3.2 of arXiv:0907.3022): every system
+// has its own grid, on-site energies, spectral scale (a, b), order M and
+// Bessel weights, and each system's sites are cut into tiles of `tile`
+// consecutive site indices.
+//
+// Two schedules share the per-tile work:
+//  * levels:     one launch per recursion level; block b takes tile b of the
+//                systems still active at that level (systems are sorted by
+//                M, descending, so the active ones form a prefix).
+//  * persistent: one launch per time step; resident workgroups pull
+//                (level, system, tile) items from a queue ordered level by
+//                level.  Before a tile of level k runs, every tile of level
+//                k-1 of the same system must be done; per-system completion
+//                counters (release/acquire at agent scope) carry that
+//                dependency.  The wait is bounded: after a spin limit the
+//                kernel records a timeout, finishes the queue without
+//                computing and exits, so every wave always terminates.
+//                Items are dequeued in level order and a dequeued item's
+//                dependencies were dequeued earlier by running workgroups,
+//                so the earliest unfinished item can always proceed.
+#include <hip/hip_runtime.h>
+
+#include "batch_internal.h"
+#include "device_ops.h"
+
+namespace chebtd {
+
+// site index -> (x, y) walker over one tile
+struct TileWalk {
+    int64_t i, end;
+    int32_t x, y, L;
+    __device__ __forceinline__ void start(int64_t t0, int64_t n, int32_t tile, int32_t Lx)
+    {
+        L = Lx;
+        i = t0 + threadIdx.x;
+        end = t0 + tile < n ? t0 + tile : n;
+        y = (int32_t)(i / L);
+        x = (int32_t)(i - (int64_t)y * L);
+    }
+    __device__ __forceinline__ bool ok() const { return i < end; }
+    __device__ __forceinline__ void next()
+    {
+        i += blockDim.x;
+        x += blockDim.x;
+        while (x >= L) {
+            x -= L;
+            ++y;
+        }
+    }
+};
+
+__device__ __forceinline__ double2 honey_apply2(const SysDev &sd, int64_t i, int32_t x, int32_t y,
+                                                const double2 *v, double2 vi)
+{
+    OpHoney op;
+    op.eps = sd.eps;
+    op.b = sd.b;
+    op.s2 = sd.s2;
+    op.off2 = sd.off2;
+    op.W = sd.W;
+    op.L = sd.L;
+    if (sd.edge == CHEBTD_ZIGZAG) return HoneyRow<CHEBTD_ZIGZAG>::apply2(op, i, x, y, v, vi);
+    return HoneyRow<CHEBTD_ARMCHAIR>::apply2(op, i, x, y, v, vi);
+}
+
+// Level k of one tile of system sd in step parity `par`
+//   k = 0: v1 = H~ psi -> A, acc = g0 psi + g1 v1 -> nxt
+//   k > 0: v_{k+1} = 2 H~ v_k - v_{k-1} over v_{k-1}; acc += g_{k+1} v_{k+1}
+__device__ __forceinline__ void tile_level(const SysDev &sd, const double2 *gamma, int k, int tile_idx,
+                                           int32_t tile, int par)
+{
+    double2 *cur = par ? sd.B : sd.psi;
+    double2 *nxt = par ? sd.psi : sd.B;
+    double2 *A = sd.A;
+    const int64_t n = (int64_t)sd.W * sd.L;
+    TileWalk w;
+    w.start((int64_t)tile_idx * tile, n, tile, sd.L);
+    const double2 *g = gamma + sd.gamma_off;
+    if (k == 0) {
+        const double2 g0 = g[0];
+        const double2 g1 = sd.M >= 1 ? g[1] : make_double2(0.0, 0.0);
+        for (; w.ok(); w.next()) {
+            const double2 vi = cur[w.i];
+            const double2 h = cscale(0.5, honey_apply2(sd, w.i, w.x, w.y, cur, vi));
+            A[w.i] = h;
+            nxt[w.i] = cfma(g1, h, cfma(g0, vi, make_double2(0.0, 0.0)));
+        }
+    } else {
+        const double2 gk = g[k + 1];
+        const double2 *vk = (k & 1) ? A : cur;
+        double2 *vprev = (k & 1) ? cur : A;
+        for (; w.ok(); w.next()) {
+            const double2 vi = vk[w.i];
+            const double2 nv = csub(honey_apply2(sd, w.i, w.x, w.y, vk, vi), vprev[w.i]);
+            vprev[w.i] = nv;
+            nxt[w.i] = cfma(gk, nv, nxt[w.i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// levels schedule
+// ---------------------------------------------------------------------------
+__global__ void k_batch_level(const SysDev *__restrict__ sys, const double2 *__restrict__ gamma,
+                              const int32_t *__restrict__ blk_sys, const int32_t *__restrict__ blk_tile,
+                              int k, int32_t tile, int par)
+{
+    const int32_t s = blk_sys[blockIdx.x];
+    const SysDev sd = sys[s];
+    if (k > 0 && k > sd.M - 1) return;
+    tile_level(sd, gamma, k, blk_tile[blockIdx.x], tile, par);
+}
+
+// ---------------------------------------------------------------------------
+// persistent schedule
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t upper_index(const int64_t *a, int32_t cnt, int64_t v)
+{
+    // largest j in [0, cnt) with a[j] <= v (a ascending, a[0] = 0)
+    int32_t lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_batch_persistent(const SysDev *__restrict__ sys, const double2 *__restrict__ gamma,
+                                   const QueueDev q, int32_t tile, int par, int64_t *queue_head,
+                                   int32_t *done, int32_t *timeout_flag, int64_t spin_limit)
+{
+    __shared__ int64_t s_item;
+    __shared__ int32_t s_k, s_sys, s_tile, s_skip;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = __hip_atomic_fetch_add(queue_head, (int64_t)1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= q.total) break;
+        if (threadIdx.x == 0) {
+            // level k: items [q.level_off[k], q.level_off[k+1])
+            const int32_t k = upper_index(q.level_off, q.nlevels, item);
+            const int64_t r = item - q.level_off[k];
+            // active systems at level k are a prefix of the M-sorted order
+            const int32_t j = upper_index(q.tile_prefix, q.level_active[k], r);
+            const int32_t s = q.order[j];
+            s_k = k;
+            s_sys = s;
+            s_tile = (int32_t)(r - q.tile_prefix[j]);
+            int skip = 0;
+            if (k > 0) {
+                // wait for every tile of level k-1 of system s
+                const int32_t need = k * sys[s].ntiles;
+                int64_t spins = 0;
+                while (__hip_atomic_load(&done[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(timeout_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                        ++spins > spin_limit) {
+                        __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        skip = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            s_skip = skip;
+        }
+        __syncthreads();
+        // make the other tiles' results visible to every thread of the block
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int32_t k = s_k, s = s_sys;
+        if (!s_skip) tile_level(sys[s], gamma, k, s_tile, tile, par);
+        // publish this tile: all stores of the block, then the counter
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&done[s], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void k_batch_reset(int64_t *queue_head, int32_t *done, int32_t nsys)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) queue_head[0] = 0;
+    if (i < nsys) done[i] = 0;
+}
+
+__global__ void k_batch_copy_back(const SysDev *__restrict__ sys, const int32_t *__restrict__ blk_sys,
+                                  const int32_t *__restrict__ blk_tile, int32_t tile)
+{
+    const SysDev sd = sys[blk_sys[blockIdx.x]];
+    const int64_t n = (int64_t)sd.W * sd.L;
+    const int64_t t0 = (int64_t)blk_tile[blockIdx.x] * tile;
+    const int64_t end = t0 + tile < n ? t0 + tile : n;
+    for (int64_t i = t0 + threadIdx.x; i < end; i += blockDim.x) sd.psi[i] = sd.B[i];
+}
+
+hipError_t launch_batch_level(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                              const int32_t *blk_tile, int64_t nblocks, int k, int32_t tile, int par,
+                              int block)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_level, dim3((unsigned)nblocks), dim3(block), 0, s, sys, gamma, blk_sys,
+                       blk_tile, k, tile, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(hipStream_t s, const SysDev *sys, const double2 *gamma, const QueueDev &q,
+                                   int32_t tile, int par, int64_t *queue_head, int32_t *done,
+                                   int32_t *timeout_flag, int nsys, int grid, int block, int64_t spin_limit)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3((nsys + 255) / 256), dim3(256), 0, s, queue_head, done, nsys);
+    hipLaunchKernelGGL(k_batch_persistent, dim3(grid), dim3(block), 0, s, sys, gamma, q, tile, par,
+                       queue_head, done, timeout_flag, spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_copy_back(hipStream_t s, const SysDev *sys, const int32_t *blk_sys,
+                                  const int32_t *blk_tile, int64_t nblocks, int32_t tile, int block)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_copy_back, dim3((unsigned)nblocks), dim3(block), 0, s, sys, blk_sys, blk_tile,
+                       tile);
+    return hipGetLastError();
+}
+
+}  // namespace chebtd

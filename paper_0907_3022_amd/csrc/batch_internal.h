@@ -1,0 +1,42 @@
+// Device-side descriptors of the batched ribbon path (batch.hip/batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace chebtd {
+
+// One ribbon of a batch, as the kernels see it.
+struct SysDev {
+    const double *eps;  // on-site energies
+    double2 *psi;       // caller's state (in/out)
+    double2 *A, *B;     // work vectors: v_1, v_3, ... and the accumulator/state
+    int32_t W, L, edge, M;
+    double b, s2, off2;  // shift, 2/a, -2t/a
+    int64_t gamma_off;   // first weight in the concatenated table
+    int32_t ntiles;
+    int32_t pad;
+};
+
+// Work queue of the persistent schedule (item = level, system, tile).
+struct QueueDev {
+    const int64_t *level_off;    // [nlevels + 1]
+    const int32_t *level_active; // [nlevels]: systems active at a level (prefix of order)
+    const int64_t *tile_prefix;  // [nsys + 1]: tiles before the j-th system of order
+    const int32_t *order;        // [nsys]: systems sorted by M, descending
+    int32_t nlevels;
+    int32_t pad;
+    int64_t total;
+};
+
+hipError_t launch_batch_level(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                              const int32_t *blk_tile, int64_t nblocks, int k, int32_t tile, int par,
+                              int block);
+hipError_t launch_batch_persistent(hipStream_t s, const SysDev *sys, const double2 *gamma, const QueueDev &q,
+                                   int32_t tile, int par, int64_t *queue_head, int32_t *done,
+                                   int32_t *timeout_flag, int nsys, int grid, int block, int64_t spin_limit);
+hipError_t launch_batch_copy_back(hipStream_t s, const SysDev *sys, const int32_t *blk_sys,
+                                  const int32_t *blk_tile, int64_t nblocks, int32_t tile, int block);
+
+}  // namespace chebtd

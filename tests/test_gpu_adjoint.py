@@ -1,0 +1,169 @@
+"""GPU adjoint (dL/dV) against the CPU oracle's reverse mode and against
+central finite differences of the GPU forward pass."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+@pytest.fixture(scope="module")
+def cheb():
+    import paper_0907_3022_amd as P
+    P.load_library()
+    return P
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def chain_inputs(n, a=0.05, b=5.0):
+    x, dx, V, psi0 = W.double_well_inputs(n, -20.0, 20.0, a, b, -5.0, 1.0, 1.0)
+    mask = (x > 0).astype(np.float64)
+    return dx, V, psi0, mask
+
+
+def ribbon_inputs(width, length, Wd=0.5, seed=0):
+    eps, psi0 = W.ribbon_inputs(width, length, Wd, seed)
+    return eps, psi0, W.right_half_mask_ribbon(width, length)
+
+
+def gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, mode):
+    prop = cheb.Propagator(kind, dt, K, bounds, adjoint_mode=mode, **geom)
+    Vt = torch.from_numpy(V.copy()).cuda().requires_grad_(True)
+    p0 = torch.from_numpy(psi0.copy()).cuda().requires_grad_(True)
+    say(f"[gpu] adjoint {kind} n={V.size} K={K} mode={mode}")
+    psi = cheb.ChebPropagate.apply(Vt, p0, prop)
+    m = torch.from_numpy(mask).cuda()
+    L = (m * psi.abs() ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    return float(L.item()), Vt.grad.cpu().numpy(), p0.grad.cpu().numpy(), prop
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", ["chain", "zigzag", "armchair", "chain_large"])
+def test_adjoint_matches_oracle(torch, cheb, case, mode):
+    if case.startswith("chain"):
+        n = 300 if case == "chain" else 9001
+        dx, V, psi0, mask = chain_inputs(n)
+        H = O.chain1d(V, dx)
+        geom = dict(dx=dx)
+        kind = "chain"
+        lo, hi = H.gershgorin()
+        dt = 30.0 / (0.5 * 1.01 * (hi - lo))   # order ~ 64
+    else:
+        w, l = 8, 60
+        V, psi0, mask = ribbon_inputs(w, l)
+        H = O.honeycomb(w, l, V, edge=case)
+        geom = dict(width=w, length=l, edge=case)
+        kind = "honeycomb"
+        lo, hi = H.gershgorin()
+        dt = 2.5
+    K = 4
+    Lg, g, u0, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, (lo, hi), dt, K, mode)
+    plan = O.Plan(lo, hi, dt)
+    assert prop.M == plan.M
+    Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
+    assert Lg == pytest.approx(Lr, rel=1e-10)
+    assert rel_l2(g, gr) <= 1e-8
+    assert rel_l2(u0, ur) <= 1e-10
+
+
+def test_adjoint_modes_agree_bitwise_free(torch, cheb):
+    # the two memory schedules rebuild the same v_k by the same kernels
+    w, l = 16, 200
+    V, psi0, mask = ribbon_inputs(w, l)
+    H = O.honeycomb(w, l, V)
+    b = H.gershgorin()
+    _, g0, u0, _ = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask, b, 9.4, 3, 0)
+    _, g1, u1, _ = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask, b, 9.4, 3, 1)
+    np.testing.assert_array_equal(g0, g1)
+    np.testing.assert_array_equal(u0, u1)
+
+
+def _fd_check(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, sites, h, rtol_floor):
+    Lg, g, _, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, 0)
+    Vd = torch.from_numpy(V.copy()).cuda()
+    m = torch.from_numpy(mask).cuda()
+    p0 = torch.from_numpy(psi0).cuda()
+
+    def loss(Vx):
+        with torch.no_grad():
+            psi = prop.forward(Vx, p0, keep=False)
+            return float((m * psi.abs() ** 2).sum().item())
+
+    fd = []
+    for i in sites:
+        Vd[i] += h
+        Lp = loss(Vd)
+        Vd[i] -= 2 * h
+        Lm = loss(Vd)
+        Vd[i] += h
+        fd.append((Lp - Lm) / (2 * h))
+    fd = np.array(fd)
+    ga = g[sites]
+    say(f"[gpu] FD {kind}: L={Lg:.6e} max|g|={np.abs(g).max():.3e} max|g-fd|={np.abs(ga - fd).max():.3e}")
+    assert np.all(np.abs(ga - fd) <= rtol_floor * np.abs(g).max() + 1e-13)
+    return g
+
+
+def test_adjoint_config_ribbon_256x4096_fd(torch, cheb):
+    p = W.ADJOINT.params
+    w, l = p["width"], p["length"]
+    V, psi0, mask = ribbon_inputs(w, l, p["W"], 0)
+    ctx = cheb.Context()
+    ctx.honeycomb(w, l, torch.from_numpy(V).cuda())
+    lo, hi = ctx.gershgorin()
+    a = 0.5 * 1.01 * (hi - lo)
+    dt = 30.5 / a
+    # sites inside the packet's reach
+    sites = W.fd_sites(w * l, p["fd_sites"], 77, candidates=np.arange(w * l)[(np.tile(np.arange(l), w) > l // 8)])
+    g = _fd_check(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask, (lo, hi), dt,
+                  p["K"], sites, p["h"], 1e-5)
+    assert np.abs(g).max() > 0
+
+
+def test_adjoint_config_chain_65536_fd(torch, cheb):
+    p = W.ADJOINT.params
+    dx, V, psi0, mask = chain_inputs(p["n1d"])
+    ctx = cheb.Context()
+    ctx.chain1d(torch.from_numpy(V).cuda(), dx)
+    lo, hi = ctx.gershgorin()
+    dt = 30.5 / (0.5 * 1.01 * (hi - lo))
+    x = np.linspace(-20, 20, p["n1d"])
+    sites = W.fd_sites(p["n1d"], p["fd_sites"], 78, candidates=np.nonzero(np.abs(x) < 1.0)[0])
+    _fd_check(torch, cheb, "chain", dict(dx=dx), V, psi0, mask, (lo, hi), dt, p["K"], sites, p["h"], 1e-4)
+
+
+def test_adjoint_full_size_vs_oracle_short(torch, cheb):
+    # full 256 x 4096 ribbon, order ~64, 2 steps: GPU reverse sweep vs the oracle's
+    p = W.ADJOINT.params
+    w, l = p["width"], p["length"]
+    V, psi0, mask = ribbon_inputs(w, l, p["W"], 0)
+    H = O.honeycomb(w, l, V)
+    lo, hi = H.gershgorin()
+    dt = 30.5 / (0.5 * 1.01 * (hi - lo))
+    Lg, g, u0, prop = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask,
+                                  (lo, hi), dt, 2, 0)
+    plan = O.Plan(lo, hi, dt)
+    assert prop.M == plan.M and 60 <= plan.M <= 70
+    Lr, gr, ur = O.adjoint(H, plan, psi0, 2, mask)
+    assert rel_l2(g, gr) <= 1e-8
+    assert rel_l2(u0, ur) <= 1e-10

@@ -1,0 +1,167 @@
+"""Batched ribbons on the GPU: both schedules, graph replay and the
+autotuner against the CPU oracle (system by system) and against the
+single-system path (bit for bit: the per-site arithmetic is the same)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+@pytest.fixture(scope="module")
+def cheb():
+    import paper_0907_3022_amd as P
+    P.load_library()
+    return P
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make_systems(specs, torch):
+    """specs: (width, length, W, seed, edge); bounds from the oracle's discs."""
+    out = []
+    for (w, l, Wd, seed, edge) in specs:
+        eps, psi0 = W.ribbon_inputs(w, l, Wd, seed)
+        H = O.honeycomb(w, l, eps, edge=edge)
+        lo, hi = H.gershgorin()
+        out.append(dict(width=w, length=l, edge=edge, eps_np=eps, psi0=psi0, H=H, emin=lo, emax=hi,
+                        eps=torch.from_numpy(eps).cuda(), psi=torch.from_numpy(psi0.copy()).cuda()))
+    return out
+
+
+SMALL = [(1, 50, 0.3, 1, "zigzag"), (7, 300, 1.0, 2, "armchair"), (33, 129, 2.0, 3, "zigzag"),
+         (40, 700, 0.1, 4, "zigzag"), (5, 1025, 0.5, 5, "armchair"), (16, 64, 1.5, 6, "zigzag"),
+         (128, 40, 0.7, 7, "zigzag"), (2, 2, 0.9, 8, "armchair"), (64, 513, 1.2, 9, "zigzag"),
+         (9, 999, 0.2, 10, "zigzag"), (31, 257, 1.9, 11, "armchair"), (3, 4097, 0.6, 12, "zigzag")]
+
+
+def reset(systems, torch):
+    for s in systems:
+        s["psi"].copy_(torch.from_numpy(s["psi0"]).cuda())
+
+
+@pytest.mark.parametrize("mode,tile,block,wg", [(0, 1024, 256, 1), (0, 512, 512, 1), (1, 1024, 256, 2),
+                                                (1, 4096, 512, 4), (1, 256, 256, 8)])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle(torch, cheb, mode, tile, block, wg, graph):
+    systems = make_systems(SMALL, torch)
+    ctx = cheb.Context()
+    dt, K = 1.0, 5
+    ctx.batch_create(systems, dt)
+    ctx.batch_set_schedule(mode, tile, block, wg)
+    say(f"[gpu] batch mode={mode} tile={tile} block={block} wg={wg} graph={graph}")
+    ctx.batch_propagate(K, cheb.GRAPH if graph else 0)
+    torch.cuda.synchronize()
+    Ms = ctx.batch_info()
+    for s, M in zip(systems, Ms):
+        plan = O.Plan(s["emin"], s["emax"], dt)
+        assert M == plan.M
+        ref = O.propagate(s["H"], plan, s["psi0"], K)
+        assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-10
+
+
+def test_batch_equals_single_system_path_bitwise(torch, cheb):
+    systems = make_systems(SMALL[:6], torch)
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    ctx.batch_set_schedule(1, 2048, 256, 2)
+    ctx.batch_propagate(4)
+    torch.cuda.synchronize()
+    for s in systems:
+        one = cheb.Context()
+        one.honeycomb(s["width"], s["length"], s["eps"], edge=s["edge"])
+        one.set_bounds(s["emin"], s["emax"])
+        one.plan(1.0)
+        p = torch.from_numpy(s["psi0"].copy()).cuda()
+        one.propagate(p, 4)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(p.cpu().numpy(), s["psi"].cpu().numpy())
+
+
+def test_batch_autotune_restores_state_and_caches(torch, cheb, tmp_path):
+    systems = make_systems(SMALL, torch)
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    cache = str(tmp_path / "tune.txt")
+    best = ctx.batch_autotune(cache)
+    assert best[0] in (0, 1)
+    for s in systems:
+        np.testing.assert_array_equal(s["psi"].cpu().numpy(), s["psi0"])
+    assert os.path.exists(cache) and len(open(cache).read().split()) == 5
+    best2 = ctx.batch_autotune(cache)  # read back from the cache
+    assert tuple(best2) == tuple(best)
+    ctx.batch_propagate(3, cheb.GRAPH)
+    torch.cuda.synchronize()
+    s = systems[3]
+    ref = O.propagate(s["H"], O.Plan(s["emin"], s["emax"], 1.0), s["psi0"], 3)
+    assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-10
+
+
+def test_batch_rejects_bad_schedule(torch, cheb):
+    systems = make_systems(SMALL[:2], torch)
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    with pytest.raises(cheb.ChebError):
+        ctx.batch_set_schedule(1, 1000, 256, 2)  # tile not a multiple of block
+    with pytest.raises(cheb.ChebError):
+        ctx.batch_set_schedule(5, 1024, 256, 2)
+
+
+def test_full_batched_config_sampled(torch, cheb):
+    # 256 ribbons, widths 32-128, lengths 512-4096, W in [0.1, 2]: both schedules
+    # agree bit for bit everywhere; three systems are checked against the oracle
+    p = W.BATCHED.params
+    descs = W.batched_ribbons(p["nsys"], p["seed_base"])
+    total = sum(d.n for d in descs)
+    assert 3e7 < total < 7e7
+    systems = []
+    for d in descs:
+        eps, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        # Gershgorin discs of a zigzag brick wall (interior sites have 3 bonds)
+        systems.append(dict(width=d.width, length=d.length, eps=torch.from_numpy(eps).cuda(),
+                            psi=torch.from_numpy(psi0).cuda(), emin=float(eps.min()) - 3.0,
+                            emax=float(eps.max()) + 3.0))
+    ctx = cheb.Context()
+    ctx.batch_create(systems, p["dt"])
+    Ms = ctx.batch_info()
+    assert 18 <= Ms.min() and Ms.max() <= 24
+    say(f"[gpu] full batch: {len(descs)} systems, {total} sites, levels schedule")
+    ctx.batch_set_schedule(0, 2048, 256, 1)
+    ctx.batch_propagate(2)
+    torch.cuda.synchronize()
+    lev = [s["psi"].cpu().numpy() for s in systems]
+    for s, d in zip(systems, descs):
+        _, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        s["psi"].copy_(torch.from_numpy(psi0).cuda())
+    say("[gpu] full batch: persistent schedule")
+    ctx.batch_set_schedule(1, 4096, 256, 2)
+    ctx.batch_propagate(2, cheb.GRAPH)
+    torch.cuda.synchronize()
+    for s, ref in zip(systems, lev):
+        np.testing.assert_array_equal(s["psi"].cpu().numpy(), ref)
+    sizes = np.array([d.n for d in descs])
+    for j in (int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), 17):
+        d = descs[j]
+        eps, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        H = O.honeycomb(d.width, d.length, eps)
+        plan = O.Plan(systems[j]["emin"], systems[j]["emax"], p["dt"])
+        assert plan.M == Ms[j]
+        ref = O.propagate(H, plan, psi0, 2)
+        assert rel_l2(lev[j], ref) <= 1e-10
