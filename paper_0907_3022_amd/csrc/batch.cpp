@@ -38,7 +38,7 @@ struct BatchState {
     QueueDev q{};
     int64_t nblocks = 0;
     DevBuf head, done, flag;
-    int64_t spin_limit = (int64_t)1 << 24;
+    int64_t spin_limit = 0;  // wall-clock ticks a dependency wait may take
     hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
 };
@@ -255,6 +255,13 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
     c->batch = b;
     b->nsys = nsys;
     b->dt = dt;
+    {
+        // two seconds of the device's constant-rate wall clock
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        b->spin_limit = (int64_t)khz * 1000 * 2;
+    }
     b->sys.resize(nsys);
     b->M.resize(nsys);
     b->nsites.resize(nsys);

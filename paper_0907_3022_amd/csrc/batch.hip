@@ -13,9 +13,9 @@
 //                level.  Before a tile of level k runs, every tile of level
 //                k-1 of the same system must be done; per-system completion
 //                counters (release/acquire at agent scope) carry that
-//                dependency.  The wait is bounded: after a spin limit the
-//                kernel records a timeout, finishes the queue without
-//                computing and exits, so every wave always terminates.
+//                dependency.  The wait is bounded in wall-clock time: past
+//                the limit the kernel records a timeout, finishes the queue
+//                without computing and exits, so every wave terminates.
 //                Items are dequeued in level order and a dequeued item's
 //                dependencies were dequeued earlier by running workgroups,
 //                so the earliest unfinished item can always proceed.
@@ -129,57 +129,74 @@ __device__ __forceinline__ int32_t upper_index(const int64_t *a, int32_t cnt, in
     return lo;
 }
 
+// Loop shape matters here: every thread-0-only action (publishing the
+// previous tile, fetching and decoding the next item, waiting for its
+// dependencies) sits in one block at the top of the loop, followed by a
+// barrier, and the exit test reads the item through readfirstlane so that
+// the compiler sees a uniform loop exit.  A thread-0-only tail before the
+// back edge together with an exit the compiler cannot prove uniform lets it
+// rotate the loop so that lanes 1..63 of wave 0 re-enter the barrier with a
+// stale item while lane 0 waits outside the inner loop: a hang.
 __global__ void k_batch_persistent(const SysDev *__restrict__ sys, const double2 *__restrict__ gamma,
                                    const QueueDev q, int32_t tile, int par, int64_t *queue_head,
                                    int32_t *done, int32_t *timeout_flag, int64_t spin_limit)
 {
-    __shared__ int64_t s_item;
-    __shared__ int32_t s_k, s_sys, s_tile, s_skip;
+    __shared__ int32_t s_info[6];  // item (lo, hi), k, system, tile, skip
+    int32_t pending = -1;          // system whose tile this block finished last (thread 0)
     for (;;) {
         if (threadIdx.x == 0) {
-            s_item = __hip_atomic_fetch_add(queue_head, (int64_t)1, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        const int64_t item = s_item;
-        if (item >= q.total) break;
-        if (threadIdx.x == 0) {
-            // level k: items [q.level_off[k], q.level_off[k+1])
-            const int32_t k = upper_index(q.level_off, q.nlevels, item);
-            const int64_t r = item - q.level_off[k];
-            // active systems at level k are a prefix of the M-sorted order
-            const int32_t j = upper_index(q.tile_prefix, q.level_active[k], r);
-            const int32_t s = q.order[j];
-            s_k = k;
-            s_sys = s;
-            s_tile = (int32_t)(r - q.tile_prefix[j]);
-            int skip = 0;
-            if (k > 0) {
-                // wait for every tile of level k-1 of system s
-                const int32_t need = k * sys[s].ntiles;
-                int64_t spins = 0;
-                while (__hip_atomic_load(&done[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    if (__hip_atomic_load(timeout_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                        ++spins > spin_limit) {
-                        __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        skip = 1;
-                        break;
+            if (pending >= 0)
+                __hip_atomic_fetch_add(&done[pending], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t item = __hip_atomic_fetch_add(queue_head, (int64_t)1, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            int32_t k = 0, s = 0, t = 0, skip = 0;
+            const int32_t valid = item < q.total;
+            if (valid) {
+                // level k: items [q.level_off[k], q.level_off[k+1])
+                k = upper_index(q.level_off, q.nlevels, item);
+                const int64_t r = item - q.level_off[k];
+                // active systems at level k are a prefix of the M-sorted order
+                const int32_t j = upper_index(q.tile_prefix, q.level_active[k], r);
+                s = q.order[j];
+                t = (int32_t)(r - q.tile_prefix[j]);
+                if (k > 0) {
+                    // every tile of level k-1 of system s must be done; the wait
+                    // is bounded in wall-clock ticks
+                    const int32_t need = k * sys[s].ntiles;
+                    const int64_t t_start = wall_clock64();
+                    int64_t spins = 0;
+                    while (__hip_atomic_load(&done[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (wall_clock64() - t_start > spin_limit ||
+                            ((++spins & 255) == 0 &&
+                             __hip_atomic_load(timeout_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                            __hip_atomic_store(timeout_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            skip = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(8);
                     }
-                    __builtin_amdgcn_s_sleep(2);
                 }
             }
-            s_skip = skip;
+            s_info[0] = valid;
+            s_info[2] = k;
+            s_info[3] = s;
+            s_info[4] = t;
+            s_info[5] = skip;
+            pending = valid ? s : -1;
         }
         __syncthreads();
-        // make the other tiles' results visible to every thread of the block
+        const int32_t valid = __builtin_amdgcn_readfirstlane(s_info[0]);
+        if (!valid) break;
+        const int32_t k = __builtin_amdgcn_readfirstlane(s_info[2]);
+        const int32_t s = __builtin_amdgcn_readfirstlane(s_info[3]);
+        const int32_t t = __builtin_amdgcn_readfirstlane(s_info[4]);
+        const int32_t skip = __builtin_amdgcn_readfirstlane(s_info[5]);
+        // the other tiles' results become visible to every thread of the block
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const int32_t k = s_k, s = s_sys;
-        if (!s_skip) tile_level(sys[s], gamma, k, s_tile, tile, par);
-        // publish this tile: all stores of the block, then the counter
+        if (!skip) tile_level(sys[s], gamma, k, t, tile, par);
+        // this block's stores complete before thread 0 publishes the tile
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&done[s], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
