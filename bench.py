@@ -292,6 +292,16 @@ def bench_adjoint(torch, P, K):
     return out
 
 
+def bench_copy(torch, nbytes=1 << 30, reps=5):
+    """A plain device copy of known size: the reference that scales the
+    hardware byte counters (FETCH_SIZE, WRITE_SIZE) of the other kernels."""
+    n = nbytes // 16
+    src = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    dst = torch.empty_like(src)
+    t = timed(torch, lambda: dst.copy_(src), reps)
+    return dict(bytes_each_way=n * 16, reps=reps, GBs=2 * n * 16 * reps / t / 1e9)
+
+
 def cpu_baseline(target_seconds=12.0):
     """The serial oracle on the first steps of the headline workload."""
     import oracle as O
@@ -391,6 +401,9 @@ def main():
     if "sweep" in sections:
         log("[bench] ribbon size sweep")
         extra["sweep"] = bench_sweep(torch, P, [(128, 8192), (256, 16384), (512, 32768), (1024, 65536)])
+    if "copy" in sections:
+        log("[bench] reference copy")
+        extra["copy"] = bench_copy(torch)
     if "cpu" in sections:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()
