@@ -34,6 +34,7 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 STENCIL_BYTES = 88       # per site and order: v_k, v_{k-1}, v_{k+1}, acc r/w, on-site term
+PAIR_BYTES = 104         # per site and two orders: v_{k-1}, v_k, on-site, acc r/w, v_{k+1}, v_{k+2}
 CSR_VEC_BYTES = 80       # vector traffic per row and order for CSR
 CSR_NNZ_BYTES = 20       # complex128 value + int32 column
 CSR_ROW_BYTES = 8        # rowptr
@@ -45,7 +46,7 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_ops.h"):
+    for f in ("kernels.hip", "device_ops.h", "pair.hip"):
         with open(os.path.join(ROOT, "paper_0907_3022_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -104,9 +105,14 @@ def bench_main(torch, P, steps, warmup, mode_flags):
     nr = nrm[:steps].cpu().numpy()
     drift = float(np.abs(nr - nr[0]).max()) if steps else 0.0
     # dominant kernel timed alone with HIP events on the library's stream
-    ms_iter, kname = ctx.time_recursion_kernel(200)
-    return dict(ctx=ctx, n=n, M=M, seconds=t, ms_iter=ms_iter, kernel=kname, norm_drift=drift,
-                psi=psi, eps=eps_d)
+    ms_iter, kname, orders = ctx.time_recursion_kernel(200)
+    ms_single, kname_single, _ = ctx.time_recursion_kernel(200, P.SINGLE_ORDER)
+    # the same run with one order per pass, for comparison
+    psi2 = psi.clone()
+    t_single = timed(torch, lambda: ctx.propagate(psi2, steps, nrm, en, flags | P.SINGLE_ORDER))
+    return dict(ctx=ctx, n=n, M=M, seconds=t, ms_iter=ms_iter, kernel=kname, orders=orders,
+                ms_single=ms_single, kernel_single=kname_single, seconds_single=t_single,
+                norm_drift=drift, psi=psi, eps=eps_d)
 
 
 def bench_mode_choice(torch, P):
@@ -167,7 +173,7 @@ def bench_holstein(torch, P, K):
         ctx.propagate(psi, 5, None, None, P.NO_CHECK)
         psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
         t = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
-        ms_iter, kname = ctx.time_recursion_kernel(100)
+        ms_iter, kname, _ = ctx.time_recursion_kernel(100)
         nnz_row = 4.0
         bytes_row = CSR_VEC_BYTES + nnz_row * CSR_NNZ_BYTES + CSR_ROW_BYTES
         n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
@@ -184,10 +190,14 @@ def bench_sweep(torch, P, sizes):
     res = []
     for width, length in sizes:
         ctx, eps_d, psi, M = ribbon_context(torch, P, width, length, 0.5, 1)
-        ms, kname = ctx.time_recursion_kernel(50)
+        ms, kname, orders = ctx.time_recursion_kernel(50)
+        ms1, kname1, _ = ctx.time_recursion_kernel(50, P.SINGLE_ORDER)
         n = width * length
-        res.append(dict(sites=n, shape=f"{width}x{length}", kernel_ms=ms,
-                        GBs=STENCIL_BYTES * n / (ms * 1e-3) / 1e9))
+        per = PAIR_BYTES if orders == 2 else STENCIL_BYTES
+        res.append(dict(sites=n, shape=f"{width}x{length}", kernel=kname, kernel_ms=ms,
+                        orders_per_launch=orders, GBs=per * n / (ms * 1e-3) / 1e9,
+                        ns_per_site_order=ms * 1e6 / n / orders,
+                        single_order_kernel_ms=ms1, single_order_GBs=STENCIL_BYTES * n / (ms1 * 1e-3) / 1e9))
         ctx.close()
         del eps_d, psi
         torch.cuda.empty_cache()
@@ -358,7 +368,8 @@ def main():
     r = bench_main(torch, P, args.steps, args.warmup, mode_flags)
     hv = args.steps * r["M"]
     value = hv / r["seconds"] if r["seconds"] > 0 else 0.0
-    achieved = STENCIL_BYTES * r["n"] / (r["ms_iter"] * 1e-3) / 1e9
+    unit_bytes = PAIR_BYTES if r["orders"] == 2 else STENCIL_BYTES
+    achieved = unit_bytes * r["n"] / (r["ms_iter"] * 1e-3) / 1e9
     traffic = traffic_record(r["kernel"])
     line = {
         "metric": "H·v Chebyshev steps/s + achieved HBM GB/s; batched & adjoint vs plain",
@@ -379,9 +390,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": r["kernel"], "kernel_ms_per_launch": r["ms_iter"],
-                     "algorithmic_bytes_per_launch": STENCIL_BYTES * r["n"]},
+                     "orders_per_launch": r["orders"],
+                     "algorithmic_bytes_per_launch": unit_bytes * r["n"]},
+        "single_order": {"kernel": r["kernel_single"], "kernel_ms_per_launch": r["ms_single"],
+                         "GBs": STENCIL_BYTES * r["n"] / (r["ms_single"] * 1e-3) / 1e9,
+                         "hv_per_s": hv / r["seconds_single"]},
         "time_steps_per_s": args.steps / r["seconds"] if r["seconds"] > 0 else 0.0,
-        "step_GBs": STENCIL_BYTES * r["n"] * hv / r["seconds"] / 1e9 if r["seconds"] > 0 else 0.0,
+        "step_equivalent_GBs": STENCIL_BYTES * r["n"] * hv / r["seconds"] / 1e9 if r["seconds"] > 0 else 0.0,
         "norm_drift": r["norm_drift"],
     }
     r["ctx"].close()

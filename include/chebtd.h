@@ -59,6 +59,8 @@ extern "C" {
 #define CHEBTD_NO_PERSISTENT 8u    /* small chains: one launch per          */
                                    /* iteration instead of the one-         */
                                    /* workgroup persistent kernel           */
+#define CHEBTD_SINGLE_ORDER 16u    /* chains and ribbons: one recursion     */
+                                   /* order per pass instead of two         */
 
 typedef struct chebtd_ctx chebtd_ctx;
 
@@ -295,11 +297,14 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev);
 /* ======================================================================= */
 
 /* Launch the current Hamiltonian's recursion kernel (the hot loop) `launches`
- * times on the context's stream between two hipEvents, on the context's own
- * work vectors, and return the mean time per launch in milliseconds and the
- * kernel's name.  Needs a plan.  Synchronises.  name_out may be NULL. */
-int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, double *ms_per_launch,
-                                 const char **name_out);
+ * times on the context's stream between two hipEvents, on scratch vectors
+ * (allocated and freed here), and return the mean time per launch in
+ * milliseconds, the kernel's name and the recursion orders one launch
+ * advances (2 for the two-orders-per-pass kernel, else 1; CHEBTD_SINGLE_ORDER
+ * in `flags` times the one-order kernel).  Needs a plan.  Synchronises.
+ * name_out and orders_out may be NULL. */
+int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, double *ms_per_launch,
+                                 const char **name_out, int *orders_out);
 
 #ifdef __cplusplus
 }

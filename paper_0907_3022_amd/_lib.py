@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchebtd.s
 OK = 0
 E_ARG, E_HIP, E_DIVERGED, E_OOM, E_STATE, E_TIMEOUT = -1, -2, -3, -4, -5, -6
 ZIGZAG, ARMCHAIR = 0, 1
-KEEP_CHECKPOINTS, NO_CHECK, GRAPH, NO_PERSISTENT = 1, 2, 4, 8
+KEEP_CHECKPOINTS, NO_CHECK, GRAPH, NO_PERSISTENT, SINGLE_ORDER = 1, 2, 4, 8, 16
 SCHED_LEVELS, SCHED_PERSISTENT = 0, 1
 ADJ_STEP, ADJ_SQRTM = 0, 1
 
@@ -79,8 +79,8 @@ _SIGS = {
     "chebtd_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_void_p]),
     "chebtd_reserve_adjoint": (C.c_int, [C.c_void_p, C.c_int64, C.c_int]),
     "chebtd_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
-    "chebtd_time_recursion_kernel": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
-                                               C.POINTER(C.c_char_p)]),
+    "chebtd_time_recursion_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_uint, C.POINTER(C.c_double),
+                                               C.POINTER(C.c_char_p), C.POINTER(C.c_int)]),
 }
 
 

@@ -281,9 +281,11 @@ class Context:
         self._check(self._lib.chebtd_adjoint(self.h, pg, pd))
 
     # -- measurement ---------------------------------------------------------------------
-    def time_recursion_kernel(self, launches: int = 100):
+    def time_recursion_kernel(self, launches: int = 100, flags: int = 0):
+        """(ms per launch, kernel name, recursion orders per launch)."""
         ms = C.c_double()
         name = C.c_char_p()
-        self._check(self._lib.chebtd_time_recursion_kernel(self.h, int(launches), C.byref(ms),
-                                                           C.byref(name)))
-        return ms.value, name.value.decode()
+        orders = C.c_int()
+        self._check(self._lib.chebtd_time_recursion_kernel(self.h, int(launches), int(flags), C.byref(ms),
+                                                           C.byref(name), C.byref(orders)))
+        return ms.value, name.value.decode(), orders.value

@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
 #include "internal.h"
+#include "pair.h"
 
 using namespace chebtd;
 
@@ -69,12 +71,33 @@ int ensure_partials(Ctx *c)
 {
     int64_t nb = (c->n + kBlock - 1) / kBlock;
     nb = std::max<int64_t>(nb, grid_blocks(*c));
+    if (pair_supported(*c)) nb = std::max<int64_t>(nb, pair_grid_blocks(*c, c->pair_rows));
     size_t bytes = (size_t)std::max<int64_t>(nb, 1) * 2 * sizeof(double);
     if (c->holstein) {
         size_t hb = (size_t)holstein_obs_blocks(c->hol_nconf) * 3 * c->hol_L * sizeof(double);
         bytes = std::max(bytes, hb);
     }
     return ensure(c, c->partials, bytes, "partials");
+}
+
+// Rows per wavefront chunk of the two-orders-per-pass kernel: enough chunks
+// for about eight wavefronts per CU, at least eight rows (each chunk re-reads
+// two halo rows of v_k on either side).  CHEBTD_PAIR_ROWS overrides.
+int choose_pair_rows(const Ctx &c)
+{
+    const char *env = std::getenv("CHEBTD_PAIR_ROWS");
+    if (env) {
+        const int r = std::atoi(env);
+        if (r >= 1) return r;
+    }
+    if (!pair_supported(c)) return 16;
+    const int64_t W = c.kind == HKind::Chain ? 1 : c.W;
+    const int64_t L = c.kind == HKind::Chain ? c.n : c.L;
+    const int64_t strips = (L + 61) / 62;
+    const int64_t target = 8 * (int64_t)c.num_cus;
+    const int64_t chunks = std::max<int64_t>(1, (target + strips - 1) / strips);
+    int64_t rows = std::max<int64_t>(8, (W + chunks - 1) / chunks);
+    return (int)std::min<int64_t>(rows, std::max<int64_t>(W, 1));
 }
 
 void invalidate_h(Ctx *c)
@@ -136,7 +159,7 @@ int chebtd_destroy(chebtd_ctx *ctx)
     batch_destroy(c);
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (DevBuf *b : {&c->vA, &c->vB, &c->partials, &c->results, &c->counter, &c->gamma_dev,
+    for (DevBuf *b : {&c->vA, &c->vB, &c->vC, &c->vD, &c->partials, &c->results, &c->counter, &c->gamma_dev,
                       &c->hol_rowptr, &c->hol_col, &c->hol_val, &c->hol_occ, &c->hol_up})
         release(*b);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -353,6 +376,15 @@ static int plan_common(Ctx *c, double dt, int M)
     const size_t vbytes = (size_t)c->n * 2 * sizeof(double);
     if ((rc = ensure(c, c->vA, vbytes, "work vector A")) || (rc = ensure(c, c->vB, vbytes, "work vector B")))
         return rc;
+    // two more vectors let brick-wall Hamiltonians advance two orders per pass
+    c->use_pairs = false;
+    c->pair_rows = choose_pair_rows(*c);
+    if ((rc = ensure_partials(c))) return rc;
+    if (pair_supported(*c) && M >= 2) {
+        if ((rc = ensure(c, c->vC, vbytes, "work vector C")) || (rc = ensure(c, c->vD, vbytes, "work vector D")))
+            return rc;
+        c->use_pairs = true;
+    }
     if ((rc = ensure_partials(c))) return rc;
     c->dt = dt;
     c->M = M;

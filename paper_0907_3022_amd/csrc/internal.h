@@ -94,8 +94,11 @@ struct Ctx {
     std::vector<double> gamma;  // interleaved complex, M+1 entries
     DevBuf gamma_dev;           // device copy of gamma
 
-    // work vectors: two complex vectors of length n
-    DevBuf vA, vB;
+    // work vectors: two complex vectors of length n, two more for the
+    // two-orders-per-pass kernel
+    DevBuf vA, vB, vC, vD;
+    bool use_pairs = false;  // brick-wall H with M >= 2 and pair buffers present
+    int pair_rows = 16;      // rows per wavefront chunk of the pair kernel
     // reduction scratch: partial sums, step counter, results
     DevBuf partials;   // double[2 * max_blocks]
     DevBuf results;    // double[16]

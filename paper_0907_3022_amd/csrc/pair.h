@@ -1,0 +1,32 @@
+// Two-orders-per-pass recursion kernel for brick-wall lattices (pair.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace chebtd {
+
+struct OpPair {
+    const double *onsite;  // eps (ribbon) or V (chain)
+    double dshift;         // -b (ribbon) or 1/dx^2 - b (chain)
+    double s2;             // 2/a
+    double off2;           // -2t/a (ribbon) or -1/(dx^2 a) (chain)
+    int32_t W, L;          // rows, columns (a chain is one row of n columns)
+    int32_t rows;          // rows per chunk
+    int32_t nstrips, nchunks;
+    int32_t xcd_remap;
+};
+
+OpPair make_pair_op(const Ctx &c, int rows);
+int64_t pair_grid_blocks(const Ctx &c, int rows);
+bool pair_supported(const Ctx &c);
+// head: v1 = H~ vk, v2 = 2 H~ v1 - vk, acc = g0 vk + g1 v1 + g2 v2 (+ partials, ckpt)
+// else: v_{k+1} = 2 H~ vk - vkm1, v_{k+2} = 2 H~ v_{k+1} - vk, acc += g1 v_{k+1} + g2 v_{k+2}
+hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1, const double2 *vk,
+                       double2 *out1, double2 *out2, double2 *acc, double2 g0, double2 g1, double2 g2,
+                       double2 *ckpt, double *partials);
+
+}  // namespace chebtd

@@ -1,0 +1,207 @@
+// Two Chebyshev orders per pass over HBM for brick-wall lattices: the
+// honeycomb ribbons of eq. (model) and, as a ribbon of width 1, the 1D
+// finite-difference chain of Sect. 3.1 (arXiv:0907.3022, Sect. 2.2 recursion).
+//
+// One pass reads v_{k-1}, v_k, the on-site term and acc once and writes
+//   v_{k+1} = 2 H~ v_k - v_{k-1},   v_{k+2} = 2 H~ v_{k+1} - v_k,
+//   acc += g_{k+1} v_{k+1} + g_{k+2} v_{k+2}
+// (104 B per site for two orders instead of 2 x 88 B).  The head variant
+// starts a time step: v_1 = H~ psi, v_2 = 2 H~ v_1 - psi,
+// acc = g_0 psi + g_1 v_1 + g_2 v_2, plus the norm and energy partials.
+//
+// Mapping: each wavefront owns a strip of 62 columns and a chunk of rows.
+// Lane l holds column x = 62*strip + l - 1, so lanes 0 and 63 are halo
+// columns whose v_{k+1} the neighbouring lanes need for the second order.
+// The wavefront walks down its rows keeping three rows of v_k and three of
+// v_{k+1} in registers: vertical neighbours come from registers, horizontal
+// ones from the adjacent lanes (cross-lane shuffles); only lanes 0 and 63
+// load one extra v_k value per row.  A chunk of rows [ys, ye) computes
+// v_{k+1} on rows ys-1 .. ye (one halo row each side, recomputed by the
+// neighbouring chunk) and v_{k+2} on its own rows.  Outputs are written to
+// buffers distinct from the inputs, so no wavefront overwrites a value
+// another one still reads.
+#include <hip/hip_runtime.h>
+
+#include "device_ops.h"
+#include "internal.h"
+#include "pair.h"
+
+namespace chebtd {
+
+namespace {
+
+constexpr int kStrip = 62;
+
+__device__ __forceinline__ double2 shfl_up1(double2 v)
+{
+    return make_double2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+}
+__device__ __forceinline__ double2 shfl_down1(double2 v)
+{
+    return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+
+}  // namespace
+
+template <int EDGE, bool HEAD>
+__global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restrict__ vkm1,
+                                              const double2 *__restrict__ vk, double2 *__restrict__ out1,
+                                              double2 *__restrict__ out2, double2 *__restrict__ acc,
+                                              double2 g0, double2 g1, double2 g2, double2 *__restrict__ ckpt,
+                                              double *partials)
+{
+    __shared__ double red[2 * 4];
+    const int lane = threadIdx.x & 63;
+    const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
+    const int32_t strip = gw % op.nstrips;
+    const int32_t chunk = gw / op.nstrips;
+    const int32_t W = op.W, L = op.L;
+    const int32_t x = strip * kStrip + lane - 1;
+    const bool colok = x >= 0 && x < L;
+    const bool own = colok && lane >= 1 && lane <= kStrip;
+    const double2 zero = make_double2(0.0, 0.0);
+    double nrm = 0.0, en = 0.0;
+
+    if (chunk < op.nchunks) {  // uniform per wavefront
+        const int32_t ys = chunk * op.rows;
+        const int32_t ye = min(ys + op.rows, W);
+        auto ld = [&](const double2 *v, int32_t r) -> double2 {
+            return (colok && r >= 0 && r < W) ? v[(int64_t)r * L + x] : zero;
+        };
+        double2 a_m1 = ld(vk, ys - 2), a_0 = ld(vk, ys - 1);  // v_k rows r-1, r
+        double2 b_m2 = zero, b_m1 = zero;                     // v_{k+1} rows r-2, r-1
+        double e_m1 = 0.0;                                    // on-site term, row r-1
+        for (int32_t r = ys - 1; r <= ye; ++r) {
+            const double2 a_p1 = ld(vk, r + 1);
+            const bool rowok = r >= 0 && r < W;
+            const int64_t ir = (int64_t)r * L + x;
+            // ---- first order at row r: v_{k+1} = 2 H~ v_k - v_{k-1} ----
+            double2 left = shfl_up1(a_0), right = shfl_down1(a_0);
+            if (lane == 0) left = (rowok && x - 1 >= 0 && x - 1 < L) ? vk[ir - 1] : zero;
+            if (lane == 63) right = (rowok && x + 1 >= 0 && x + 1 < L) ? vk[ir + 1] : zero;
+            const bool even_r = ((x + r) & 1) == 0;
+            double2 s;
+            if (EDGE == CHEBTD_ZIGZAG)
+                s = cadd(cadd(left, right), even_r ? a_p1 : a_m1);
+            else
+                s = cadd(cadd(a_m1, a_p1), even_r ? right : left);
+            const double e_0 = (colok && rowok) ? op.onsite[ir] : 0.0;
+            const double d0 = op.s2 * (e_0 + op.dshift);
+            double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
+            double2 b_0;
+            if (HEAD)
+                b_0 = cscale(0.5, h);
+            else
+                b_0 = csub(h, (colok && rowok) ? vkm1[ir] : zero);
+            if (!(colok && rowok)) b_0 = zero;
+            if (own && r >= ys && r < ye) out1[ir] = b_0;
+            // ---- second order at row q = r-1: v_{k+2} = 2 H~ v_{k+1} - v_k ----
+            if (r - 1 >= ys) {
+                const int32_t q = r - 1;
+                const int64_t iq = (int64_t)q * L + x;
+                const double2 l2 = shfl_up1(b_m1), r2 = shfl_down1(b_m1);
+                const bool even_q = ((x + q) & 1) == 0;
+                double2 s2;
+                if (EDGE == CHEBTD_ZIGZAG)
+                    s2 = cadd(cadd(l2, r2), even_q ? b_0 : b_m2);
+                else
+                    s2 = cadd(cadd(b_m2, b_0), even_q ? r2 : l2);
+                const double d1 = op.s2 * (e_m1 + op.dshift);
+                const double2 h2 = make_double2(fma(d1, b_m1.x, op.off2 * s2.x), fma(d1, b_m1.y, op.off2 * s2.y));
+                const double2 c = csub(h2, a_m1);
+                if (own) {
+                    out2[iq] = c;
+                    double2 a;
+                    if (HEAD) {
+                        a = cfma(g0, a_m1, zero);
+                        if (ckpt) ckpt[iq] = a_m1;
+                        nrm += a_m1.x * a_m1.x + a_m1.y * a_m1.y;
+                        en += a_m1.x * b_m1.x + a_m1.y * b_m1.y;
+                    } else {
+                        a = acc[iq];
+                    }
+                    a = cfma(g1, b_m1, a);
+                    acc[iq] = cfma(g2, c, a);
+                }
+            }
+            a_m1 = a_0;
+            a_0 = a_p1;
+            b_m2 = b_m1;
+            b_m1 = b_0;
+            e_m1 = e_0;
+        }
+    }
+    if (HEAD) {
+        block_sum2(nrm, en, red);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = nrm;
+            partials[2 * blockIdx.x + 1] = en;
+        }
+    }
+}
+
+OpPair make_pair_op(const Ctx &c, int rows)
+{
+    OpPair op{};
+    op.s2 = 2.0 / c.a;
+    if (c.kind == HKind::Chain) {
+        op.onsite = c.V;
+        op.dshift = 1.0 / (c.dx * c.dx) - c.b;
+        op.off2 = 2.0 * (-0.5 / (c.dx * c.dx)) / c.a;
+        op.W = 1;
+        op.L = (int32_t)c.n;
+    } else {
+        op.onsite = c.eps;
+        op.dshift = -c.b;
+        op.off2 = -2.0 * c.t_hop / c.a;
+        op.W = (int32_t)c.W;
+        op.L = (int32_t)c.L;
+    }
+    op.rows = rows < 1 ? 1 : rows;
+    op.nstrips = (op.L + kStrip - 1) / kStrip;
+    op.nchunks = (op.W + op.rows - 1) / op.rows;
+    op.xcd_remap = 1;
+    return op;
+}
+
+int64_t pair_grid_blocks(const Ctx &c, int rows)
+{
+    const OpPair op = make_pair_op(c, rows);
+    const int64_t waves = (int64_t)op.nstrips * op.nchunks;
+    return (waves + 3) / 4;
+}
+
+bool pair_supported(const Ctx &c)
+{
+    if (c.kind == HKind::Honeycomb) return c.L < (1 << 30) && c.W < (1 << 30);
+    return c.kind == HKind::Chain && c.n < ((int64_t)1 << 31);
+}
+
+hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1, const double2 *vk,
+                       double2 *out1, double2 *out2, double2 *acc, double2 g0, double2 g1, double2 g2,
+                       double2 *ckpt, double *partials)
+{
+    const OpPair op = make_pair_op(c, rows);
+    const int64_t nb = pair_grid_blocks(c, rows);
+    if (nb <= 0 || nb > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    if (head) {
+        if (zig)
+            hipLaunchKernelGGL((k_pair<CHEBTD_ZIGZAG, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, g0,
+                               g1, g2, ckpt, partials);
+        else
+            hipLaunchKernelGGL((k_pair<CHEBTD_ARMCHAIR, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
+                               g0, g1, g2, ckpt, partials);
+    } else {
+        if (zig)
+            hipLaunchKernelGGL((k_pair<CHEBTD_ZIGZAG, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
+                               g0, g1, g2, ckpt, partials);
+        else
+            hipLaunchKernelGGL((k_pair<CHEBTD_ARMCHAIR, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
+                               g0, g1, g2, ckpt, partials);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace chebtd

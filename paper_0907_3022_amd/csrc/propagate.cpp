@@ -9,6 +9,7 @@
 #include <string>
 
 #include "internal.h"
+#include "pair.h"
 
 namespace chebtd {
 int fail(Ctx *c, int code, const std::string &msg);
@@ -30,10 +31,50 @@ double2 weight(const Ctx *c, int k)
     return make_double2(c->gamma[2 * (size_t)k], c->gamma[2 * (size_t)k + 1]);
 }
 
+// One time step with two orders per pass (brick-wall H, M >= 2): the head
+// pass forms v_1, v_2 and starts acc; each further pass forms the next two
+// orders from the previous two; an odd M ends with one single-order pass.
+// Pass outputs alternate between (vA, vC) and (vD, cur): cur is free once the
+// head pass has read it.
+hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt,
+                              double *norm_out, double *energy_out)
+{
+    double2 *A = static_cast<double2 *>(c->vA.p), *C = static_cast<double2 *>(c->vC.p),
+            *D = static_cast<double2 *>(c->vD.p);
+    double *partials = static_cast<double *>(c->partials.p);
+    hipError_t e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, A, C, nxt, weight(c, 0), weight(c, 1),
+                               weight(c, 2), ckpt, partials);
+    if (e != hipSuccess) return e;
+    if (norm_out || energy_out) {
+        e = launch_finalize_ne(s, partials, (int)pair_grid_blocks(*c, c->pair_rows), c->a, c->b, norm_out,
+                               energy_out, static_cast<int64_t *>(c->counter.p), nullptr);
+        if (e != hipSuccess) return e;
+    }
+    double2 *X = A, *Y = C, *F1 = D, *F2 = cur;  // (v_{k-1}, v_k) and the free pair
+    int k = 2;
+    for (; k + 2 <= c->M; k += 2) {
+        e = launch_pair(*c, s, c->pair_rows, false, X, Y, F1, F2, nxt, make_double2(0.0, 0.0), weight(c, k + 1),
+                        weight(c, k + 2), nullptr, nullptr);
+        if (e != hipSuccess) return e;
+        double2 *t1 = X, *t2 = Y;
+        X = F1;
+        Y = F2;
+        F1 = t1;
+        F2 = t2;
+    }
+    if (k < c->M) {  // one order left: v_M = 2 H~ v_{M-1} - v_{M-2} over v_{M-2}
+        e = launch_iter(*c, s, Y, X, nxt, weight(c, c->M));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Enqueue one time step: cur -> nxt.  cur is overwritten with v_2, v_4, ...
 hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt,
-                        double *norm_out, double *energy_out)
+                        double *norm_out, double *energy_out, unsigned flags)
 {
+    if (c->use_pairs && !(flags & CHEBTD_SINGLE_ORDER))
+        return enqueue_step_pairs(c, s, cur, nxt, ckpt, norm_out, energy_out);
     double2 *A = static_cast<double2 *>(c->vA.p);
     double *partials = static_cast<double *>(c->partials.p);
     hipError_t e = launch_head(*c, s, cur, A, nxt, weight(c, 0), weight(c, 1), ckpt, partials);
@@ -63,9 +104,11 @@ hipError_t enqueue_norm(Ctx *c, hipStream_t s, const double2 *psi, int slot)
 }
 
 // Two steps (psi -> B -> psi) captured once into a graph and replayed.
-int get_pair_graph(Ctx *c, double2 *psi, double *norm_out, double *energy_out, hipGraphExec_t *out)
+int get_pair_graph(Ctx *c, double2 *psi, double *norm_out, double *energy_out, unsigned flags,
+                   hipGraphExec_t *out)
 {
-    const void *key[4] = {psi, norm_out, energy_out, c->vA.p};
+    const void *key[4] = {psi, norm_out, energy_out,
+                          reinterpret_cast<const void *>((uintptr_t)(flags & CHEBTD_SINGLE_ORDER) + 1)};
     if (c->graph_exec[0] && key[0] == c->graph_key[0] && key[1] == c->graph_key[1] &&
         key[2] == c->graph_key[2] && key[3] == c->graph_key[3]) {
         *out = c->graph_exec[0];
@@ -79,8 +122,8 @@ int get_pair_graph(Ctx *c, double2 *psi, double *norm_out, double *energy_out, h
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
-    hipError_t e1 = enqueue_step(c, c->cap_stream, psi, B, nullptr, norm_out, energy_out);
-    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, c->cap_stream, B, psi, nullptr, norm_out, energy_out)
+    hipError_t e1 = enqueue_step(c, c->cap_stream, psi, B, nullptr, norm_out, energy_out, flags);
+    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, c->cap_stream, B, psi, nullptr, norm_out, energy_out, flags)
                                      : e1;
     e = hipStreamEndCapture(c->cap_stream, &g);
     if (e2 != hipSuccess) {
@@ -138,14 +181,14 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
         if (e != hipSuccess) return hip_fail(c, e, "persistent chain kernel");
     } else if ((flags & CHEBTD_GRAPH) && !keep) {
         hipGraphExec_t ge = nullptr;
-        int rc = get_pair_graph(c, P, norm_dev, energy_dev, &ge);
+        int rc = get_pair_graph(c, P, norm_dev, energy_dev, flags, &ge);
         if (rc) return rc;
         for (int64_t s2 = 0; s2 + 1 < K; s2 += 2) {
             e = hipGraphLaunch(ge, s);
             if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
         }
         if (K & 1) {
-            e = enqueue_step(c, s, P, B, nullptr, norm_dev, energy_dev);
+            e = enqueue_step(c, s, P, B, nullptr, norm_dev, energy_dev, flags);
             if (e == hipSuccess) e = launch_copy(s, B, P, c->n);
             if (e != hipSuccess) return hip_fail(c, e, "last step");
         }
@@ -154,7 +197,7 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
             double2 *cur = (st & 1) ? B : P;
             double2 *nxt = (st & 1) ? P : B;
             e = enqueue_step(c, s, cur, nxt, keep ? adj_checkpoint(c, st, K) : nullptr, norm_dev,
-                             energy_dev);
+                             energy_dev, flags);
             if (e != hipSuccess) return hip_fail(c, e, "step launch");
         }
         if (K & 1) {
@@ -235,37 +278,47 @@ int chebtd_holstein_obs(chebtd_ctx *ctx, const double *psi_dev, double *n_dev, d
     return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, "chebtd_holstein_obs");
 }
 
-int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, double *ms_per_launch,
-                                 const char **name_out)
+int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, double *ms_per_launch,
+                                 const char **name_out, int *orders_out)
 {
     if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
     Ctx *c = static_cast<Ctx *>(ctx);
     if (!c->has_plan) return fail(c, CHEBTD_E_STATE, "chebtd_time_recursion_kernel: no plan");
     if (launches < 1 || !ms_per_launch) return fail(c, CHEBTD_E_ARG, "need launches >= 1 and an output");
-    static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr"};
-    const char *nm = c->kind == HKind::Chain ? names[0]
-                     : c->kind == HKind::Csr ? names[3]
+    const bool pairs = c->use_pairs && !(flags & CHEBTD_SINGLE_ORDER);
+    static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr",
+                                  "k_pair<0,false>", "k_pair<1,false>"};
+    const char *nm = pairs ? (c->kind == HKind::Honeycomb && c->edge == CHEBTD_ARMCHAIR ? names[5] : names[4])
+                     : c->kind == HKind::Chain ? names[0]
+                     : c->kind == HKind::Csr   ? names[3]
                      : (c->edge == CHEBTD_ZIGZAG ? names[1] : names[2]);
     if (name_out) *name_out = nm;
-    DevBuf acc;
-    int rc = ensure(c, acc, (size_t)c->n * sizeof(double2), "timing accumulator");
+    if (orders_out) *orders_out = pairs ? 2 : 1;
+    // scratch: four vectors and an accumulator, zeroed
+    DevBuf scratch;
+    const size_t vb = (size_t)c->n * sizeof(double2);
+    int rc = ensure(c, scratch, 5 * vb, "timing vectors");
     if (rc) return rc;
     hipStream_t s = c->stream;
-    double2 *A = static_cast<double2 *>(c->vA.p), *B = static_cast<double2 *>(c->vB.p);
-    hipError_t e = hipMemsetAsync(acc.p, 0, acc.bytes, s);
-    if (e == hipSuccess) e = hipMemsetAsync(A, 0, c->vA.bytes, s);
-    if (e == hipSuccess) e = hipMemsetAsync(B, 0, c->vB.bytes, s);
-    // one untimed launch to page in code and caches
-    if (e == hipSuccess) e = launch_iter(*c, s, A, B, static_cast<double2 *>(acc.p), weight(c, 1));
+    double2 *V0 = static_cast<double2 *>(scratch.p), *V1 = V0 + c->n, *V2 = V1 + c->n, *V3 = V2 + c->n,
+            *acc = V3 + c->n;
+    hipError_t e = hipMemsetAsync(scratch.p, 0, 5 * vb, s);
+    auto one = [&](int i) -> hipError_t {
+        if (pairs)
+            return (i & 1) ? launch_pair(*c, s, c->pair_rows, false, V2, V3, V0, V1, acc, make_double2(0, 0),
+                                         weight(c, 1), weight(c, 2), nullptr, nullptr)
+                           : launch_pair(*c, s, c->pair_rows, false, V0, V1, V2, V3, acc, make_double2(0, 0),
+                                         weight(c, 1), weight(c, 2), nullptr, nullptr);
+        return launch_iter(*c, s, (i & 1) ? V1 : V0, (i & 1) ? V0 : V1, acc, weight(c, 1));
+    };
+    if (e == hipSuccess) e = one(0);  // untimed: pages in code and caches
     if (e == hipSuccess) e = hipEventRecord(c->ev_a, s);
-    for (int i = 0; i < launches && e == hipSuccess; ++i)
-        e = launch_iter(*c, s, (i & 1) ? B : A, (i & 1) ? A : B, static_cast<double2 *>(acc.p),
-                        weight(c, 1));
+    for (int i = 0; i < launches && e == hipSuccess; ++i) e = one(i + 1);
     if (e == hipSuccess) e = hipEventRecord(c->ev_b, s);
     if (e == hipSuccess) e = hipEventSynchronize(c->ev_b);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev_a, c->ev_b);
-    release(acc);
+    release(scratch);
     if (e != hipSuccess) return hip_fail(c, e, "chebtd_time_recursion_kernel");
     *ms_per_launch = (double)ms / launches;
     return CHEBTD_OK;

@@ -228,6 +228,42 @@ def test_low_orders(torch, cheb, M):
 
 
 # ---------------------------------------------------------------------------
+# two orders per pass vs one order per pass
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("rows", ["1", "3", "8", "16", "200"])
+def test_two_orders_per_pass_matches_single_order_and_oracle(torch, cheb, rows, monkeypatch):
+    monkeypatch.setenv("CHEBTD_PAIR_ROWS", rows)
+    cases = [(honey_case(19, 211), 1.0), (honey_case(12, 130, "armchair"), 1.0),
+             (honey_case(1, 300), 1.0), (chain_case(9001), 0.002), (honey_case(64, 640), 1.4)]
+    for case, dt in cases:
+        H = case["H"]
+        emin, emax = H.gershgorin()
+        ctx = gpu_context(torch, cheb, case)
+        ctx.set_bounds(emin, emax)
+        M = ctx.plan(dt)
+        a = dev(torch, case["psi0"])
+        b = dev(torch, case["psi0"])
+        na = torch.zeros(3, dtype=torch.float64, device="cuda")
+        nb = torch.zeros(3, dtype=torch.float64, device="cuda")
+        say(f"[gpu] pairs rows={rows} {case['kind']} n={ctx.n} M={M}")
+        ctx.propagate(a, 3, na)
+        ctx.propagate(b, 3, nb, flags=cheb.SINGLE_ORDER)
+        torch.cuda.synchronize()
+        ref = O.propagate(H, O.Plan(emin, emax, dt), case["psi0"], 3)
+        assert rel_l2(host(a), ref) <= TOL
+        assert rel_l2(host(a), host(b)) <= 1e-13
+        np.testing.assert_allclose(host(na), host(nb), rtol=1e-13)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 5, 8, 9])
+def test_two_orders_per_pass_at_small_orders(torch, cheb, M):
+    for case in (honey_case(10, 300), chain_case(7000)):
+        _, psi, ref, nrm, rn, *_ = run_both(torch, cheb, case, 0.01, 3, flags=cheb.NO_CHECK, M=M)
+        assert rel_l2(psi, ref) <= TOL
+        np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
 # launch-mode equivalence, determinism, resume
 # ---------------------------------------------------------------------------
 def test_graph_replay_matches_direct_launches(torch, cheb):
