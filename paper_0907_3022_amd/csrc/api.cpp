@@ -80,9 +80,12 @@ int ensure_partials(Ctx *c)
     return ensure(c, c->partials, bytes, "partials");
 }
 
-// Rows per wavefront chunk of the two-orders-per-pass kernel: enough chunks
-// for about eight wavefronts per CU, at least eight rows (each chunk re-reads
-// two halo rows of v_k on either side).  CHEBTD_PAIR_ROWS overrides.
+// Rows per wavefront chunk of the two-orders-per-pass kernel.  Each
+// wavefront walks its chunk row by row with one row of loads in flight, so
+// short chunks (many wavefronts) hide memory latency best; each chunk also
+// re-reads two halo rows of v_k on either side.  Measured on MI355X: 2 rows
+// for ribbons up to 128 rows wide, 4 beyond (16M-64M sites).
+// CHEBTD_PAIR_ROWS overrides.
 int choose_pair_rows(const Ctx &c)
 {
     const char *env = std::getenv("CHEBTD_PAIR_ROWS");
@@ -90,14 +93,8 @@ int choose_pair_rows(const Ctx &c)
         const int r = std::atoi(env);
         if (r >= 1) return r;
     }
-    if (!pair_supported(c)) return 16;
-    const int64_t W = c.kind == HKind::Chain ? 1 : c.W;
-    const int64_t L = c.kind == HKind::Chain ? c.n : c.L;
-    const int64_t strips = (L + 61) / 62;
-    const int64_t target = 8 * (int64_t)c.num_cus;
-    const int64_t chunks = std::max<int64_t>(1, (target + strips - 1) / strips);
-    int64_t rows = std::max<int64_t>(8, (W + chunks - 1) / chunks);
-    return (int)std::min<int64_t>(rows, std::max<int64_t>(W, 1));
+    if (c.kind != HKind::Honeycomb) return 1;
+    return c.W <= 128 ? 2 : 4;
 }
 
 void invalidate_h(Ctx *c)

@@ -32,6 +32,14 @@ namespace {
 
 constexpr int kStrip = 62;
 
+// Component-wise select by value.  A ternary between two double2 objects can
+// make the compiler pick between their addresses, which sends them through
+// scratch memory; selecting the scalars keeps everything in registers.
+__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b)
+{
+    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
+
 __device__ __forceinline__ double2 shfl_up1(double2 v)
 {
     return make_double2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
@@ -65,35 +73,68 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
     if (chunk < op.nchunks) {  // uniform per wavefront
         const int32_t ys = chunk * op.rows;
         const int32_t ye = min(ys + op.rows, W);
+        // Loads are unconditional, from a clamped index, with the value selected
+        // afterwards: a conditional load of either memory or a local zero is
+        // turned into a flat load of a selected pointer, whose completion the
+        // cross-lane shuffles would then have to wait for.
         auto ld = [&](const double2 *v, int32_t r) -> double2 {
-            return (colok && r >= 0 && r < W) ? v[(int64_t)r * L + x] : zero;
+            const bool ok = colok && r >= 0 && r < W;
+            const double2 val = v[ok ? (int64_t)r * L + x : 0];
+            return csel(ok, val, zero);
         };
+        auto ld_on = [&](int32_t r) -> double {
+            const bool ok = colok && r >= 0 && r < W;
+            const double val = op.onsite[ok ? (int64_t)r * L + x : 0];
+            return ok ? val : 0.0;
+        };
+        // lanes 0 and 63 also need the v_k value just outside the strip
+        auto ld_ext = [&](int32_t r) -> double2 {
+            const int32_t xe = lane == 0 ? x - 1 : x + 1;
+            const bool ok = (lane == 0 || lane == 63) && r >= 0 && r < W && xe >= 0 && xe < L;
+            const double2 val = vk[ok ? (int64_t)r * L + xe : 0];
+            return csel(ok, val, zero);
+        };
+        // operands of row r (v_k row r+1, v_{k-1}, on-site and outside value of
+        // row r, acc of row r-1) are loaded one iteration ahead
         double2 a_m1 = ld(vk, ys - 2), a_0 = ld(vk, ys - 1);  // v_k rows r-1, r
-        double2 b_m2 = zero, b_m1 = zero;                     // v_{k+1} rows r-2, r-1
-        double e_m1 = 0.0;                                    // on-site term, row r-1
+        double2 a_p1 = ld(vk, ys);
+        double2 km1 = zero;
+        if (!HEAD) km1 = ld(vkm1, ys - 1);
+        double e_0 = ld_on(ys - 1);
+        double2 ext = ld_ext(ys - 1);
+        double2 accq = zero;
+        double2 b_m2 = zero, b_m1 = zero;  // v_{k+1} rows r-2, r-1
+        double e_m1 = 0.0;                 // on-site term, row r-1
         for (int32_t r = ys - 1; r <= ye; ++r) {
-            const double2 a_p1 = ld(vk, r + 1);
+            // prefetch row r+1
+            const double2 n_a = ld(vk, r + 2);
+            double2 n_km1 = zero;
+            if (!HEAD) n_km1 = ld(vkm1, r + 1);
+            const double n_e = ld_on(r + 1);
+            const double2 n_ext = ld_ext(r + 1);
+            double2 n_acc = zero;
+            if (!HEAD) {
+                const bool ok = own && r >= ys && r < ye;
+                const double2 val = acc[ok ? (int64_t)r * L + x : 0];
+                n_acc = csel(ok, val, zero);
+            }
+
             const bool rowok = r >= 0 && r < W;
             const int64_t ir = (int64_t)r * L + x;
             // ---- first order at row r: v_{k+1} = 2 H~ v_k - v_{k-1} ----
             double2 left = shfl_up1(a_0), right = shfl_down1(a_0);
-            if (lane == 0) left = (rowok && x - 1 >= 0 && x - 1 < L) ? vk[ir - 1] : zero;
-            if (lane == 63) right = (rowok && x + 1 >= 0 && x + 1 < L) ? vk[ir + 1] : zero;
+            left = csel(lane == 0, ext, left);
+            right = csel(lane == 63, ext, right);
             const bool even_r = ((x + r) & 1) == 0;
             double2 s;
             if (EDGE == CHEBTD_ZIGZAG)
-                s = cadd(cadd(left, right), even_r ? a_p1 : a_m1);
+                s = cadd(cadd(left, right), csel(even_r, a_p1, a_m1));
             else
-                s = cadd(cadd(a_m1, a_p1), even_r ? right : left);
-            const double e_0 = (colok && rowok) ? op.onsite[ir] : 0.0;
+                s = cadd(cadd(a_m1, a_p1), csel(even_r, right, left));
             const double d0 = op.s2 * (e_0 + op.dshift);
-            double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
-            double2 b_0;
-            if (HEAD)
-                b_0 = cscale(0.5, h);
-            else
-                b_0 = csub(h, (colok && rowok) ? vkm1[ir] : zero);
-            if (!(colok && rowok)) b_0 = zero;
+            const double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
+            double2 b_0 = HEAD ? cscale(0.5, h) : csub(h, km1);
+            b_0 = csel(colok && rowok, b_0, zero);
             if (own && r >= ys && r < ye) out1[ir] = b_0;
             // ---- second order at row q = r-1: v_{k+2} = 2 H~ v_{k+1} - v_k ----
             if (r - 1 >= ys) {
@@ -103,9 +144,9 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                 const bool even_q = ((x + q) & 1) == 0;
                 double2 s2;
                 if (EDGE == CHEBTD_ZIGZAG)
-                    s2 = cadd(cadd(l2, r2), even_q ? b_0 : b_m2);
+                    s2 = cadd(cadd(l2, r2), csel(even_q, b_0, b_m2));
                 else
-                    s2 = cadd(cadd(b_m2, b_0), even_q ? r2 : l2);
+                    s2 = cadd(cadd(b_m2, b_0), csel(even_q, r2, l2));
                 const double d1 = op.s2 * (e_m1 + op.dshift);
                 const double2 h2 = make_double2(fma(d1, b_m1.x, op.off2 * s2.x), fma(d1, b_m1.y, op.off2 * s2.y));
                 const double2 c = csub(h2, a_m1);
@@ -118,7 +159,7 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                         nrm += a_m1.x * a_m1.x + a_m1.y * a_m1.y;
                         en += a_m1.x * b_m1.x + a_m1.y * b_m1.y;
                     } else {
-                        a = acc[iq];
+                        a = accq;
                     }
                     a = cfma(g1, b_m1, a);
                     acc[iq] = cfma(g2, c, a);
@@ -126,9 +167,14 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
             }
             a_m1 = a_0;
             a_0 = a_p1;
+            a_p1 = n_a;
+            km1 = n_km1;
             b_m2 = b_m1;
             b_m1 = b_0;
             e_m1 = e_0;
+            e_0 = n_e;
+            ext = n_ext;
+            accq = n_acc;
         }
     }
     if (HEAD) {
