@@ -123,8 +123,11 @@ int chebtd_h_csr(chebtd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr_
  * Basis: phonon configurations ordered by total phonon number, then
  * lexicographically ascending in (n_1..n_L) (n_1 most significant); state
  * index = rank * L + electron site.  g_host, Delta_host: float64[L] host
- * arrays (copied).  The context builds the matrix on the host and owns the
- * device copy, plus the occupation tables used by chebtd_holstein_obs. */
+ * arrays (copied).  The operator is applied matrix-free (the memory-saving
+ * scheme of Sect. 3.3): the context builds on the host, and owns on the
+ * device, per-state tables of the raised and lowered phonon configuration
+ * and the site occupation (9 B per state) instead of the matrix; these also
+ * serve chebtd_holstein_obs.  L * C(L+nph, nph) must stay below 2^31. */
 int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0,
                       const double *g_host, const double *Delta_host, int periodic);
 

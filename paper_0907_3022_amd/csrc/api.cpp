@@ -157,7 +157,8 @@ int chebtd_destroy(chebtd_ctx *ctx)
     drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : {&c->vA, &c->vB, &c->vC, &c->vD, &c->partials, &c->results, &c->counter, &c->gamma_dev,
-                      &c->hol_rowptr, &c->hol_col, &c->hol_val, &c->hol_occ, &c->hol_up})
+                      &c->hol_occ, &c->hol_up, &c->hol_dn,
+                      &c->hol_tot, &c->hol_site})
         release(*b);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->ev_a) (void)hipEventDestroy(c->ev_a);
@@ -260,7 +261,7 @@ int chebtd_holstein_csr_host(int L, int nph, double t, double w0, const double *
 {
     HolsteinCsr h;
     std::string err;
-    int rc = holstein_build(L, nph, t, w0, g_host, Delta_host, periodic, false, h, err);
+    int rc = holstein_build(L, nph, t, w0, g_host, Delta_host, periodic, h, err);
     if (rc) return fail(nullptr, rc, err);
     if (n_out) *n_out = h.n;
     if (nnz_out) *nnz_out = h.nnz;
@@ -275,11 +276,9 @@ int chebtd_holstein_occupations(int L, int nph, int64_t *count_out, uint8_t *occ
     if (!count_out) return fail(nullptr, CHEBTD_E_ARG, "count_out is null");
     if (holstein_count(L, nph, count_out)) return fail(nullptr, CHEBTD_E_ARG, "bad L or nph");
     if (!occ) return CHEBTD_OK;
-    std::vector<double> z((size_t)L, 0.0);
-    HolsteinCsr h;
+    HolsteinTables h;
     std::string err;
-    // open chain, no couplings: only the occupation table is used
-    int rc = holstein_build(L, nph, 0.0, 0.0, z.data(), z.data(), 0, true, h, err);
+    int rc = holstein_tables(L, nph, 0, h, err);
     if (rc) return fail(nullptr, rc, err);
     std::memcpy(occ, h.occ.data(), h.occ.size());
     return CHEBTD_OK;
@@ -290,38 +289,47 @@ int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0, cons
 {
     if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
     Ctx *c = as_ctx(ctx);
-    HolsteinCsr h;
+    if (!g_host || !Delta_host || !std::isfinite(t) || !std::isfinite(w0))
+        return fail(c, CHEBTD_E_ARG, "chebtd_h_holstein: need g, Delta and finite t, w0");
+    for (int i = 0; i < L; ++i)
+        if (!std::isfinite(g_host[i]) || !std::isfinite(Delta_host[i]))
+            return fail(c, CHEBTD_E_ARG, "chebtd_h_holstein: g and Delta must be finite");
+    HolsteinTables h;
     std::string err;
-    int rc = holstein_build(L, nph, t, w0, g_host, Delta_host, periodic, true, h, err);
+    int rc = holstein_tables(L, nph, periodic, h, err);
     if (rc) return fail(c, rc, err);
     invalidate_h(c);
     c->kind = HKind::None;
-    if ((rc = ensure(c, c->hol_rowptr, h.rowptr.size() * sizeof(int64_t), "holstein rowptr")) ||
-        (rc = ensure(c, c->hol_col, h.col.size() * sizeof(int32_t), "holstein col")) ||
-        (rc = ensure(c, c->hol_val, h.val.size() * sizeof(double), "holstein val")) ||
+    // per-site constants: Delta_i, g_i w0, then sqrt(0 .. nph+1)
+    std::vector<double> site((size_t)(2 * L + nph + 2));
+    for (int i = 0; i < L; ++i) {
+        site[(size_t)i] = Delta_host[i];
+        site[(size_t)(L + i)] = g_host[i] * w0;
+    }
+    for (int q = 0; q <= nph + 1; ++q) site[(size_t)(2 * L + q)] = std::sqrt((double)q);
+    if ((rc = ensure(c, c->hol_up, h.up.size() * sizeof(int32_t), "holstein raise table")) ||
+        (rc = ensure(c, c->hol_dn, h.dn.size() * sizeof(int32_t), "holstein lower table")) ||
         (rc = ensure(c, c->hol_occ, h.occ.size(), "holstein occupations")) ||
-        (rc = ensure(c, c->hol_up, h.up.size() * sizeof(int32_t), "holstein raise table")))
+        (rc = ensure(c, c->hol_tot, h.tot.size(), "holstein totals")) ||
+        (rc = ensure(c, c->hol_site, site.size() * sizeof(double), "holstein site constants")))
         return rc;
-    hipError_t e = hipMemcpy(c->hol_rowptr.p, h.rowptr.data(), h.rowptr.size() * sizeof(int64_t),
-                             hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(c->hol_up.p, h.up.data(), h.up.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->hol_col.p, h.col.data(), h.col.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(c->hol_val.p, h.val.data(), h.val.size() * sizeof(double), hipMemcpyHostToDevice);
+        e = hipMemcpy(c->hol_dn.p, h.dn.data(), h.dn.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->hol_occ.p, h.occ.data(), h.occ.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->hol_tot.p, h.tot.data(), h.tot.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(c->hol_up.p, h.up.data(), h.up.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        e = hipMemcpy(c->hol_site.p, site.data(), site.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(c, e, "chebtd_h_holstein upload");
-    c->kind = HKind::Csr;
+    c->kind = HKind::Holstein;
     c->n = h.n;
-    c->nnz = h.nnz;
-    c->rowptr = static_cast<const int64_t *>(c->hol_rowptr.p);
-    c->col = static_cast<const int32_t *>(c->hol_col.p);
-    c->val = static_cast<const double *>(c->hol_val.p);
     c->holstein = true;
     c->hol_L = L;
     c->hol_nph = nph;
     c->hol_nconf = h.nconf;
+    c->hol_t = t;
+    c->hol_w0 = w0;
+    c->hol_periodic = periodic ? 1 : 0;
     return ensure_partials(c);
 }
 

@@ -146,6 +146,59 @@ struct CsrRow {
     }
 };
 
+// Matrix-free Holstein rows (eq. (ghm)); state i = r*L + site.
+struct HolRow {
+    __device__ static __forceinline__ int64_t row(const OpHol &op)
+    {
+        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        return i < op.n ? i : -1;
+    }
+    __device__ static __forceinline__ double2 apply2(const OpHol &op, int64_t i, const double2 *v, double2 vi)
+    {
+        // n < 2^31, so 32-bit division suffices
+        const uint32_t ui = (uint32_t)i, L = (uint32_t)op.L;
+        const uint32_t r = ui / L, site = ui - r * L;
+        const double diag = op.Delta[site] + op.w0 * (double)op.tot[r];
+        // electron hops to the neighbouring sites
+        double hx = 0.0, hy = 0.0;
+        const bool has_l = op.periodic || site > 0, has_r = op.periodic || site + 1 < L;
+        const uint32_t sl = site == 0 ? L - 1 : site - 1, sr = site + 1 == L ? 0 : site + 1;
+        const uint32_t base = r * L;
+        if (has_l) {
+            const double2 u = v[base + sl];
+            hx += u.x;
+            hy += u.y;
+        }
+        if (has_r) {
+            const double2 u = v[base + sr];
+            hx += u.x;
+            hy += u.y;
+        }
+        // phonon creation/annihilation at the electron's site
+        const int32_t ru = op.up[i], rd = op.dn[i];
+        const uint32_t ni = op.occ[i];
+        double px = 0.0, py = 0.0;
+        if (ru >= 0) {
+            const double2 u = v[(uint32_t)ru * L + site];
+            const double w = op.sq[ni + 1];
+            px = fma(w, u.x, px);
+            py = fma(w, u.y, py);
+        }
+        if (rd >= 0) {
+            const double2 u = v[(uint32_t)rd * L + site];
+            const double w = op.sq[ni];
+            px = fma(w, u.x, px);
+            py = fma(w, u.y, py);
+        }
+        const double gw = op.gw0[site];
+        // (H v)_i = diag v_i - t (hops) - g_i w0 (phonon terms); return (2/a)(H - b) v
+        const double d = diag - op.b;
+        const double hvx = fma(d, vi.x, fma(-op.t, hx, -gw * px));
+        const double hvy = fma(d, vi.y, fma(-op.t, hy, -gw * py));
+        return make_double2(op.s2 * hvx, op.s2 * hvy);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Host-side construction of the operator parameters from the context
 // ---------------------------------------------------------------------------
@@ -171,6 +224,27 @@ inline OpHoney make_honey(const Ctx &c)
     op.L = (int32_t)c.L;
     op.xblocks = (int32_t)((c.L + kBlock - 1) / kBlock);
     op.xcd_remap = 1;
+    return op;
+}
+
+inline OpHol make_hol(const Ctx &c)
+{
+    OpHol op;
+    op.up = static_cast<const int32_t *>(c.hol_up.p);
+    op.dn = static_cast<const int32_t *>(c.hol_dn.p);
+    op.occ = static_cast<const uint8_t *>(c.hol_occ.p);
+    op.tot = static_cast<const uint8_t *>(c.hol_tot.p);
+    const double *site = static_cast<const double *>(c.hol_site.p);
+    op.Delta = site;
+    op.gw0 = site + c.hol_L;
+    op.sq = site + 2 * c.hol_L;
+    op.w0 = c.hol_w0;
+    op.t = c.hol_t;
+    op.b = c.b;
+    op.s2 = 2.0 / c.a;
+    op.L = c.hol_L;
+    op.periodic = c.hol_periodic;
+    op.n = c.n;
     return op;
 }
 

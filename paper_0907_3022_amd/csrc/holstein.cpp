@@ -11,6 +11,7 @@
 //   C(r_j + m_j, m_j) - C(r_j - n_j + m_j, m_j),
 // with r_j the phonons left for positions j..L and m_j = L - j parts after j.
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -83,7 +84,92 @@ bool next_config(uint8_t *n, int L, int nph)
     return true;
 }
 
+// Configuration of rank `r` (inverse of rank_of).
+void unrank(const Binom &C, int64_t r, uint8_t *n, int L, int nph)
+{
+    int T = 0;
+    while (T < nph && C(T + L, L) <= r) ++T;  // C(T+L, L) = configurations of total <= T
+    int64_t within = r - (T == 0 ? 0 : C(T - 1 + L, L));
+    int left = T;
+    for (int j = 0; j + 1 < L; ++j) {
+        const int m = L - 1 - j;
+        const int64_t all = C(left + m, m);
+        int v = 0;
+        // largest v whose preceding count fits in `within`
+        while (v < left && all - C(left - (v + 1) + m, m) <= within) ++v;
+        within -= all - C(left - v + m, m);
+        n[j] = (uint8_t)v;
+        left -= v;
+    }
+    n[L - 1] = (uint8_t)left;
+}
+
 }  // namespace
+
+int holstein_tables(int L, int nph, int periodic, HolsteinTables &out, std::string &err)
+{
+    if (L < 1 || L > 64 || nph < 0 || nph > 254) {
+        err = "holstein: need 1 <= L <= 64 and 0 <= nph <= 254";
+        return CHEBTD_E_ARG;
+    }
+    if (periodic && L < 3) {
+        err = "holstein: a ring needs L >= 3";
+        return CHEBTD_E_ARG;
+    }
+    Binom C(L + nph + 1, L);
+    if (!C.ok) {
+        err = "holstein: basis too large";
+        return CHEBTD_E_ARG;
+    }
+    const int64_t nconf = C(L + nph, L);
+    const int64_t n = nconf * (int64_t)L;
+    if (n >= (int64_t)INT32_MAX) {
+        err = "holstein: dimension exceeds 2^31 - 1";
+        return CHEBTD_E_ARG;
+    }
+    out.L = L;
+    out.nph = nph;
+    out.nconf = nconf;
+    out.n = n;
+    out.up.assign((size_t)n, -1);
+    out.dn.assign((size_t)n, -1);
+    out.occ.assign((size_t)n, 0);
+    out.tot.assign((size_t)nconf, 0);
+    // configurations are independent: split the rank range over host threads
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (nconf < 4096) nt = 1;
+    std::vector<std::thread> pool;
+    for (unsigned tix = 0; tix < nt; ++tix) {
+        const int64_t r0 = nconf * tix / nt, r1 = nconf * (tix + 1) / nt;
+        pool.emplace_back([&, r0, r1]() {
+            std::vector<uint8_t> cfg((size_t)L), tmp((size_t)L);
+            if (r0 >= r1) return;
+            unrank(C, r0, cfg.data(), L, nph);
+            for (int64_t r = r0; r < r1; ++r) {
+                int T = 0;
+                for (int j = 0; j < L; ++j) T += cfg[(size_t)j];
+                out.tot[(size_t)r] = (uint8_t)T;
+                for (int i = 0; i < L; ++i) {
+                    const size_t row = (size_t)(r * L + i);
+                    out.occ[row] = cfg[(size_t)i];
+                    if (T < nph) {
+                        tmp = cfg;
+                        tmp[(size_t)i]++;
+                        out.up[row] = (int32_t)rank_of(C, tmp.data(), L);
+                    }
+                    if (cfg[(size_t)i] > 0) {
+                        tmp = cfg;
+                        tmp[(size_t)i]--;
+                        out.dn[row] = (int32_t)rank_of(C, tmp.data(), L);
+                    }
+                }
+                if (r + 1 < r1) next_config(cfg.data(), L, nph);
+            }
+        });
+    }
+    for (auto &th : pool) th.join();
+    return CHEBTD_OK;
+}
 
 int holstein_count(int L, int nph, int64_t *count)
 {
@@ -95,7 +181,7 @@ int holstein_count(int L, int nph, int64_t *count)
 }
 
 int holstein_build(int L, int nph, double t, double w0, const double *g, const double *Delta,
-                   int periodic, bool want_tables, HolsteinCsr &out, std::string &err)
+                   int periodic, HolsteinCsr &out, std::string &err)
 {
     if (L < 1 || L > 64 || nph < 0 || nph > 255) {
         err = "holstein: need 1 <= L <= 64 and 0 <= nph <= 255";
@@ -127,10 +213,6 @@ int holstein_build(int L, int nph, double t, double w0, const double *g, const d
     out.val.clear();
     out.col.reserve((size_t)n * 5);
     out.val.reserve((size_t)n * 10);
-    if (want_tables) {
-        out.occ.assign((size_t)nconf * L, 0);
-        out.up.assign((size_t)nconf * L, -1);
-    }
     std::vector<uint8_t> cfg((size_t)L, 0), tmp((size_t)L);
     struct Entry {
         int64_t c;
@@ -141,7 +223,6 @@ int holstein_build(int L, int nph, double t, double w0, const double *g, const d
     do {
         int T = 0;
         for (int j = 0; j < L; ++j) T += cfg[(size_t)j];
-        if (want_tables) std::memcpy(&out.occ[(size_t)r * L], cfg.data(), (size_t)L);
         for (int i = 0; i < L; ++i) {
             const int64_t rowi = r * L + i;
             int cnt = 0;
@@ -158,7 +239,6 @@ int holstein_build(int L, int nph, double t, double w0, const double *g, const d
                 tmp[(size_t)i]++;
                 const int64_t ru = rank_of(C, tmp.data(), L);
                 row[cnt++] = {ru * L + i, -g[i] * w0 * std::sqrt((double)cfg[(size_t)i] + 1.0)};
-                if (want_tables) out.up[(size_t)r * L + i] = (int32_t)ru;
             }
             if (cfg[(size_t)i] > 0) {
                 tmp = cfg;

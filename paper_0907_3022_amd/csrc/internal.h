@@ -35,6 +35,22 @@ struct OpHoney {
     int32_t xcd_remap;  // 1: map blocks XCD-contiguously
 };
 
+// Matrix-free Holstein operator, eq. (ghm): per state (r, i) the raised and
+// lowered phonon configurations of site i and its occupation, per
+// configuration the total phonon number.
+struct OpHol {
+    const int32_t *up;     // rank of n + e_i, or -1     [state]
+    const int32_t *dn;     // rank of n - e_i, or -1     [state]
+    const uint8_t *occ;    // n_i                        [state]
+    const uint8_t *tot;    // sum_j n_j                  [configuration]
+    const double *Delta;   // Delta_i                    [site]
+    const double *gw0;     // g_i w0                     [site]
+    const double *sq;      // sqrt(0 .. nph+1)
+    double w0, t, b, s2;
+    int32_t L, periodic;
+    int64_t n;
+};
+
 struct OpCsr {
     const int64_t *rowptr;
     const int32_t *col;
@@ -47,7 +63,7 @@ struct OpCsr {
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
-enum class HKind { None = 0, Chain, Honeycomb, Csr };
+enum class HKind { None = 0, Chain, Honeycomb, Csr, Holstein };
 
 struct DevBuf {
     void *p = nullptr;
@@ -83,7 +99,11 @@ struct Ctx {
     bool holstein = false;
     int hol_L = 0, hol_nph = 0;
     int64_t hol_nconf = 0;
-    DevBuf hol_rowptr, hol_col, hol_val, hol_occ, hol_up;
+    // matrix-free tables (per state: up, dn, occ; per configuration: tot) and
+    // per-site constants (Delta, g w0, then the sqrt table)
+    DevBuf hol_occ, hol_up, hol_dn, hol_tot, hol_site;
+    int hol_periodic = 0;
+    double hol_t = 0.0, hol_w0 = 0.0;
 
     // bounds and plan
     bool has_bounds = false;
@@ -130,12 +150,18 @@ struct HolsteinCsr {
     std::vector<int64_t> rowptr;
     std::vector<int32_t> col;
     std::vector<double> val;  // complex interleaved
-    std::vector<uint8_t> occ;
-    std::vector<int32_t> up;  // rank of n + e_i, or -1
 };
+struct HolsteinTables {
+    int L = 0, nph = 0;
+    int64_t nconf = 0, n = 0;
+    std::vector<int32_t> up, dn;  // per state
+    std::vector<uint8_t> occ;     // per state
+    std::vector<uint8_t> tot;     // per configuration
+};
+int holstein_tables(int L, int nph, int periodic, HolsteinTables &out, std::string &err);
 int holstein_count(int L, int nph, int64_t *count);
 int holstein_build(int L, int nph, double t, double w0, const double *g, const double *Delta,
-                   int periodic, bool want_tables, HolsteinCsr &out, std::string &err);
+                   int periodic, HolsteinCsr &out, std::string &err);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All enqueue on `s` and return hipError_t.

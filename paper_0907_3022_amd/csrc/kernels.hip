@@ -77,6 +77,20 @@ __global__ __launch_bounds__(kBlock) void k_head_honey(OpHoney op, const double2
     head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
 }
 
+__global__ __launch_bounds__(kBlock) void k_head_hol(OpHol op, const double2 *__restrict__ v0,
+                                                     double2 *__restrict__ v1,
+                                                     double2 *__restrict__ acc, double2 g0,
+                                                     double2 g1, double2 *ckpt, double *partials)
+{
+    const int64_t i = HolRow::row(op);
+    double2 vi = make_double2(0.0, 0.0), h2 = vi;
+    if (i >= 0) {
+        vi = v0[i];
+        h2 = HolRow::apply2(op, i, v0, vi);
+    }
+    head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
+}
+
 __global__ __launch_bounds__(kBlock) void k_head_csr(OpCsr op, const double2 *__restrict__ v0,
                                                      double2 *__restrict__ v1,
                                                      double2 *__restrict__ acc, double2 g0,
@@ -123,6 +137,16 @@ __global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2
     if (i < 0) return;
     const double2 vi = vk[i];
     iter_body(i, HoneyRow<EDGE>::apply2(op, i, x, y, vk, vi), vprev, acc, g);
+}
+
+__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, const double2 *__restrict__ vk,
+                                                     double2 *vprev, double2 *__restrict__ acc,
+                                                     double2 g)
+{
+    const int64_t i = HolRow::row(op);
+    if (i < 0) return;
+    const double2 vi = vk[i];
+    iter_body(i, HolRow::apply2(op, i, vk, vi), vprev, acc, g);
 }
 
 __global__ __launch_bounds__(kBlock) void k_iter_csr(OpCsr op, const double2 *__restrict__ vk,
@@ -310,7 +334,8 @@ __device__ __forceinline__ void block_minmax(double &lo, double &hi, double *lds
 }
 
 struct GershSrc {
-    int kind;  // 0 chain, 1 honeycomb zigzag, 2 honeycomb armchair, 3 csr
+    int kind;  // 0 chain, 1 honeycomb zigzag, 2 honeycomb armchair, 3 csr, 4 Holstein tables
+    OpHol hol;
     int64_t n;
     const double *onsite;  // V or eps
     double dx;
@@ -346,6 +371,16 @@ __global__ __launch_bounds__(kBlock) void k_gersh(GershSrc g, double *partials)
             }
             d = g.onsite[i];
             for (int q = 0; q < nb; ++q) r += fabs(g.t);
+        } else if (g.kind == 4) {
+            const OpHol &h = g.hol;
+            const uint32_t L = (uint32_t)h.L, cfg = (uint32_t)i / L, site = (uint32_t)i - cfg * L;
+            d = h.Delta[site] + h.w0 * (double)h.tot[cfg];
+            const int hops = h.periodic ? 2 : (site > 0) + (site + 1 < L);
+            r = hops * fabs(h.t);
+            const uint32_t ni = h.occ[i];
+            const double gw = fabs(h.gw0[site]);
+            if (h.up[i] >= 0) r += gw * h.sq[ni + 1];
+            if (h.dn[i] >= 0) r += gw * h.sq[ni];
         } else {
             for (int64_t p = g.rowptr[i]; p < g.rowptr[i + 1]; ++p) {
                 const double2 h = g.val[p];
@@ -580,6 +615,10 @@ hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *
         hipLaunchKernelGGL(k_head_csr, grid, block, 0, s, make_csr(c), v0, v1, acc, g0, g1, ckpt,
                            partials);
         break;
+    case HKind::Holstein:
+        hipLaunchKernelGGL(k_head_hol, grid, block, 0, s, make_hol(c), v0, v1, acc, g0, g1, ckpt,
+                           partials);
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -604,6 +643,9 @@ hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *
         break;
     case HKind::Csr:
         hipLaunchKernelGGL(k_iter_csr, grid, block, 0, s, make_csr(c), vk, vprev, acc, g);
+        break;
+    case HKind::Holstein:
+        hipLaunchKernelGGL(k_iter_hol, grid, block, 0, s, make_hol(c), vk, vprev, acc, g);
         break;
     default:
         return hipErrorInvalidValue;
@@ -691,6 +733,10 @@ hipError_t launch_gershgorin(const Ctx &c, hipStream_t s, double *partials, doub
         g.rowptr = c.rowptr;
         g.col = c.col;
         g.val = reinterpret_cast<const double2 *>(c.val);
+        break;
+    case HKind::Holstein:
+        g.kind = 4;
+        g.hol = make_hol(c);
         break;
     default:
         return hipErrorInvalidValue;

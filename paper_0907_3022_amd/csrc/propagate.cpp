@@ -287,10 +287,11 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
     if (launches < 1 || !ms_per_launch) return fail(c, CHEBTD_E_ARG, "need launches >= 1 and an output");
     const bool pairs = c->use_pairs && !(flags & CHEBTD_SINGLE_ORDER);
     static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr",
-                                  "k_pair<0,false>", "k_pair<1,false>"};
+                                  "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol"};
     const char *nm = pairs ? (c->kind == HKind::Honeycomb && c->edge == CHEBTD_ARMCHAIR ? names[5] : names[4])
-                     : c->kind == HKind::Chain ? names[0]
-                     : c->kind == HKind::Csr   ? names[3]
+                     : c->kind == HKind::Chain    ? names[0]
+                     : c->kind == HKind::Csr      ? names[3]
+                     : c->kind == HKind::Holstein ? names[6]
                      : (c->edge == CHEBTD_ZIGZAG ? names[1] : names[2]);
     if (name_out) *name_out = nm;
     if (orders_out) *orders_out = pairs ? 2 : 1;

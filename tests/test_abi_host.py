@@ -72,6 +72,15 @@ def test_host_holstein_builder_matches_oracle(L_sites, nph, periodic):
                                   O.holstein_occupations(L_sites, nph))
 
 
+@pytest.mark.parametrize("L_sites,nph", [(10, 6), (7, 9), (1, 40)])
+def test_host_holstein_tables_match_oracle_order(L_sites, nph):
+    # large enough that the library splits the basis over host threads and
+    # starts each thread by unranking
+    from paper_0907_3022_amd import holstein_occupations
+    np.testing.assert_array_equal(holstein_occupations(L_sites, nph),
+                                  O.holstein_occupations(L_sites, nph))
+
+
 def test_host_holstein_config3_dimension_and_nnz():
     from paper_0907_3022_amd import holstein_csr_host
     rowptr, col, val = holstein_csr_host(10, 10, 1.0, 1.0, np.sqrt(0.5), 0.0, True)

@@ -184,6 +184,34 @@ def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic):
     np.testing.assert_allclose(chi, rchi, rtol=1e-11, atol=1e-14)
 
 
+def test_holstein_matrix_free_matches_csr_path(torch, cheb):
+    # the matrix-free Holstein operator and the general CSR kernel on the
+    # library's own host-built CSR of the same eq. (ghm) matrix
+    L, nph = 6, 5
+    g = np.linspace(0.4, 1.1, L)
+    Delta = np.linspace(-0.3, 0.4, L)
+    for periodic in (True, False):
+        rowptr, col, val = cheb.holstein_csr_host(L, nph, 1.0, 1.3, g, Delta, periodic)
+        mf = cheb.Context()
+        mf.holstein(L, nph, 1.0, 1.3, g, Delta, periodic)
+        cs = cheb.Context()
+        r_d, c_d, v_d = dev(torch, rowptr), dev(torch, col), dev(torch, val)
+        cs.csr(r_d, c_d, v_d)
+        lo, hi = mf.gershgorin()
+        lo2, hi2 = cs.gershgorin()
+        assert lo == pytest.approx(lo2, rel=1e-14) and hi == pytest.approx(hi2, rel=1e-14)
+        psi0 = W.holstein_packet(L, mf.n // L, 2.0, 1.0, 0.5)
+        outs = []
+        for ctx in (mf, cs):
+            ctx.set_bounds(lo, hi)
+            ctx.plan(0.3)
+            p = dev(torch, psi0)
+            ctx.propagate(p, 6)
+            torch.cuda.synchronize()
+            outs.append(host(p))
+        assert rel_l2(outs[0], outs[1]) <= 1e-13
+
+
 def test_generic_csr_parity(torch, cheb):
     # a complex Hermitian matrix through chebtd_h_csr (device CSR from the caller)
     rng = np.random.default_rng(3)
