@@ -38,6 +38,7 @@ PAIR_BYTES = 104         # per site and two orders: v_{k-1}, v_k, on-site, acc r
 CSR_VEC_BYTES = 80       # vector traffic per row and order for CSR
 CSR_NNZ_BYTES = 20       # complex128 value + int32 column
 CSR_ROW_BYTES = 8        # rowptr
+HOL_CSR_BYTES = CSR_VEC_BYTES + 4 * CSR_NNZ_BYTES + CSR_ROW_BYTES  # the same rows stored as CSR
 
 
 def log(msg):
@@ -174,16 +175,62 @@ def bench_holstein(torch, P, K):
         psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
         t = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
         ms_iter, kname, _ = ctx.time_recursion_kernel(100)
-        nnz_row = 4.0
-        bytes_row = CSR_VEC_BYTES + nnz_row * CSR_NNZ_BYTES + CSR_ROW_BYTES
+        # matrix-free rows: the vectors plus the raise/lower tables (2 x int32),
+        # the occupation (uint8) and the configuration total (uint8 per L rows)
+        bytes_row = CSR_VEC_BYTES + 4 + 4 + 1 + 1.0 / p["L"]
         n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
         out[f"g2={g2}"] = dict(n=n, M=M, steps=K, seconds=t, hv_per_s=K * M / t,
                                kernel=kname, kernel_ms=ms_iter,
                                kernel_GBs=bytes_row * n / (ms_iter * 1e-3) / 1e9,
                                bytes_per_row_order=bytes_row,
+                               csr_bytes_per_row_order=HOL_CSR_BYTES,
                                total_phonons=float(nph_i.sum()), electron_density_sum=float(n_i.sum()))
         ctx.close()
     return out
+
+
+def bench_polaron_paper(torch, P):
+    """Sect. 3.3 / Fig. 3 at the paper's size: D = 622,751,220 states, the
+    matrix-free Holstein operator, observables at the figure's times."""
+    p = W.POLARON_PAPER.params
+    L = p["L"]
+    g, Delta = W.polaron_couplings(L, p["w0"], p["eps_p"], p["eps_p_barrier"], p["barrier_site"],
+                                   p["barrier"])
+    t0 = time.perf_counter()
+    ctx = P.Context()
+    ctx.holstein(L, p["nph"], p["t"], p["w0"], g, Delta, False)
+    build_s = time.perf_counter() - t0
+    n = ctx.n
+    psi = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    # bare electron packet with the phonon vacuum (configuration rank 0)
+    psi[:L] = torch.from_numpy(W.holstein_packet(L, 1, p["packet_site"], p["width"], p["k"])[:L]).cuda()
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi)
+    M = ctx.plan(p["dt"])
+    snaps = []
+    t_prev, run_s = 0.0, 0.0
+    n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
+    snaps.append(dict(t=0.0, n=n_i.round(6).tolist(), nph=nph_i.round(6).tolist(), chi=chi.round(6).tolist()))
+    norms = []
+    for ts in p["snapshots"]:
+        K = int(round((ts - t_prev) / p["dt"]))
+        nrm = torch.zeros(K, dtype=torch.float64, device="cuda")
+        run_s += timed(torch, lambda: ctx.propagate(psi, K, nrm, None, 0))
+        norms.append(float(nrm.max().item()))
+        t_prev = ts
+        n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
+        snaps.append(dict(t=ts, n=n_i.round(6).tolist(), nph=nph_i.round(6).tolist(),
+                          chi=chi.round(6).tolist(), sum_n=float(n_i.sum())))
+    ms_iter, kname, _ = ctx.time_recursion_kernel(10)
+    orders = int(round(p["snapshots"][-1] / p["dt"])) * M
+    bytes_row = CSR_VEC_BYTES + 4 + 4 + 1 + 1.0 / L
+    ctx.close()
+    del psi
+    torch.cuda.empty_cache()
+    return dict(workload="polaron_L18_nph11", states=n, M=M, dt=p["dt"], build_seconds=build_s,
+                propagate_seconds=run_s, orders=orders, hv_per_s=orders / run_s,
+                kernel=kname, kernel_ms=ms_iter, kernel_GBs=bytes_row * n / (ms_iter * 1e-3) / 1e9,
+                device_GB=(3 * 16 + 9) * n / 1e9, snapshots=snaps, max_norm_deviation=max(abs(x - 1) for x in norms))
 
 
 def bench_sweep(torch, P, sizes):
@@ -346,7 +393,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--sections", default="main,double_well,holstein,batched,adjoint,sweep,cpu")
+    ap.add_argument("--sections", default="main,double_well,holstein,batched,adjoint,polaron,sweep,cpu")
     ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -413,6 +460,9 @@ def main():
     if "adjoint" in sections:
         log("[bench] adjoint, 100 steps, order ~64")
         extra["adjoint"] = bench_adjoint(torch, P, W.ADJOINT.params["K"])
+    if "polaron" in sections:
+        log("[bench] polaron at the paper's size (D = 622,751,220)")
+        extra["polaron_paper"] = bench_polaron_paper(torch, P)
     if "sweep" in sections:
         log("[bench] ribbon size sweep")
         extra["sweep"] = bench_sweep(torch, P, [(128, 8192), (256, 16384), (512, 32768), (1024, 65536)])

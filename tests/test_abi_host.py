@@ -81,6 +81,18 @@ def test_host_holstein_tables_match_oracle_order(L_sites, nph):
                                   O.holstein_occupations(L_sites, nph))
 
 
+def test_paper_scale_polaron_dimension(golden_dir):
+    # Sect. 3.3: 18 sites, at most 11 phonons -> D = 6.2e8
+    import ctypes as C
+    import json
+    L, lib = _lib()
+    g = json.load(open(os.path.join(golden_dir, "paper_values.json")))["polaron"]
+    cnt = C.c_int64()
+    assert lib.chebtd_holstein_occupations(g["L"], g["nph"], C.byref(cnt), None) == L.OK
+    assert cnt.value * g["L"] == 622_751_220
+    assert float(f"{cnt.value * g['L']:.2g}") == g["D_tot"]
+
+
 def test_host_holstein_config3_dimension_and_nnz():
     from paper_0907_3022_amd import holstein_csr_host
     rowptr, col, val = holstein_csr_host(10, 10, 1.0, 1.0, np.sqrt(0.5), 0.0, True)

@@ -184,6 +184,28 @@ def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic):
     np.testing.assert_allclose(chi, rchi, rtol=1e-11, atol=1e-14)
 
 
+def test_polaron_figure3_parameters_reduced(torch, cheb):
+    # the Fig. 3 setting (open chain, barrier with extra local coupling, packet
+    # moving right with k = pi/9) on 12 sites with at most 5 phonons
+    p = W.POLARON_PAPER.params
+    L, nph = 12, 5
+    g, Delta = W.polaron_couplings(L, p["w0"], p["eps_p"], p["eps_p_barrier"], 8, p["barrier"])
+    H = O.holstein(L, nph, p["t"], p["w0"], g, Delta, False)
+    psi0 = W.holstein_packet(L, O.holstein_nconf(L, nph), p["packet_site"], p["width"], p["k"])
+    emin, emax = H.gershgorin()
+    ctx = cheb.Context()
+    ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, False)
+    ctx.set_bounds(emin, emax)
+    assert ctx.plan(p["dt"]) == O.Plan(emin, emax, p["dt"]).M
+    psi = dev(torch, psi0)
+    ctx.propagate(psi, 12)
+    torch.cuda.synchronize()
+    ref = O.propagate(H, O.Plan(emin, emax, p["dt"]), psi0, 12)
+    assert rel_l2(host(psi), ref) <= TOL
+    for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
+        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+
+
 def test_holstein_matrix_free_matches_csr_path(torch, cheb):
     # the matrix-free Holstein operator and the general CSR kernel on the
     # library's own host-built CSR of the same eq. (ghm) matrix

@@ -172,6 +172,14 @@ GRAPHENE = Workload("zigzag_ribbon_128x8192", dict(width=128, length=8192, edge=
 HOLSTEIN = Workload("holstein_ring_L10_nph10", dict(L=10, nph=10, t=1.0, w0=1.0, g2=(0.5, 2.0),
                                                     periodic=True, dt=0.1, K=500))
 BATCHED = Workload("batched_256_ribbons", dict(nsys=256, seed_base=1000, dt=1.0, K=200))
+# Sect. 3.3 / Fig. 3: open 18-site chain, at most 11 phonons (D = 622,751,220),
+# eps_p = 1, w0 = 2 (g = sqrt(eps_p / w0)), barrier Delta = 2 at site 12 with an
+# extra local coupling eps_p,12 there, packet around site 4 moving with k = pi/9.
+# Not printed, chosen here: eps_p,12 = eps_p, packet width 2 sites, dt = 0.5.
+POLARON_PAPER = Workload("polaron_L18_nph11", dict(L=18, nph=11, t=1.0, w0=2.0, eps_p=1.0,
+                                                   eps_p_barrier=1.0, barrier_site=11,
+                                                   barrier=2.0, packet_site=3, k=math.pi / 9,
+                                                   width=2.0, dt=0.5, snapshots=(6.0, 10.0, 14.0)))
 ADJOINT = Workload("adjoint_transmission", dict(n1d=65536, width=256, length=4096, W=0.5, K=100,
                                                 order=64, fd_sites=32, h=1e-6))
 
@@ -189,6 +197,18 @@ def double_well_inputs(n: int = 4096, xmin: float = -20.0, xmax: float = 20.0, a
                        b: float = 5.0, x0: float = -5.0, sigma: float = 1.0, k0: float = 1.0):
     x, dx = chain_grid(n, xmin, xmax)
     return x, dx, quartic_well(x, a, b), gaussian_1d(x, x0, sigma, k0)
+
+
+def polaron_couplings(L: int, w0: float, eps_p: float, eps_p_barrier: float, barrier_site: int,
+                      barrier: float):
+    """(g_i, Delta_i) of eq. (ghm): g_i = sqrt((eps_p + eps_p,i)/w0), with the
+    extra coupling and the barrier potential only on `barrier_site`."""
+    extra = np.zeros(L)
+    extra[barrier_site] = eps_p_barrier
+    g = np.sqrt((eps_p + extra) / w0)
+    Delta = np.zeros(L)
+    Delta[barrier_site] = barrier
+    return g, Delta
 
 
 def fd_sites(n: int, count: int, seed: int, candidates=None) -> np.ndarray:
