@@ -136,7 +136,7 @@ int holstein_tables(int L, int nph, int periodic, HolsteinTables &out, std::stri
     out.occ.assign((size_t)n, 0);
     out.tot.assign((size_t)nconf, 0);
     // configurations are independent: split the rank range over host threads
-    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     if (nconf < 4096) nt = 1;
     std::vector<std::thread> pool;
     for (unsigned tix = 0; tix < nt; ++tix) {
