@@ -193,6 +193,18 @@ int chebtd_get_plan(const chebtd_ctx *ctx, double *gamma_host, double *a, double
 int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_dev,
                      double *energy_dev, unsigned flags);
 
+/* Time-dependent on-site term (Sect. 2.2: for a time-dependent H the
+ * variation of H(t) bounds the step).  H is held constant within each step at
+ * the caller's values for that step -- taking them at the step's midpoint
+ * makes the scheme second order in dt.  onsite_dev + s*stride (float64)
+ * holds, for step s = 0..K-1, V (chain, n values), eps (ribbon, n values) or
+ * Delta_i (Holstein, L values); the rest of H is the one built.  The bounds
+ * and the plan stay fixed, so they must enclose the spectrum of every step's
+ * H.  One launch sequence per step (no graph, no persistent kernel, no
+ * checkpoints); norm_dev, energy_dev and flags as chebtd_propagate. */
+int chebtd_propagate_td(chebtd_ctx *ctx, double *psi_dev, int64_t K, const double *onsite_dev,
+                        int64_t stride, double *norm_dev, double *energy_dev, unsigned flags);
+
 /* Relative norm tolerance of the end-of-call check (default 1e-6). */
 int chebtd_set_check_tol(chebtd_ctx *ctx, double rel_tol);
 

@@ -65,6 +65,8 @@ _SIGS = {
                                   C.POINTER(C.c_int)]),
     "chebtd_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                    C.c_uint]),
+    "chebtd_propagate_td": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                      C.c_void_p, C.c_void_p, C.c_uint]),
     "chebtd_set_check_tol": (C.c_int, [C.c_void_p, C.c_double]),
     "chebtd_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "chebtd_region_sum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

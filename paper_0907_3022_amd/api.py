@@ -186,6 +186,24 @@ class Context:
         self._check(self._lib.chebtd_propagate(self.h, p, int(K), pn, pe, int(flags)))
         return psi
 
+    def propagate_td(self, psi, onsite, norm=None, energy=None, flags: int = 0):
+        """K = onsite.shape[0] steps; onsite[s] is the step's V (chain), eps
+        (ribbon) or Delta (Holstein)."""
+        torch = _torch()
+        if onsite.dim() != 2:
+            raise ValueError("onsite must be (K, values per step)")
+        K = onsite.shape[0]
+        p = _need(psi, torch.complex128, self.n, "psi")
+        po = _need(onsite, torch.float64, None, "onsite")
+        pn = _need(norm, torch.float64, None, "norm") if norm is not None else None
+        pe = _need(energy, torch.float64, None, "energy") if energy is not None else None
+        for t, nm in ((norm, "norm"), (energy, "energy")):
+            if t is not None and t.numel() < K:
+                raise ValueError(f"{nm} needs K entries")
+        self._check(self._lib.chebtd_propagate_td(self.h, p, int(K), po, int(onsite.shape[1]), pn, pe,
+                                                  int(flags)))
+        return psi
+
     def set_check_tol(self, rel_tol: float):
         self._check(self._lib.chebtd_set_check_tol(self.h, float(rel_tol)))
 

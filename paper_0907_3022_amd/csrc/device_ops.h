@@ -235,7 +235,7 @@ inline OpHol make_hol(const Ctx &c)
     op.occ = static_cast<const uint8_t *>(c.hol_occ.p);
     op.tot = static_cast<const uint8_t *>(c.hol_tot.p);
     const double *site = static_cast<const double *>(c.hol_site.p);
-    op.Delta = site;
+    op.Delta = c.hol_delta ? c.hol_delta : site;
     op.gw0 = site + c.hol_L;
     op.sq = site + 2 * c.hol_L;
     op.w0 = c.hol_w0;

@@ -104,6 +104,7 @@ struct Ctx {
     DevBuf hol_occ, hol_up, hol_dn, hol_tot, hol_site;
     int hol_periodic = 0;
     double hol_t = 0.0, hol_w0 = 0.0;
+    const double *hol_delta = nullptr;  // per-step Delta_i during a time-dependent run
 
     // bounds and plan
     bool has_bounds = false;

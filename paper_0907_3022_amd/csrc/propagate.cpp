@@ -221,6 +221,65 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
     return CHEBTD_OK;
 }
 
+int chebtd_propagate_td(chebtd_ctx *ctx, double *psi_dev, int64_t K, const double *onsite_dev,
+                        int64_t stride, double *norm_dev, double *energy_dev, unsigned flags)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    Ctx *c = static_cast<Ctx *>(ctx);
+    if (!c->has_plan) return fail(c, CHEBTD_E_STATE, "chebtd_propagate_td: no plan");
+    if (!psi_dev || K < 0 || !onsite_dev)
+        return fail(c, CHEBTD_E_ARG, "chebtd_propagate_td: need psi, K >= 0 and the on-site schedule");
+    if (flags & CHEBTD_KEEP_CHECKPOINTS)
+        return fail(c, CHEBTD_E_ARG, "chebtd_propagate_td: checkpoints are not kept for a time-dependent H");
+    const int64_t need = c->kind == HKind::Holstein ? c->hol_L : c->n;
+    if (c->kind != HKind::Chain && c->kind != HKind::Honeycomb && c->kind != HKind::Holstein)
+        return fail(c, CHEBTD_E_STATE, "chebtd_propagate_td: needs a chain, ribbon or Holstein H");
+    if (stride < need) return fail(c, CHEBTD_E_ARG, "chebtd_propagate_td: stride smaller than one step's values");
+    if (K == 0) return CHEBTD_OK;
+    // one launch sequence per step with that step's on-site values; the
+    // borrowed pointer is restored afterwards
+    const double *saved = c->kind == HKind::Chain ? c->V : c->eps;
+    const unsigned step_flags = (flags & ~(CHEBTD_GRAPH)) | CHEBTD_NO_PERSISTENT;
+    hipStream_t s = c->stream;
+    double2 *P = reinterpret_cast<double2 *>(psi_dev);
+    double2 *B = static_cast<double2 *>(c->vB.p);
+    hipError_t e = hipSuccess;
+    const bool check = (flags & CHEBTD_NO_CHECK) == 0;
+    if (check) e = enqueue_norm(c, s, P, 0);
+    if (e == hipSuccess && (norm_dev || energy_dev)) e = launch_reset_counter(s, static_cast<int64_t *>(c->counter.p));
+    for (int64_t st = 0; st < K && e == hipSuccess; ++st) {
+        const double *on = onsite_dev + st * stride;
+        if (c->kind == HKind::Chain)
+            c->V = on;
+        else if (c->kind == HKind::Honeycomb)
+            c->eps = on;
+        else
+            c->hol_delta = on;
+        double2 *cur = (st & 1) ? B : P;
+        double2 *nxt = (st & 1) ? P : B;
+        e = enqueue_step(c, s, cur, nxt, nullptr, norm_dev, energy_dev, step_flags);
+    }
+    if (c->kind == HKind::Chain)
+        c->V = saved;
+    else if (c->kind == HKind::Honeycomb)
+        c->eps = saved;
+    c->hol_delta = nullptr;
+    if (e == hipSuccess && (K & 1)) e = launch_copy(s, B, P, c->n);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_propagate_td");
+    if (!check) return CHEBTD_OK;
+    e = enqueue_norm(c, s, P, 2);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->pinned, c->results.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "norm check");
+    const double n0 = c->pinned[0], n1 = c->pinned[2];
+    if (!std::isfinite(n1) || !std::isfinite(n0) || std::fabs(n1 - n0) > c->check_tol * n0)
+        return fail(c, CHEBTD_E_DIVERGED,
+                    "chebtd_propagate_td: norm went from " + std::to_string(n0) + " to " + std::to_string(n1) +
+                        "; the bounds do not enclose every step's H");
+    return CHEBTD_OK;
+}
+
 int chebtd_density(chebtd_ctx *ctx, const double *psi_dev, double *rho_dev)
 {
     if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");

@@ -574,3 +574,49 @@ def test_adjoint_honeycomb_central_differences():
         Lp = np.sum(mask * np.abs(O.propagate(O.honeycomb(w, l, ep), P, psi0, K)) ** 2)
         Lm = np.sum(mask * np.abs(O.propagate(O.honeycomb(w, l, em), P, psi0, K)) ** 2)
         assert g[i] == pytest.approx((Lp - Lm) / (2 * h), abs=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Time-dependent H(t) held constant within each step (Sect. 2.2, last paragraph)
+# ---------------------------------------------------------------------------
+def _td_oracle(V_of_step, dx, psi0, plan, K):
+    psi = psi0.copy()
+    for s in range(K):
+        psi = O.propagate(O.chain1d(V_of_step(s), dx), plan, psi, 1)
+    return psi
+
+
+def test_time_dependent_uniform_shift_is_a_global_phase():
+    # V(x, t) = V0(x) + f0 + f1 t: the shift only multiplies psi by
+    # exp(-i int f dt); mid-step values make the sum exact for linear f
+    x, dx = W.chain_grid(200, -8.0, 8.0)
+    V0 = W.quartic_well(x, 0.05, 3.0)
+    psi0 = W.gaussian_1d(x, -3.0, 0.7, 1.0)
+    f0, f1, dt, K = 0.3, 0.8, 0.05, 24
+    H0 = O.chain1d(V0, dx)
+    lo, hi = H0.gershgorin()
+    plan = O.Plan(lo - 1.0, hi + f0 + f1 * dt * K + 1.0, dt)
+    psi = _td_oracle(lambda s: V0 + f0 + f1 * (s + 0.5) * dt, dx, psi0, plan, K)
+    T = dt * K
+    ref = np.exp(-1j * (f0 * T + 0.5 * f1 * T * T)) * O.propagate(H0, plan, psi0, K)
+    assert rel_l2(psi, ref) < 1e-12
+
+
+def test_time_dependent_midpoint_is_second_order():
+    # driven particle V(x, t) = V0(x) + E sin(w t) x: error vs a fine-step run
+    x, dx = W.chain_grid(160, -8.0, 8.0)
+    V0 = W.harmonic(x, 0.5)
+    psi0 = W.gaussian_1d(x, -1.0, 1.0, 0.5)
+    E, w, T = 0.4, 1.3, 2.0
+    lo, hi = O.chain1d(V0, dx).gershgorin()
+    bound = E * np.abs(x).max()
+
+    def run(K):
+        dt = T / K
+        plan = O.Plan(lo - bound, hi + bound, dt)
+        return _td_oracle(lambda s: V0 + E * np.sin(w * (s + 0.5) * dt) * x, dx, psi0, plan, K)
+
+    ref = run(512)
+    errs = [np.linalg.norm(run(K) - ref) for K in (16, 32, 64)]
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(order - 2.0) < 0.15)
