@@ -205,6 +205,15 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
 int chebtd_propagate_td(chebtd_ctx *ctx, double *psi_dev, int64_t K, const double *onsite_dev,
                         int64_t stride, double *norm_dev, double *energy_dev, unsigned flags);
 
+/* Crank-Nicolson, eq. (CN), the comparison method of Sect. 2.2 and Table 1:
+ * S steps of (1 + i dt H/2) psi_{s+1} = (1 - i dt H/2) psi_s for the chain
+ * built by chebtd_h_chain1d (second order in dt, unitary).  The
+ * step-independent tridiagonal factors are computed on the host; one
+ * wavefront then runs all S steps with both vectors in LDS (n <= LDS/32
+ * entries, 2048 on 64 KB workgroups).  Needs no bounds or plan.
+ * Synchronises. */
+int chebtd_crank_nicolson(chebtd_ctx *ctx, double *psi_dev, double dt, int64_t S);
+
 /* Relative norm tolerance of the end-of-call check (default 1e-6). */
 int chebtd_set_check_tol(chebtd_ctx *ctx, double rel_tol);
 

@@ -67,6 +67,7 @@ _SIGS = {
                                    C.c_uint]),
     "chebtd_propagate_td": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                       C.c_void_p, C.c_void_p, C.c_uint]),
+    "chebtd_crank_nicolson": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
     "chebtd_set_check_tol": (C.c_int, [C.c_void_p, C.c_double]),
     "chebtd_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "chebtd_region_sum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

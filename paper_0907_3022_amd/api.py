@@ -204,6 +204,13 @@ class Context:
                                                   int(flags)))
         return psi
 
+    def crank_nicolson(self, psi, dt: float, S: int):
+        """S Crank-Nicolson steps of the current 1D chain (comparison method)."""
+        torch = _torch()
+        p = _need(psi, torch.complex128, self.n, "psi")
+        self._check(self._lib.chebtd_crank_nicolson(self.h, p, float(dt), int(S)))
+        return psi
+
     def set_check_tol(self, rel_tol: float):
         self._check(self._lib.chebtd_set_check_tol(self.h, float(rel_tol)))
 
