@@ -159,6 +159,74 @@ def bench_double_well(torch, P, K):
                 bound="one workgroup: barrier latency + one CU's fp64 rate")
 
 
+def bench_table1(torch, P, t_end=40.0, target=1e-9, cn_dts=(2e-4, 1e-4), run_limit_s=30.0):
+    """Table 1 comparison on the Sect. 3.1 double well (N = 4096): run time to
+    t = 40 of the Chebyshev propagator (dt = 0.5) and of Crank-Nicolson at the
+    step that keeps the wave function's real and imaginary parts within
+    `target` of the Chebyshev result (continuum normalisation, the integral
+    of |psi|^2 over x equal to 1).  CN's step follows from two coarse runs
+    and its second order; the run at that step is timed when it is expected
+    to take at most `run_limit_s`, else its time is the measured per-step
+    time times the step count."""
+    p = W.DOUBLE_WELL.params
+    x, dx, V, psi0 = W.double_well_inputs(p["n"], p["xmin"], p["xmax"], p["a"], p["b"], p["x0"],
+                                          p["sigma"], p["k0"])
+    ctx = P.Context()
+    V_d = torch.from_numpy(V).cuda()
+    ctx.chain1d(V_d, dx)
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi, 0.01)
+    dt_c = p["dt"]
+    K = int(round(t_end / dt_c))
+    M = ctx.plan(dt_c)
+    psi = torch.from_numpy(psi0).cuda()
+    ctx.propagate(psi, 1, None, None, P.NO_CHECK)  # warm-up
+    psi = torch.from_numpy(psi0).cuda()
+    t_cheb = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
+    ref = psi.cpu().numpy()
+    scale = 1.0 / np.sqrt(dx)
+
+    def err(a):
+        d = (a - ref) * scale
+        return float(max(np.abs(d.real).max(), np.abs(d.imag).max()))
+
+    # the Chebyshev result against itself at half the step
+    M2 = ctx.plan(dt_c / 2)
+    ph = torch.from_numpy(psi0).cuda()
+    ctx.propagate(ph, 2 * K, None, None, P.NO_CHECK)
+    cheb_self = err(ph.cpu().numpy())
+    cn = []
+    for dt in cn_dts:
+        S = int(round(t_end / dt))
+        pc = torch.from_numpy(psi0).cuda()
+        ctx.crank_nicolson(pc, dt, 1)  # warm-up
+        pc = torch.from_numpy(psi0).cuda()
+        t = timed(torch, lambda: ctx.crank_nicolson(pc, dt, S))
+        cn.append(dict(dt=dt, steps=S, seconds=t, us_per_step=t / S * 1e6,
+                       max_abs_err=err(pc.cpu().numpy())))
+    e1, e2 = cn[0]["max_abs_err"], cn[1]["max_abs_err"]
+    order = float(np.log(e1 / e2) / np.log(cn_dts[0] / cn_dts[1]))
+    dt_star = cn_dts[1] * (target / e2) ** 0.5
+    S_star = int(np.ceil(t_end / dt_star))
+    us_step = min(c["us_per_step"] for c in cn)
+    est = S_star * us_step * 1e-6
+    out = dict(workload="double_well_1d_N4096_t40", chebyshev=dict(dt=dt_c, M=M, steps=K,
+               seconds=t_cheb, self_err_half_step=cheb_self, M_half_step=M2),
+               crank_nicolson_runs=cn, cn_order=order, cn_dt_for_target=dt_star,
+               cn_steps_for_target=S_star, target_abs_err=target, cn_us_per_step=us_step)
+    if est <= run_limit_s:
+        dt_star = t_end / S_star
+        pc = torch.from_numpy(psi0).cuda()
+        t = timed(torch, lambda: ctx.crank_nicolson(pc, dt_star, S_star))
+        out.update(cn_seconds=t, cn_seconds_kind="measured", cn_err_at_target_step=err(pc.cpu().numpy()))
+    else:
+        out.update(cn_seconds=est, cn_seconds_kind="per-step time x steps")
+    out["cn_over_chebyshev"] = out["cn_seconds"] / t_cheb
+    out["paper_cn_over_chebyshev"] = 1871.0 / 4.8
+    ctx.close()
+    return out
+
+
 def bench_holstein(torch, P, K):
     p = W.HOLSTEIN.params
     out = {}
@@ -393,7 +461,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--sections", default="main,double_well,holstein,batched,adjoint,polaron,sweep,cpu")
+    ap.add_argument("--sections",
+                    default="main,double_well,table1,holstein,batched,adjoint,polaron,sweep,cpu")
     ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -451,6 +520,9 @@ def main():
     if "double_well" in sections:
         log("[bench] double well N=4096, 200 steps")
         extra["double_well"] = bench_double_well(torch, P, W.DOUBLE_WELL.params["K"])
+    if "table1" in sections:
+        log("[bench] double well to t = 40: Chebyshev vs Crank-Nicolson")
+        extra["table1"] = bench_table1(torch, P)
     if "holstein" in sections:
         log("[bench] Holstein ring L=10, N_ph<=10, 500 steps")
         extra["holstein"] = bench_holstein(torch, P, W.HOLSTEIN.params["K"])

@@ -209,9 +209,10 @@ int chebtd_propagate_td(chebtd_ctx *ctx, double *psi_dev, int64_t K, const doubl
  * S steps of (1 + i dt H/2) psi_{s+1} = (1 - i dt H/2) psi_s for the chain
  * built by chebtd_h_chain1d (second order in dt, unitary).  The
  * step-independent tridiagonal factors are computed on the host; one
- * wavefront then runs all S steps with both vectors in LDS (n <= LDS/32
- * entries, 2048 on 64 KB workgroups).  Needs no bounds or plan.
- * Synchronises. */
+ * 256-thread workgroup then runs all S steps with the state in registers
+ * (n <= 4096, else CHEBTD_E_ARG).  psi_dev: complex128[n] device array,
+ * overwritten.  dt > 0, S >= 0 (S = 0 leaves psi unchanged).  Needs no bounds
+ * or plan; other kinds of Hamiltonian give CHEBTD_E_STATE.  Synchronises. */
 int chebtd_crank_nicolson(chebtd_ctx *ctx, double *psi_dev, double dt, int64_t S);
 
 /* Relative norm tolerance of the end-of-call check (default 1e-6). */

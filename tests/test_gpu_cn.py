@@ -36,9 +36,9 @@ def run(torch, cheb, V, dx, psi0, dt, S):
     return psi.cpu().numpy()
 
 
-# ragged chain lengths: fewer sites than lanes, one per lane, one past a
-# full chunk, several chunks with a short last lane, the LDS-size maximum
-@pytest.mark.parametrize("n", [2, 37, 64, 65, 1000, 2048, 4096])
+# ragged chain lengths: fewer sites than threads, one per thread, one past
+# that (two per thread), partly filled chunks, the 4096 maximum
+@pytest.mark.parametrize("n", [2, 37, 64, 256, 257, 1000, 2048, 4095, 4096])
 @pytest.mark.parametrize("S", [1, 7])
 def test_cn_matches_oracle(torch, cheb, n, S):
     x, dx, V, psi0 = W.double_well_inputs(n)
@@ -70,11 +70,11 @@ def test_cn_zero_steps_and_errors(torch, cheb):
     psi = torch.from_numpy(psi0.copy()).cuda()
     with pytest.raises(cheb.ChebError):
         ctx.crank_nicolson(psi, -0.1, 3)
-    # a chain too long for one workgroup's LDS is refused
+    # a chain longer than one workgroup holds in registers is refused
     xb, dxb, Vb, pb = W.double_well_inputs(1 << 14)
     big = cheb.Context()
     big.chain1d(torch.from_numpy(Vb).cuda(), dxb)
-    with pytest.raises(cheb.ChebError, match="LDS"):
+    with pytest.raises(cheb.ChebError, match="n <= 4096"):
         big.crank_nicolson(torch.from_numpy(pb).cuda(), 0.1, 1)
     # only the chain has a CN path
     eps, pr = W.ribbon_inputs(8, 40, 0.5, 3)
