@@ -83,8 +83,9 @@ int ensure_partials(Ctx *c)
 // Rows per wavefront chunk of the two-orders-per-pass kernel.  Each
 // wavefront walks its chunk row by row with one row of loads in flight, so
 // short chunks (many wavefronts) hide memory latency best; each chunk also
-// re-reads two halo rows of v_k on either side.  Measured on MI355X: 2 rows
-// for ribbons up to 128 rows wide, 4 beyond (16M-64M sites).
+// re-reads two halo rows of v_k on either side, which costs more once the
+// vectors no longer fit the last-level cache.  Measured on MI355X: 2 rows for
+// ribbons up to 128 rows wide, 4 below 1024 rows, 16 from there (64M sites).
 // CHEBTD_PAIR_ROWS overrides.
 int choose_pair_rows(const Ctx &c)
 {
@@ -94,7 +95,7 @@ int choose_pair_rows(const Ctx &c)
         if (r >= 1) return r;
     }
     if (c.kind != HKind::Honeycomb) return 1;
-    return c.W <= 128 ? 2 : 4;
+    return c.W <= 128 ? 2 : (c.W < 1024 ? 4 : 16);
 }
 
 void invalidate_h(Ctx *c)

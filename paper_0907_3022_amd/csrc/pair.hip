@@ -49,6 +49,14 @@ __device__ __forceinline__ double2 shfl_down1(double2 v)
     return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
 }
 
+// Operands of one row loaded one iteration ahead: v_k of the row below,
+// and v_{k-1}, the on-site term, the outside v_k value (strip-edge lanes) and
+// acc of the row itself.
+struct Prefetch {
+    double2 a, km1, ext, acc;
+    double e;
+};
+
 }  // namespace
 
 template <int EDGE, bool HEAD>
@@ -73,52 +81,50 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
     if (chunk < op.nchunks) {  // uniform per wavefront
         const int32_t ys = chunk * op.rows;
         const int32_t ye = min(ys + op.rows, W);
-        // Loads are unconditional, from a clamped index, with the value selected
-        // afterwards: a conditional load of either memory or a local zero is
-        // turned into a flat load of a selected pointer, whose completion the
-        // cross-lane shuffles would then have to wait for.
+        // Loads are unconditional, from a clamped index, and return the raw
+        // value; where a zero is needed outside the lattice it is selected
+        // when the value is used, one row later.  (A conditional load of
+        // memory or a local zero becomes a flat load of a selected pointer,
+        // and selecting right after the load would make every iteration wait
+        // for the prefetch it has just issued.)
+        auto okr = [&](int32_t r) -> bool { return colok && r >= 0 && r < W; };
         auto ld = [&](const double2 *v, int32_t r) -> double2 {
-            const bool ok = colok && r >= 0 && r < W;
-            const double2 val = v[ok ? (int64_t)r * L + x : 0];
-            return csel(ok, val, zero);
+            return v[okr(r) ? (int64_t)r * L + x : 0];
         };
-        auto ld_on = [&](int32_t r) -> double {
-            const bool ok = colok && r >= 0 && r < W;
-            const double val = op.onsite[ok ? (int64_t)r * L + x : 0];
-            return ok ? val : 0.0;
-        };
+        auto ld_on = [&](int32_t r) -> double { return op.onsite[okr(r) ? (int64_t)r * L + x : 0]; };
         // lanes 0 and 63 also need the v_k value just outside the strip
-        auto ld_ext = [&](int32_t r) -> double2 {
-            const int32_t xe = lane == 0 ? x - 1 : x + 1;
-            const bool ok = (lane == 0 || lane == 63) && r >= 0 && r < W && xe >= 0 && xe < L;
-            const double2 val = vk[ok ? (int64_t)r * L + xe : 0];
-            return csel(ok, val, zero);
-        };
+        const int32_t xe = lane == 0 ? x - 1 : x + 1;
+        const bool ext_lane = (lane == 0 || lane == 63) && xe >= 0 && xe < L;
+        auto ok_ext = [&](int32_t r) -> bool { return ext_lane && r >= 0 && r < W; };
+        auto ld_ext = [&](int32_t r) -> double2 { return vk[ok_ext(r) ? (int64_t)r * L + xe : 0]; };
         // operands of row r (v_k row r+1, v_{k-1}, on-site and outside value of
-        // row r, acc of row r-1) are loaded one iteration ahead
-        double2 a_m1 = ld(vk, ys - 2), a_0 = ld(vk, ys - 1);  // v_k rows r-1, r
-        double2 a_p1 = ld(vk, ys);
-        double2 km1 = zero;
-        if (!HEAD) km1 = ld(vkm1, ys - 1);
-        double e_0 = ld_on(ys - 1);
-        double2 ext = ld_ext(ys - 1);
-        double2 accq = zero;
+        // row r, acc of row r-1) are loaded one iteration ahead; v_{k-1}, the
+        // on-site term and acc are only used where they are in range
+        double2 a_m1 = csel(okr(ys - 2), ld(vk, ys - 2), zero);  // v_k rows r-1, r
+        double2 a_0 = csel(okr(ys - 1), ld(vk, ys - 1), zero);
+        // Two sets of prefetch registers, used alternately: the loads issued
+        // for the next row are never copied (a copy would wait for them).
+        Prefetch p0, p1;
+        p0.a = ld(vk, ys);
+        p0.km1 = HEAD ? zero : ld(vkm1, ys - 1);
+        p0.e = ld_on(ys - 1);
+        p0.ext = ld_ext(ys - 1);
+        p0.acc = zero;
         double2 b_m2 = zero, b_m1 = zero;  // v_{k+1} rows r-2, r-1
         double e_m1 = 0.0;                 // on-site term, row r-1
-        for (int32_t r = ys - 1; r <= ye; ++r) {
-            // prefetch row r+1
-            const double2 n_a = ld(vk, r + 2);
-            double2 n_km1 = zero;
-            if (!HEAD) n_km1 = ld(vkm1, r + 1);
-            const double n_e = ld_on(r + 1);
-            const double2 n_ext = ld_ext(r + 1);
-            double2 n_acc = zero;
+        // one row: prefetch row r+1 into nx, compute from cur
+        auto row_step = [&](int32_t r, const Prefetch &cur, Prefetch &nx) {
+            nx.a = ld(vk, r + 2);
+            nx.km1 = HEAD ? zero : ld(vkm1, r + 1);
+            nx.e = ld_on(r + 1);
+            nx.ext = ld_ext(r + 1);
             if (!HEAD) {
                 const bool ok = own && r >= ys && r < ye;
-                const double2 val = acc[ok ? (int64_t)r * L + x : 0];
-                n_acc = csel(ok, val, zero);
+                nx.acc = acc[ok ? (int64_t)r * L + x : 0];
             }
-
+            const double2 a_p1 = csel(okr(r + 1), cur.a, zero);
+            const double2 ext = csel(ok_ext(r), cur.ext, zero);
+            const double e_0 = cur.e;
             const bool rowok = r >= 0 && r < W;
             const int64_t ir = (int64_t)r * L + x;
             // ---- first order at row r: v_{k+1} = 2 H~ v_k - v_{k-1} ----
@@ -133,7 +139,7 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                 s = cadd(cadd(a_m1, a_p1), csel(even_r, right, left));
             const double d0 = op.s2 * (e_0 + op.dshift);
             const double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
-            double2 b_0 = HEAD ? cscale(0.5, h) : csub(h, km1);
+            double2 b_0 = HEAD ? cscale(0.5, h) : csub(h, cur.km1);
             b_0 = csel(colok && rowok, b_0, zero);
             if (own && r >= ys && r < ye) out1[ir] = b_0;
             // ---- second order at row q = r-1: v_{k+2} = 2 H~ v_{k+1} - v_k ----
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                         nrm += a_m1.x * a_m1.x + a_m1.y * a_m1.y;
                         en += a_m1.x * b_m1.x + a_m1.y * b_m1.y;
                     } else {
-                        a = accq;
+                        a = cur.acc;  // acc of row q, loaded with the previous row
                     }
                     a = cfma(g1, b_m1, a);
                     acc[iq] = cfma(g2, c, a);
@@ -167,15 +173,16 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
             }
             a_m1 = a_0;
             a_0 = a_p1;
-            a_p1 = n_a;
-            km1 = n_km1;
             b_m2 = b_m1;
             b_m1 = b_0;
             e_m1 = e_0;
-            e_0 = n_e;
-            ext = n_ext;
-            accq = n_acc;
+        };
+        int32_t r = ys - 1;
+        for (; r + 1 <= ye; r += 2) {
+            row_step(r, p0, p1);
+            row_step(r + 1, p1, p0);
         }
+        if (r <= ye) row_step(r, p0, p1);
     }
     if (HEAD) {
         block_sum2(nrm, en, red);
