@@ -357,12 +357,20 @@ def bench_batched(torch, P, K, seq_steps=10):
     ctx.close()
     batched_rate = site_orders * K / t
     seq_rate = site_orders * seq_steps / seq_t
+    mode = ["levels", "persistent", "pairs"][best[0]]
+    # algorithmic bytes of one step: 88 per site and order, or for the pairs
+    # schedule 104 per site and pass of two orders plus 88 for an odd tail
+    if mode == "pairs":
+        step_bytes = sum(s["width"] * s["length"] * (PAIR_BYTES * (int(M) // 2) + STENCIL_BYTES * (int(M) % 2))
+                         for s, M in zip(systems, Ms))
+    else:
+        step_bytes = STENCIL_BYTES * site_orders
     return dict(workload="batched_256_ribbons", systems=len(systems),
                 sites=int(sum(s["width"] * s["length"] for s in systems)),
                 M_min=int(Ms.min()), M_max=int(Ms.max()), steps=K, seconds=t,
-                schedule=dict(mode=["levels", "persistent"][best[0]], tile=best[1], block=best[2],
-                              wg_per_cu=best[3]), autotune_seconds=tune_s,
-                site_orders_per_s=batched_rate, GBs=STENCIL_BYTES * batched_rate / 1e9,
+                schedule=dict(mode=mode, tile=best[1], block=best[2], wg_per_cu=best[3]),
+                autotune_seconds=tune_s, site_orders_per_s=batched_rate,
+                GBs=step_bytes * K / t / 1e9, GBs_at_88B_per_site_order=STENCIL_BYTES * batched_rate / 1e9,
                 sequential_site_orders_per_s=seq_rate, sequential_steps=seq_steps,
                 speedup_vs_sequential=batched_rate / seq_rate)
 

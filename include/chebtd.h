@@ -256,7 +256,7 @@ typedef struct {
 
 /* Prepare a batch of nsys ribbons stepped by the same dt (each with its
  * own a, b, M and weights; alpha and tol as chebtd_set_bounds/plan).
- * Allocates the batch's work vectors (two per system) and schedule tables.
+ * Allocates the batch's work vectors (four per system) and schedule tables.
  * Replaces any previous batch on the context. */
 int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs, double dt,
                         double alpha, double tol);
@@ -267,10 +267,16 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
 #define CHEBTD_SCHED_PERSISTENT 1 /* one persistent launch per step: a     */
                                   /* work queue of (level, system, tile)    */
                                   /* with per-system completion counters    */
+#define CHEBTD_SCHED_PAIRS 2      /* one launch per two recursion orders    */
+                                  /* over every system still active (needs  */
+                                  /* M >= 2 everywhere), plus one tail      */
+                                  /* launch for systems with odd M           */
 
 /* Fix the schedule: mode, rows per tile (multiple of block, >= block),
  * threads per block (64..1024, multiple of 64), and for the persistent
- * mode the number of resident workgroups per CU (1..8). */
+ * mode the number of resident workgroups per CU (1..8).  The pairs mode
+ * walks whole ribbons with 256-thread blocks; its tile and block apply to
+ * the odd-M tail and the final copy. */
 int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int block,
                               int wg_per_cu);
 

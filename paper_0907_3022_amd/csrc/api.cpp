@@ -87,15 +87,20 @@ int ensure_partials(Ctx *c)
 // vectors no longer fit the last-level cache.  Measured on MI355X: 2 rows for
 // ribbons up to 128 rows wide, 4 below 1024 rows, 16 from there (64M sites).
 // CHEBTD_PAIR_ROWS overrides.
-int choose_pair_rows(const Ctx &c)
+int pair_rows_for_width(int64_t W)
 {
     const char *env = std::getenv("CHEBTD_PAIR_ROWS");
     if (env) {
         const int r = std::atoi(env);
         if (r >= 1) return r;
     }
+    return W <= 128 ? 2 : (W < 1024 ? 4 : 16);
+}
+
+int choose_pair_rows(const Ctx &c)
+{
     if (c.kind != HKind::Honeycomb) return 1;
-    return c.W <= 128 ? 2 : (c.W < 1024 ? 4 : 16);
+    return pair_rows_for_width(c.W);
 }
 
 void invalidate_h(Ctx *c)

@@ -14,6 +14,7 @@
 
 #include "batch_internal.h"
 #include "internal.h"
+#include "pair.h"
 
 namespace chebtd {
 int fail(Ctx *c, int code, const std::string &msg);
@@ -37,6 +38,12 @@ struct BatchState {
     DevBuf blk_sys, blk_tile, q_level_off, q_level_active, q_tile_prefix, q_order;
     QueueDev q{};
     int64_t nblocks = 0;
+    // pairs schedule: blocks per pair level (active systems are a prefix of
+    // `order`), and the tail tiles of systems with odd M
+    bool pairs_ok = false;
+    std::vector<int64_t> pair_level_blocks;
+    DevBuf pblk_sys, pblk_wave0, tblk_sys, tblk_tile;
+    int64_t ntail_blocks = 0;
     DevBuf head, done, flag;
     int64_t spin_limit = 0;  // wall-clock ticks a dependency wait may take
     hipGraphExec_t graph = nullptr;
@@ -56,7 +63,8 @@ void batch_destroy(Ctx *c)
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (DevBuf *d : {&b->sys_dev, &b->gamma_dev, &b->work, &b->blk_sys, &b->blk_tile, &b->q_level_off,
-                      &b->q_level_active, &b->q_tile_prefix, &b->q_order, &b->head, &b->done, &b->flag})
+                      &b->q_level_active, &b->q_tile_prefix, &b->q_order, &b->pblk_sys, &b->pblk_wave0,
+                      &b->tblk_sys, &b->tblk_tile, &b->head, &b->done, &b->flag})
         release(*d);
     delete b;
     c->batch = nullptr;
@@ -104,7 +112,43 @@ static int build_tables(Ctx *c, BatchState *b)
         b->level_blocks[k] = prefix[cnt];
         loff[k + 1] = loff[k] + prefix[cnt];
     }
+    // pairs schedule: level p runs the systems with M >= 2p + 2
+    std::vector<int32_t> psys, pw0, tsys, ttile;
+    b->pair_level_blocks.clear();
+    if (b->pairs_ok) {
+        std::vector<int64_t> pprefix(ns + 1, 0);
+        for (int j = 0; j < ns; ++j) {
+            const SysDev &sd = b->sys[b->order[j]];
+            const int64_t waves = (int64_t)sd.nstrips * sd.nchunks;
+            const int64_t nbk = (waves + 3) / 4;
+            for (int64_t q = 0; q < nbk; ++q) {
+                psys.push_back(b->order[j]);
+                pw0.push_back((int32_t)(4 * q));
+            }
+            pprefix[j + 1] = pprefix[j] + nbk;
+        }
+        if (pprefix[ns] > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many wavefronts");
+        for (int p = 0; 2 * p + 2 <= Mmax; ++p) {
+            int cnt = 0;
+            for (int j = 0; j < ns; ++j)
+                if (b->M[b->order[j]] >= 2 * p + 2) ++cnt;
+            b->pair_level_blocks.push_back(pprefix[cnt]);
+        }
+        for (int s = 0; s < ns; ++s)
+            if (b->M[s] & 1)
+                for (int64_t t = 0; t < tiles[s]; ++t) {
+                    tsys.push_back(s);
+                    ttile.push_back((int32_t)t);
+                }
+    }
+    b->ntail_blocks = (int64_t)tsys.size();
     int rc;
+    if (b->pairs_ok &&
+        ((rc = upload(c, b->pblk_sys, psys.data(), psys.size() * 4, "pair block table")) ||
+         (rc = upload(c, b->pblk_wave0, pw0.data(), pw0.size() * 4, "pair wavefront table")) ||
+         (rc = upload(c, b->tblk_sys, tsys.data(), tsys.size() * 4, "tail block table")) ||
+         (rc = upload(c, b->tblk_tile, ttile.data(), ttile.size() * 4, "tail tile table"))))
+        return rc;
     if ((rc = upload(c, b->blk_sys, bsys.data(), bsys.size() * 4, "batch block table")) ||
         (rc = upload(c, b->blk_tile, btile.data(), btile.size() * 4, "batch tile table")) ||
         (rc = upload(c, b->q_level_off, loff.data(), loff.size() * 8, "queue levels")) ||
@@ -127,6 +171,17 @@ static hipError_t enqueue_step(Ctx *c, BatchState *b, hipStream_t s, int par)
 {
     const SysDev *sys = static_cast<const SysDev *>(b->sys_dev.p);
     const double2 *gam = static_cast<const double2 *>(b->gamma_dev.p);
+    if (b->mode == CHEBTD_SCHED_PAIRS) {
+        const int32_t *ps = static_cast<const int32_t *>(b->pblk_sys.p);
+        const int32_t *pw = static_cast<const int32_t *>(b->pblk_wave0.p);
+        for (size_t p = 0; p < b->pair_level_blocks.size(); ++p) {
+            hipError_t e = launch_batch_pair(s, sys, gam, ps, pw, b->pair_level_blocks[p], (int)p, par);
+            if (e != hipSuccess) return e;
+        }
+        return launch_batch_tail(s, sys, gam, static_cast<const int32_t *>(b->tblk_sys.p),
+                                 static_cast<const int32_t *>(b->tblk_tile.p), b->ntail_blocks, b->tile, par,
+                                 b->block);
+    }
     if (b->mode == CHEBTD_SCHED_LEVELS) {
         for (int k = 0; k < b->nlevels; ++k) {
             hipError_t e = launch_batch_level(s, sys, gam, static_cast<const int32_t *>(b->blk_sys.p),
@@ -293,16 +348,25 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
         b->nsites[s] = d.width * d.length;
         total += b->nsites[s];
     }
-    int rc = ensure(c, b->work, (size_t)total * 2 * sizeof(double2), "batch work vectors");
+    int rc = ensure(c, b->work, (size_t)total * 4 * sizeof(double2), "batch work vectors");
     if (rc) {
         batch_destroy(c);
         return rc;
     }
     double2 *w = static_cast<double2 *>(b->work.p);
+    b->pairs_ok = true;
     for (int s = 0; s < nsys; ++s) {
-        b->sys[s].A = w;
-        b->sys[s].B = w + b->nsites[s];
-        w += 2 * b->nsites[s];
+        SysDev &sd = b->sys[s];
+        sd.A = w;
+        sd.B = w + b->nsites[s];
+        sd.C = w + 2 * b->nsites[s];
+        sd.D = w + 3 * b->nsites[s];
+        w += 4 * b->nsites[s];
+        sd.rows = pair_rows_for_width(sd.W);
+        sd.nstrips = (sd.L + kPairStripCols - 1) / kPairStripCols;
+        sd.nchunks = (sd.W + sd.rows - 1) / sd.rows;
+        sd.pad2 = 0;
+        if (b->M[s] < 2) b->pairs_ok = false;  // the head of a pair level computes two orders
     }
     b->order.resize(nsys);
     for (int s = 0; s < nsys; ++s) b->order[s] = s;
@@ -323,7 +387,10 @@ int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int bloc
     Ctx *c = static_cast<Ctx *>(ctx);
     BatchState *b = c->batch;
     if (!b) return fail(c, CHEBTD_E_STATE, "chebtd_batch_set_schedule: no batch");
-    if ((mode != CHEBTD_SCHED_LEVELS && mode != CHEBTD_SCHED_PERSISTENT) || block < 64 || block > 1024 ||
+    if (mode == CHEBTD_SCHED_PAIRS && !b->pairs_ok)
+        return fail(c, CHEBTD_E_ARG, "chebtd_batch_set_schedule: the pairs schedule needs M >= 2 for every system");
+    if ((mode != CHEBTD_SCHED_LEVELS && mode != CHEBTD_SCHED_PERSISTENT && mode != CHEBTD_SCHED_PAIRS) ||
+        block < 64 || block > 1024 ||
         block % 64 || tile_rows < block || tile_rows % block || wg_per_cu < 1 || wg_per_cu > 8)
         return fail(c, CHEBTD_E_ARG,
                     "chebtd_batch_set_schedule: need a known mode, block in [64,1024] (multiple of 64), "
@@ -419,6 +486,7 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
             for (int block : {256, 512}) {
                 if (tile % block) continue;
                 cands.push_back({CHEBTD_SCHED_LEVELS, tile, block, 1});
+                if (b->pairs_ok) cands.push_back({CHEBTD_SCHED_PAIRS, tile, block, 1});
                 for (int wg : {2, 4}) cands.push_back({CHEBTD_SCHED_PERSISTENT, tile, block, wg});
             }
         double best_ms = 1e300;

@@ -4,10 +4,14 @@
 // Bessel weights, and each system's sites are cut into tiles of `tile`
 // consecutive site indices.
 //
-// Two schedules share the per-tile work:
+// Three schedules:
 //  * levels:     one launch per recursion level; block b takes tile b of the
 //                systems still active at that level (systems are sorted by
 //                M, descending, so the active ones form a prefix).
+//  * pairs:      one launch per two recursion orders; every system's
+//                wavefronts walk its strips and row chunks as the
+//                single-system two-orders-per-pass kernel does (pair_walk.h),
+//                and systems with odd M finish with a one-order tail launch.
 //  * persistent: one launch per time step; resident workgroups pull
 //                (level, system, tile) items from a queue ordered level by
 //                level.  Before a tile of level k runs, every tile of level
@@ -23,6 +27,7 @@
 
 #include "batch_internal.h"
 #include "device_ops.h"
+#include "pair_walk.h"
 
 namespace chebtd {
 
@@ -78,23 +83,23 @@ __device__ __forceinline__ void tile_level(const SysDev &sd, const double2 *gamm
     w.start((int64_t)tile_idx * tile, n, tile, sd.L);
     const double2 *g = gamma + sd.gamma_off;
     if (k == 0) {
-        const double2 g0 = g[0];
-        const double2 g1 = sd.M >= 1 ? g[1] : make_double2(0.0, 0.0);
+        const double2 g0 = ldg(g, 0);
+        const double2 g1 = sd.M >= 1 ? ldg(g, 1) : make_double2(0.0, 0.0);
         for (; w.ok(); w.next()) {
-            const double2 vi = cur[w.i];
+            const double2 vi = ldg(cur, w.i);
             const double2 h = cscale(0.5, honey_apply2(sd, w.i, w.x, w.y, cur, vi));
-            A[w.i] = h;
-            nxt[w.i] = cfma(g1, h, cfma(g0, vi, make_double2(0.0, 0.0)));
+            stg(A, w.i, h);
+            stg(nxt, w.i, cfma(g1, h, cfma(g0, vi, make_double2(0.0, 0.0))));
         }
     } else {
-        const double2 gk = g[k + 1];
+        const double2 gk = ldg(g, k + 1);
         const double2 *vk = (k & 1) ? A : cur;
         double2 *vprev = (k & 1) ? cur : A;
         for (; w.ok(); w.next()) {
-            const double2 vi = vk[w.i];
-            const double2 nv = csub(honey_apply2(sd, w.i, w.x, w.y, vk, vi), vprev[w.i]);
-            vprev[w.i] = nv;
-            nxt[w.i] = cfma(gk, nv, nxt[w.i]);
+            const double2 vi = ldg(vk, w.i);
+            const double2 nv = csub(honey_apply2(sd, w.i, w.x, w.y, vk, vi), ldg(vprev, w.i));
+            stg(vprev, w.i, nv);
+            stg(nxt, w.i, cfma(gk, nv, ldg(nxt, w.i)));
         }
     }
 }
@@ -110,6 +115,91 @@ __global__ void k_batch_level(const SysDev *__restrict__ sys, const double2 *__r
     const SysDev sd = sys[s];
     if (k > 0 && k > sd.M - 1) return;
     tile_level(sd, gamma, k, blk_tile[blockIdx.x], tile, par);
+}
+
+// ---------------------------------------------------------------------------
+// pairs schedule
+// ---------------------------------------------------------------------------
+// Buffers of one step (cur = state entering the step, nxt = accumulator):
+// level 0 reads cur and writes v_1 -> A, v_2 -> C; odd levels read (A, C) and
+// write (D, cur); even levels >= 2 read (D, cur) and write (A, C).  cur is
+// free once the head has read it.
+template <bool HEAD>
+__global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ sys,
+                                                    const double2 *__restrict__ gamma,
+                                                    const int32_t *__restrict__ blk_sys,
+                                                    const int32_t *__restrict__ blk_wave0, int level, int par)
+{
+    const int32_t lb = logical_block(1);
+    const SysDev sd = sys[blk_sys[lb]];
+    const int32_t gw = blk_wave0[lb] + (int32_t)(threadIdx.x >> 6);
+    const int32_t strip = gw % sd.nstrips;
+    const int32_t chunk = gw / sd.nstrips;
+    if (chunk >= sd.nchunks) return;  // uniform per wavefront; the kernel has no barrier
+    OpPair op{};
+    op.onsite = sd.eps;
+    op.dshift = -sd.b;
+    op.s2 = sd.s2;
+    op.off2 = sd.off2;
+    op.W = sd.W;
+    op.L = sd.L;
+    op.rows = sd.rows;
+    op.nstrips = sd.nstrips;
+    op.nchunks = sd.nchunks;
+    double2 *cur = par ? sd.B : sd.psi;
+    double2 *nxt = par ? sd.psi : sd.B;
+    const double2 *g = gamma + sd.gamma_off;
+    const double2 zero = make_double2(0.0, 0.0);
+    double nrm = 0.0, en = 0.0;
+    const double2 *in1, *in2;
+    double2 *o1, *o2;
+    double2 g0 = zero, g1, g2;
+    if (HEAD) {
+        in1 = nullptr;
+        in2 = cur;
+        o1 = sd.A;
+        o2 = sd.C;
+        g0 = ldg(g, 0);
+        g1 = ldg(g, 1);
+        g2 = ldg(g, 2);
+    } else {
+        const bool odd = level & 1;
+        in1 = odd ? sd.A : sd.D;
+        in2 = odd ? sd.C : cur;
+        o1 = odd ? sd.D : sd.A;
+        o2 = odd ? cur : sd.C;
+        g1 = ldg(g, 2 * level + 1);
+        g2 = ldg(g, 2 * level + 2);
+    }
+    if (sd.edge == CHEBTD_ZIGZAG)
+        pair_walk<CHEBTD_ZIGZAG, HEAD>(op, strip, chunk, in1, in2, o1, o2, nxt, g0, g1, g2, nullptr, nrm, en);
+    else
+        pair_walk<CHEBTD_ARMCHAIR, HEAD>(op, strip, chunk, in1, in2, o1, o2, nxt, g0, g1, g2, nullptr, nrm, en);
+}
+
+// Order M = 2P+1 of a system with odd M: v_M = 2 H~ v_{M-1} - v_{M-2} over
+// v_{M-2}, acc += g_M v_M.  Level P-1 left (v_{M-2}, v_{M-1}) in (A, C) when
+// P-1 is even, in (D, cur) when odd.
+__global__ void k_batch_tail(const SysDev *__restrict__ sys, const double2 *__restrict__ gamma,
+                             const int32_t *__restrict__ blk_sys, const int32_t *__restrict__ blk_tile,
+                             int32_t tile, int par)
+{
+    const SysDev sd = sys[blk_sys[blockIdx.x]];
+    double2 *cur = par ? sd.B : sd.psi;
+    double2 *nxt = par ? sd.psi : sd.B;
+    const bool even = (((sd.M >> 1) - 1) & 1) == 0;
+    double2 *vprev = even ? sd.A : sd.D;
+    const double2 *vk = even ? sd.C : cur;
+    const double2 gM = ldg(gamma + sd.gamma_off, sd.M);
+    const int64_t n = (int64_t)sd.W * sd.L;
+    TileWalk w;
+    w.start((int64_t)blk_tile[blockIdx.x] * tile, n, tile, sd.L);
+    for (; w.ok(); w.next()) {
+        const double2 vi = ldg(vk, w.i);
+        const double2 nv = csub(honey_apply2(sd, w.i, w.x, w.y, vk, vi), ldg(vprev, w.i));
+        stg(vprev, w.i, nv);
+        stg(nxt, w.i, cfma(gM, nv, ldg(nxt, w.i)));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -214,7 +304,7 @@ __global__ void k_batch_copy_back(const SysDev *__restrict__ sys, const int32_t 
     const int64_t n = (int64_t)sd.W * sd.L;
     const int64_t t0 = (int64_t)blk_tile[blockIdx.x] * tile;
     const int64_t end = t0 + tile < n ? t0 + tile : n;
-    for (int64_t i = t0 + threadIdx.x; i < end; i += blockDim.x) sd.psi[i] = sd.B[i];
+    for (int64_t i = t0 + threadIdx.x; i < end; i += blockDim.x) stg(sd.psi, i, ldg(sd.B, i));
 }
 
 hipError_t launch_batch_level(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
@@ -234,6 +324,28 @@ hipError_t launch_batch_persistent(hipStream_t s, const SysDev *sys, const doubl
     hipLaunchKernelGGL(k_batch_reset, dim3((nsys + 255) / 256), dim3(256), 0, s, queue_head, done, nsys);
     hipLaunchKernelGGL(k_batch_persistent, dim3(grid), dim3(block), 0, s, sys, gamma, q, tile, par,
                        queue_head, done, timeout_flag, spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pair(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                             const int32_t *blk_wave0, int64_t nblocks, int level, int par)
+{
+    if (nblocks <= 0) return hipSuccess;
+    if (level == 0)
+        hipLaunchKernelGGL(k_batch_pair<true>, dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma, blk_sys,
+                           blk_wave0, level, par);
+    else
+        hipLaunchKernelGGL(k_batch_pair<false>, dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma, blk_sys,
+                           blk_wave0, level, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tail(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                             const int32_t *blk_tile, int64_t nblocks, int32_t tile, int par, int block)
+{
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_tail, dim3((unsigned)nblocks), dim3(block), 0, s, sys, gamma, blk_sys, blk_tile,
+                       tile, par);
     return hipGetLastError();
 }
 

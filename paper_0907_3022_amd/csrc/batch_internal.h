@@ -17,6 +17,9 @@ struct SysDev {
     int64_t gamma_off;   // first weight in the concatenated table
     int32_t ntiles;
     int32_t pad;
+    // two-orders-per-pass schedule: two more work vectors and the wavefront grid
+    double2 *C, *D;
+    int32_t rows, nstrips, nchunks, pad2;
 };
 
 // Work queue of the persistent schedule (item = level, system, tile).
@@ -36,6 +39,14 @@ hipError_t launch_batch_level(hipStream_t s, const SysDev *sys, const double2 *g
 hipError_t launch_batch_persistent(hipStream_t s, const SysDev *sys, const double2 *gamma, const QueueDev &q,
                                    int32_t tile, int par, int64_t *queue_head, int32_t *done,
                                    int32_t *timeout_flag, int nsys, int grid, int block, int64_t spin_limit);
+// pairs schedule: level 0 is the step head (orders 1, 2), level p >= 1 runs
+// orders 2p+1 and 2p+2; blk_sys / blk_wave0 give each block's system and its
+// first wavefront in that system's strip-major wavefront numbering.
+hipError_t launch_batch_pair(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                             const int32_t *blk_wave0, int64_t nblocks, int level, int par);
+// the last order M of systems with odd M, one tile per block
+hipError_t launch_batch_tail(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                             const int32_t *blk_tile, int64_t nblocks, int32_t tile, int par, int block);
 hipError_t launch_batch_copy_back(hipStream_t s, const SysDev *sys, const int32_t *blk_sys,
                                   const int32_t *blk_tile, int64_t nblocks, int32_t tile, int block);
 

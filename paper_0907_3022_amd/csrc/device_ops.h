@@ -14,6 +14,25 @@ namespace chebtd {
 // ---------------------------------------------------------------------------
 // complex helpers
 // ---------------------------------------------------------------------------
+// Global-memory access through pointers the compiler cannot prove global
+// (read from a descriptor in memory, or passed through several layers):
+// addressing the data through address-space-1 pointers gives global loads
+// and stores instead of flat ones.
+typedef __attribute__((address_space(1))) const double *gconst_f64;
+typedef __attribute__((address_space(1))) double *g_f64;
+__device__ __forceinline__ double2 ldg(const double2 *p, int64_t i)
+{
+    const gconst_f64 q = (gconst_f64)p;
+    return make_double2(q[2 * i], q[2 * i + 1]);
+}
+__device__ __forceinline__ double ldg(const double *p, int64_t i) { return ((gconst_f64)p)[i]; }
+__device__ __forceinline__ void stg(double2 *p, int64_t i, double2 v)
+{
+    const g_f64 q = (g_f64)p;
+    q[2 * i] = v.x;
+    q[2 * i + 1] = v.y;
+}
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
@@ -100,24 +119,24 @@ struct HoneyRow {
     __device__ static __forceinline__ double2 apply2(const OpHoney &op, int64_t i, int32_t x,
                                                      int32_t y, const double2 *v, double2 vi)
     {
-        const double d = op.s2 * (op.eps[i] - op.b);
+        const double d = op.s2 * (ldg(op.eps, i) - op.b);
         double2 s = make_double2(0.0, 0.0);
         const bool even = ((x + y) & 1) == 0;
         if (EDGE == CHEBTD_ZIGZAG) {
-            if (x > 0) s = v[i - 1];
-            if (x + 1 < op.L) s = cadd(s, v[i + 1]);
+            if (x > 0) s = ldg(v, i - 1);
+            if (x + 1 < op.L) s = cadd(s, ldg(v, i + 1));
             if (even) {
-                if (y + 1 < op.W) s = cadd(s, v[i + op.L]);
+                if (y + 1 < op.W) s = cadd(s, ldg(v, i + op.L));
             } else {
-                if (y > 0) s = cadd(s, v[i - op.L]);
+                if (y > 0) s = cadd(s, ldg(v, i - op.L));
             }
         } else {
-            if (y > 0) s = v[i - op.L];
-            if (y + 1 < op.W) s = cadd(s, v[i + op.L]);
+            if (y > 0) s = ldg(v, i - op.L);
+            if (y + 1 < op.W) s = cadd(s, ldg(v, i + op.L));
             if (even) {
-                if (x + 1 < op.L) s = cadd(s, v[i + 1]);
+                if (x + 1 < op.L) s = cadd(s, ldg(v, i + 1));
             } else {
-                if (x > 0) s = cadd(s, v[i - 1]);
+                if (x > 0) s = cadd(s, ldg(v, i - 1));
             }
         }
         return make_double2(fma(d, vi.x, op.off2 * s.x), fma(d, vi.y, op.off2 * s.y));

@@ -20,8 +20,12 @@ struct OpPair {
     int32_t xcd_remap;
 };
 
+constexpr int kPairStripCols = 62;  // columns a wavefront owns
+
 OpPair make_pair_op(const Ctx &c, int rows);
 int64_t pair_grid_blocks(const Ctx &c, int rows);
+// rows per wavefront chunk for a ribbon of W rows (api.cpp)
+int pair_rows_for_width(int64_t W);
 bool pair_supported(const Ctx &c);
 // head: v1 = H~ vk, v2 = 2 H~ v1 - vk, acc = g0 vk + g1 v1 + g2 v2 (+ partials, ckpt)
 // else: v_{k+1} = 2 H~ vk - vkm1, v_{k+2} = 2 H~ v_{k+1} - vk, acc += g1 v_{k+1} + g2 v_{k+2}

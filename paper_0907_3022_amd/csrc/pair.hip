@@ -3,61 +3,20 @@
 // finite-difference chain of Sect. 3.1 (arXiv:0907.3022, Sect. 2.2 recursion).
 //
 // One pass reads v_{k-1}, v_k, the on-site term and acc once and writes
-//   v_{k+1} = 2 H~ v_k - v_{k-1},   v_{k+2} = 2 H~ v_{k+1} - v_k,
-//   acc += g_{k+1} v_{k+1} + g_{k+2} v_{k+2}
-// (104 B per site for two orders instead of 2 x 88 B).  The head variant
-// starts a time step: v_1 = H~ psi, v_2 = 2 H~ v_1 - psi,
-// acc = g_0 psi + g_1 v_1 + g_2 v_2, plus the norm and energy partials.
-//
-// Mapping: each wavefront owns a strip of 62 columns and a chunk of rows.
-// Lane l holds column x = 62*strip + l - 1, so lanes 0 and 63 are halo
-// columns whose v_{k+1} the neighbouring lanes need for the second order.
-// The wavefront walks down its rows keeping three rows of v_k and three of
-// v_{k+1} in registers: vertical neighbours come from registers, horizontal
-// ones from the adjacent lanes (cross-lane shuffles); only lanes 0 and 63
-// load one extra v_k value per row.  A chunk of rows [ys, ye) computes
-// v_{k+1} on rows ys-1 .. ye (one halo row each side, recomputed by the
-// neighbouring chunk) and v_{k+2} on its own rows.  Outputs are written to
-// buffers distinct from the inputs, so no wavefront overwrites a value
-// another one still reads.
+// v_{k+1}, v_{k+2} and acc (104 B per site for two orders instead of
+// 2 x 88 B).  Each wavefront owns a strip of 62 columns and a chunk of rows
+// (pair_walk.h); wavefronts are numbered strip-fastest, so consecutive ones
+// read adjacent memory.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
 
 #include "device_ops.h"
 #include "internal.h"
 #include "pair.h"
+#include "pair_walk.h"
 
 namespace chebtd {
-
-namespace {
-
-constexpr int kStrip = 62;
-
-// Component-wise select by value.  A ternary between two double2 objects can
-// make the compiler pick between their addresses, which sends them through
-// scratch memory; selecting the scalars keeps everything in registers.
-__device__ __forceinline__ double2 csel(bool c, double2 a, double2 b)
-{
-    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
-}
-
-__device__ __forceinline__ double2 shfl_up1(double2 v)
-{
-    return make_double2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
-}
-__device__ __forceinline__ double2 shfl_down1(double2 v)
-{
-    return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
-}
-
-// Operands of one row loaded one iteration ahead: v_k of the row below,
-// and v_{k-1}, the on-site term, the outside v_k value (strip-edge lanes) and
-// acc of the row itself.
-struct Prefetch {
-    double2 a, km1, ext, acc;
-    double e;
-};
-
-}  // namespace
 
 template <int EDGE, bool HEAD>
 __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restrict__ vkm1,
@@ -67,123 +26,12 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                                               double *partials)
 {
     __shared__ double red[2 * 4];
-    const int lane = threadIdx.x & 63;
     const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
     const int32_t strip = gw % op.nstrips;
     const int32_t chunk = gw / op.nstrips;
-    const int32_t W = op.W, L = op.L;
-    const int32_t x = strip * kStrip + lane - 1;
-    const bool colok = x >= 0 && x < L;
-    const bool own = colok && lane >= 1 && lane <= kStrip;
-    const double2 zero = make_double2(0.0, 0.0);
     double nrm = 0.0, en = 0.0;
-
-    if (chunk < op.nchunks) {  // uniform per wavefront
-        const int32_t ys = chunk * op.rows;
-        const int32_t ye = min(ys + op.rows, W);
-        // Loads are unconditional, from a clamped index, and return the raw
-        // value; where a zero is needed outside the lattice it is selected
-        // when the value is used, one row later.  (A conditional load of
-        // memory or a local zero becomes a flat load of a selected pointer,
-        // and selecting right after the load would make every iteration wait
-        // for the prefetch it has just issued.)
-        auto okr = [&](int32_t r) -> bool { return colok && r >= 0 && r < W; };
-        auto ld = [&](const double2 *v, int32_t r) -> double2 {
-            return v[okr(r) ? (int64_t)r * L + x : 0];
-        };
-        auto ld_on = [&](int32_t r) -> double { return op.onsite[okr(r) ? (int64_t)r * L + x : 0]; };
-        // lanes 0 and 63 also need the v_k value just outside the strip
-        const int32_t xe = lane == 0 ? x - 1 : x + 1;
-        const bool ext_lane = (lane == 0 || lane == 63) && xe >= 0 && xe < L;
-        auto ok_ext = [&](int32_t r) -> bool { return ext_lane && r >= 0 && r < W; };
-        auto ld_ext = [&](int32_t r) -> double2 { return vk[ok_ext(r) ? (int64_t)r * L + xe : 0]; };
-        // operands of row r (v_k row r+1, v_{k-1}, on-site and outside value of
-        // row r, acc of row r-1) are loaded one iteration ahead; v_{k-1}, the
-        // on-site term and acc are only used where they are in range
-        double2 a_m1 = csel(okr(ys - 2), ld(vk, ys - 2), zero);  // v_k rows r-1, r
-        double2 a_0 = csel(okr(ys - 1), ld(vk, ys - 1), zero);
-        // Two sets of prefetch registers, used alternately: the loads issued
-        // for the next row are never copied (a copy would wait for them).
-        Prefetch p0, p1;
-        p0.a = ld(vk, ys);
-        p0.km1 = HEAD ? zero : ld(vkm1, ys - 1);
-        p0.e = ld_on(ys - 1);
-        p0.ext = ld_ext(ys - 1);
-        p0.acc = zero;
-        double2 b_m2 = zero, b_m1 = zero;  // v_{k+1} rows r-2, r-1
-        double e_m1 = 0.0;                 // on-site term, row r-1
-        // one row: prefetch row r+1 into nx, compute from cur
-        auto row_step = [&](int32_t r, const Prefetch &cur, Prefetch &nx) {
-            nx.a = ld(vk, r + 2);
-            nx.km1 = HEAD ? zero : ld(vkm1, r + 1);
-            nx.e = ld_on(r + 1);
-            nx.ext = ld_ext(r + 1);
-            if (!HEAD) {
-                const bool ok = own && r >= ys && r < ye;
-                nx.acc = acc[ok ? (int64_t)r * L + x : 0];
-            }
-            const double2 a_p1 = csel(okr(r + 1), cur.a, zero);
-            const double2 ext = csel(ok_ext(r), cur.ext, zero);
-            const double e_0 = cur.e;
-            const bool rowok = r >= 0 && r < W;
-            const int64_t ir = (int64_t)r * L + x;
-            // ---- first order at row r: v_{k+1} = 2 H~ v_k - v_{k-1} ----
-            double2 left = shfl_up1(a_0), right = shfl_down1(a_0);
-            left = csel(lane == 0, ext, left);
-            right = csel(lane == 63, ext, right);
-            const bool even_r = ((x + r) & 1) == 0;
-            double2 s;
-            if (EDGE == CHEBTD_ZIGZAG)
-                s = cadd(cadd(left, right), csel(even_r, a_p1, a_m1));
-            else
-                s = cadd(cadd(a_m1, a_p1), csel(even_r, right, left));
-            const double d0 = op.s2 * (e_0 + op.dshift);
-            const double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
-            double2 b_0 = HEAD ? cscale(0.5, h) : csub(h, cur.km1);
-            b_0 = csel(colok && rowok, b_0, zero);
-            if (own && r >= ys && r < ye) out1[ir] = b_0;
-            // ---- second order at row q = r-1: v_{k+2} = 2 H~ v_{k+1} - v_k ----
-            if (r - 1 >= ys) {
-                const int32_t q = r - 1;
-                const int64_t iq = (int64_t)q * L + x;
-                const double2 l2 = shfl_up1(b_m1), r2 = shfl_down1(b_m1);
-                const bool even_q = ((x + q) & 1) == 0;
-                double2 s2;
-                if (EDGE == CHEBTD_ZIGZAG)
-                    s2 = cadd(cadd(l2, r2), csel(even_q, b_0, b_m2));
-                else
-                    s2 = cadd(cadd(b_m2, b_0), csel(even_q, r2, l2));
-                const double d1 = op.s2 * (e_m1 + op.dshift);
-                const double2 h2 = make_double2(fma(d1, b_m1.x, op.off2 * s2.x), fma(d1, b_m1.y, op.off2 * s2.y));
-                const double2 c = csub(h2, a_m1);
-                if (own) {
-                    out2[iq] = c;
-                    double2 a;
-                    if (HEAD) {
-                        a = cfma(g0, a_m1, zero);
-                        if (ckpt) ckpt[iq] = a_m1;
-                        nrm += a_m1.x * a_m1.x + a_m1.y * a_m1.y;
-                        en += a_m1.x * b_m1.x + a_m1.y * b_m1.y;
-                    } else {
-                        a = cur.acc;  // acc of row q, loaded with the previous row
-                    }
-                    a = cfma(g1, b_m1, a);
-                    acc[iq] = cfma(g2, c, a);
-                }
-            }
-            a_m1 = a_0;
-            a_0 = a_p1;
-            b_m2 = b_m1;
-            b_m1 = b_0;
-            e_m1 = e_0;
-        };
-        int32_t r = ys - 1;
-        for (; r + 1 <= ye; r += 2) {
-            row_step(r, p0, p1);
-            row_step(r + 1, p1, p0);
-        }
-        if (r <= ye) row_step(r, p0, p1);
-    }
+    if (chunk < op.nchunks)  // uniform per wavefront
+        pair_walk<EDGE, HEAD>(op, strip, chunk, vkm1, vk, out1, out2, acc, g0, g1, g2, ckpt, nrm, en);
     if (HEAD) {
         block_sum2(nrm, en, red);
         if (threadIdx.x == 0) {
@@ -211,7 +59,7 @@ OpPair make_pair_op(const Ctx &c, int rows)
         op.L = (int32_t)c.L;
     }
     op.rows = rows < 1 ? 1 : rows;
-    op.nstrips = (op.L + kStrip - 1) / kStrip;
+    op.nstrips = (op.L + kPairStrip - 1) / kPairStrip;
     op.nchunks = (op.W + op.rows - 1) / op.rows;
     op.xcd_remap = 1;
     return op;
