@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "pair.h"
 
 namespace chebtd {
 int fail(Ctx *c, int code, const std::string &msg);
@@ -67,24 +68,66 @@ double2 conj_weight(const Ctx *c, int k)
     return make_double2(c->gamma[2 * (size_t)k], -c->gamma[2 * (size_t)k + 1]);
 }
 
+// The adjoint vectors in flight: u_{k+1} (uk1) and u_{k+2} (uk2, absent
+// right after u_M), rotated through four buffers so that a two-level pass
+// writes to buffers its neighbours are not reading.
+struct URot {
+    double2 *buf[4];
+    double2 *uk1 = nullptr, *uk2 = nullptr;
+    bool has2 = false;
+    void start(double2 *uM)
+    {
+        uk1 = uM;
+        uk2 = nullptr;
+        has2 = false;
+    }
+    // two buffers holding neither uk1 nor uk2
+    void spare(double2 **a, double2 **b) const
+    {
+        int got = 0;
+        for (double2 *p : buf)
+            if (p != uk1 && p != uk2) {
+                (got == 0 ? *a : *b) = p;
+                if (++got == 2) return;
+            }
+    }
+};
+
 // Reverse sweep of one step for levels k = kend-1 .. kbeg, with the forward
-// vectors v_k available as vk(k).  U[0], U[1] hold u_{k+1}, u_{k+2}
-// alternately; u_k for k >= 1 goes to U[(M-k) & 1]; level 0 writes gbar.
+// vectors v_k available as vk(k).  Levels k, k-1 >= 1 go two per pass on
+// chains and ribbons (pair_supported); a level left alone writes u_k over
+// u_{k+2} (own site only); level 0 writes u_0 over gbar.
 template <class VK>
-hipError_t sweep_levels(Ctx *c, hipStream_t s, int kbeg, int kend, VK vk, double2 *gbar, double *grad,
-                        double2 *U0, double2 *U1)
+hipError_t sweep_levels(Ctx *c, hipStream_t s, int kbeg, int kend, VK vk, double2 *gbar, double *grad, URot &u)
 {
-    const int M = c->M;
-    double2 *U[2] = {U0, U1};
+    const bool pairs = pair_supported(*c);
     hipError_t e = hipSuccess;
-    for (int k = kend - 1; k >= kbeg && e == hipSuccess; --k) {
-        double2 *u1 = U[(M - (k + 1)) & 1];  // u_{k+1}
-        double2 *u2 = U[(M - (k + 2)) & 1];  // u_{k+2} (absent when k+2 > M)
-        const int has_u2 = (k + 2 <= M);
-        if (k >= 1)
-            e = launch_adj_level(*c, s, u1, u2, gbar, u2, vk(k), conj_weight(c, k), 2.0, has_u2, grad);
-        else
-            e = launch_adj_level(*c, s, u1, u2, gbar, gbar, vk(0), conj_weight(c, 0), 1.0, has_u2, grad);
+    int k = kend - 1;
+    while (k >= kbeg && e == hipSuccess) {
+        if (pairs && k - 1 >= std::max(kbeg, 1)) {
+            double2 *o1, *o2;
+            u.spare(&o1, &o2);
+            e = launch_adj_pair(*c, s, u.has2, u.uk2, u.uk1, o1, o2, gbar, vk(k), vk(k - 1), conj_weight(c, k),
+                                conj_weight(c, k - 1), grad);
+            u.uk2 = o1;  // u_k
+            u.uk1 = o2;  // u_{k-1}
+            u.has2 = true;
+            k -= 2;
+        } else if (k >= 1) {
+            double2 *out = u.uk2;
+            if (!u.has2) {
+                double2 *o2;
+                u.spare(&out, &o2);
+            }
+            e = launch_adj_level(*c, s, u.uk1, u.uk2, gbar, out, vk(k), conj_weight(c, k), 2.0, u.has2, grad);
+            u.uk2 = u.uk1;
+            u.uk1 = out;
+            u.has2 = true;
+            k -= 1;
+        } else {
+            e = launch_adj_level(*c, s, u.uk1, u.uk2, gbar, gbar, vk(0), conj_weight(c, 0), 1.0, u.has2, grad);
+            k -= 1;
+        }
     }
     return e;
 }
@@ -112,7 +155,7 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
     a->seg = std::max(1, (int)std::ceil(std::sqrt((double)std::max(M, 1))));
     int rc;
     if ((rc = ensure(c, a->ckpt, vb * (size_t)max_steps, "adjoint checkpoints"))) return rc;
-    if ((rc = ensure(c, a->u, 2 * vb, "adjoint vectors"))) return rc;
+    if ((rc = ensure(c, a->u, 4 * vb, "adjoint vectors"))) return rc;
     if (mode == CHEBTD_ADJ_STEP) {
         release(a->pairs);
         if ((rc = ensure(c, a->vbuf, vb * (size_t)(M + 1), "recompute buffer"))) return rc;
@@ -143,7 +186,9 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
     double2 *gbar = reinterpret_cast<double2 *>(gbar_dev);
     double2 *ck = static_cast<double2 *>(a->ckpt.p);
     double2 *vb = static_cast<double2 *>(a->vbuf.p);
-    double2 *U0 = static_cast<double2 *>(a->u.p), *U1 = U0 + n;
+    URot urot;
+    for (int q = 0; q < 4; ++q) urot.buf[q] = static_cast<double2 *>(a->u.p) + (size_t)q * n;
+    const bool pairs = pair_supported(*c);
     hipError_t e = hipSuccess;
     for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {
         double2 *psi_s = ck + (size_t)st * n;
@@ -152,14 +197,22 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
             continue;
         }
         // u_M = conj(gamma_M) gbar
-        e = launch_adj_init(s, gbar, conj_weight(c, M), U0, n);
+        urot.start(urot.buf[0]);
+        e = launch_adj_init(s, gbar, conj_weight(c, M), urot.uk1, n);
         if (e != hipSuccess) break;
         if (a->mode == CHEBTD_ADJ_STEP) {
             // v_0 = psi_s (the checkpoint itself), v_1 .. v_M into the buffer
             auto vk = [&](int k) -> double2 * { return k == 0 ? psi_s : vb + (size_t)k * n; };
-            for (int k = 0; k + 1 <= M - 1 && e == hipSuccess; ++k)
+            int k = 0;  // v_0 .. v_k are known
+            if (pairs && M - 1 >= 2) {
+                e = launch_recompute_pair(*c, s, true, nullptr, psi_s, vk(1), vk(2));
+                k = 2;
+                for (; k + 2 <= M - 1 && e == hipSuccess; k += 2)
+                    e = launch_recompute_pair(*c, s, false, vk(k - 1), vk(k), vk(k + 1), vk(k + 2));
+            }
+            for (; k + 1 <= M - 1 && e == hipSuccess; ++k)
                 e = launch_recompute(*c, s, vk(k), k ? vk(k - 1) : nullptr, vk(k + 1), k == 0);
-            if (e == hipSuccess) e = sweep_levels(c, s, 0, M, vk, gbar, dLdV_dev, U0, U1);
+            if (e == hipSuccess) e = sweep_levels(c, s, 0, M, vk, gbar, dLdV_dev, urot);
         } else {
             // forward pass keeping (v_{qS-1}, v_{qS}) for segments q >= 1
             const int S = a->seg, nseg = (M + S - 1) / S;
@@ -206,7 +259,7 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
                     const double2 *km = (k == k0) ? prev : vk(k - 1);
                     e = launch_recompute(*c, s, cur, km, vb + (size_t)(k + 1 - k0) * n, k == 0);
                 }
-                if (e == hipSuccess) e = sweep_levels(c, s, k0, k1, vk, gbar, dLdV_dev, U0, U1);
+                if (e == hipSuccess) e = sweep_levels(c, s, k0, k1, vk, gbar, dLdV_dev, urot);
             }
         }
     }

@@ -13,6 +13,8 @@
 
 #include "device_ops.h"
 #include "internal.h"
+#include "pair.h"
+#include "pair_walk.h"
 
 namespace chebtd {
 
@@ -88,6 +90,209 @@ __global__ __launch_bounds__(kBlock) void k_adj_level_honey(OpHoney op, const do
     const double2 ui = u1[i];
     level_body(i, HoneyRow<EDGE>::apply2(op, i, x, y, u1, ui), ui, u2, out, gbar, vk, gk, half, gfac,
                grad);
+}
+
+// ---------------------------------------------------------------------------
+// Two levels per pass (brick-wall lattices: ribbons, and the chain as a
+// ribbon of one row), walked like the forward pair kernel (pair_walk.h).
+// ---------------------------------------------------------------------------
+
+// Forward vectors without accumulation: head v_1 = H~ psi, v_2 = 2 H~ v_1 -
+// psi; else v_{k+1}, v_{k+2} from (v_{k-1}, v_k).
+template <int EDGE, bool HEAD>
+__global__ __launch_bounds__(256) void k_recompute_pair(OpPair op, const double2 *__restrict__ vkm1,
+                                                        const double2 *__restrict__ vk, double2 *__restrict__ out1,
+                                                        double2 *__restrict__ out2)
+{
+    const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
+    const int32_t strip = gw % op.nstrips, chunk = gw / op.nstrips;
+    const double2 zero = make_double2(0.0, 0.0);
+    double nrm = 0.0, en = 0.0;
+    if (chunk < op.nchunks)
+        pair_walk<EDGE, HEAD, false>(op, strip, chunk, vkm1, vk, out1, out2, nullptr, zero, zero, zero, nullptr,
+                                     nrm, en);
+}
+
+namespace {
+// operands of one row loaded one iteration ahead (see pair_walk.h)
+struct AdjPrefetch {
+    double2 a, km1, ext, gb, vk, vkm1;
+    double e, grad;
+};
+}  // namespace
+
+// Reverse levels k and k-1 (k-1 >= 1) of the wavefront's strip and chunk:
+//   u_k     = cg1 gbar + 2 H~ u_{k+1} - u_{k+2}  (rows ys-1 .. ye; halo rows
+//             are recomputed, not stored)
+//   u_{k-1} = cg2 gbar + 2 H~ u_k - u_{k+1}      (own rows)
+//   grad   += gf (Re[conj(u_{k+1}) v_k] + Re[conj(u_k) v_{k-1}])
+// with cg1 = conj(g_k), cg2 = conj(g_{k-1}), gf = 2/a; without HAS_U2,
+// u_{k+2} = 0 (k = M-1).  Outputs go to buffers distinct from the inputs.
+template <int EDGE, bool HAS_U2>
+__device__ __forceinline__ void adj_pair_walk(const OpPair &op, int32_t strip, int32_t chunk,
+                                              const double2 *__restrict__ uk2, const double2 *__restrict__ uk1,
+                                              double2 *__restrict__ out1, double2 *__restrict__ out2,
+                                              const double2 *__restrict__ gbar, const double2 *__restrict__ vk,
+                                              const double2 *__restrict__ vkm1, double2 cg1, double2 cg2,
+                                              double gf, double *__restrict__ grad)
+{
+    using namespace pairdev;
+    const int lane = threadIdx.x & 63;
+    const int32_t W = op.W, L = op.L;
+    const int32_t x = strip * kPairStrip + lane - 1;
+    const bool colok = x >= 0 && x < L;
+    const bool own = colok && lane >= 1 && lane <= kPairStrip;
+    const double2 zero = make_double2(0.0, 0.0);
+    const int32_t ys = chunk * op.rows;
+    const int32_t ye = min(ys + op.rows, W);
+    auto okr = [&](int32_t r) -> bool { return colok && r >= 0 && r < W; };
+    auto ld = [&](const double2 *v, int32_t r) -> double2 { return ldg(v, okr(r) ? (int64_t)r * L + x : 0); };
+    auto ld_on = [&](int32_t r) -> double { return ldg(op.onsite, okr(r) ? (int64_t)r * L + x : 0); };
+    const int32_t xe = lane == 0 ? x - 1 : x + 1;
+    const bool ext_lane = (lane == 0 || lane == 63) && xe >= 0 && xe < L;
+    auto ok_ext = [&](int32_t r) -> bool { return ext_lane && r >= 0 && r < W; };
+    auto ld_ext = [&](int32_t r) -> double2 { return ldg(uk1, ok_ext(r) ? (int64_t)r * L + xe : 0); };
+    double2 a_m1 = csel(okr(ys - 2), ld(uk1, ys - 2), zero);  // u_{k+1} rows r-1, r
+    double2 a_0 = csel(okr(ys - 1), ld(uk1, ys - 1), zero);
+    AdjPrefetch p0, p1;
+    p0.a = ld(uk1, ys);
+    p0.km1 = HAS_U2 ? ld(uk2, ys - 1) : zero;
+    p0.gb = ld(gbar, ys - 1);
+    p0.e = ld_on(ys - 1);
+    p0.ext = ld_ext(ys - 1);
+    p0.vk = p0.vkm1 = zero;
+    p0.grad = 0.0;
+    double2 b_m2 = zero, b_m1 = zero;  // u_k rows r-2, r-1
+    double e_m1 = 0.0;                 // on-site term, row r-1
+    double2 gb_m1 = zero;              // gbar, row r-1
+    auto row_step = [&](int32_t r, const AdjPrefetch &cur, AdjPrefetch &nx) {
+        nx.a = ld(uk1, r + 2);
+        nx.km1 = HAS_U2 ? ld(uk2, r + 1) : zero;
+        nx.gb = ld(gbar, r + 1);
+        nx.e = ld_on(r + 1);
+        nx.ext = ld_ext(r + 1);
+        {
+            const bool ok = own && r >= ys && r < ye;
+            const int64_t io = ok ? (int64_t)r * L + x : 0;
+            nx.vk = ldg(vk, io);
+            nx.vkm1 = ldg(vkm1, io);
+            nx.grad = ldg(grad, io);
+        }
+        const double2 a_p1 = csel(okr(r + 1), cur.a, zero);
+        const double2 ext = csel(ok_ext(r), cur.ext, zero);
+        const bool rowok = r >= 0 && r < W;
+        const int64_t ir = (int64_t)r * L + x;
+        // ---- level k at row r ----
+        double2 left = shfl_up1(a_0), right = shfl_down1(a_0);
+        left = csel(lane == 0, ext, left);
+        right = csel(lane == 63, ext, right);
+        const bool even_r = ((x + r) & 1) == 0;
+        double2 s;
+        if (EDGE == CHEBTD_ZIGZAG)
+            s = cadd(cadd(left, right), csel(even_r, a_p1, a_m1));
+        else
+            s = cadd(cadd(a_m1, a_p1), csel(even_r, right, left));
+        const double d0 = op.s2 * (cur.e + op.dshift);
+        const double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
+        double2 b_0 = cfma(cg1, cur.gb, HAS_U2 ? csub(h, cur.km1) : h);
+        b_0 = csel(colok && rowok, b_0, zero);
+        if (own && r >= ys && r < ye) stg(out1, ir, b_0);
+        // ---- level k-1 at row q = r-1 ----
+        if (r - 1 >= ys) {
+            const int32_t q = r - 1;
+            const int64_t iq = (int64_t)q * L + x;
+            const double2 l2 = shfl_up1(b_m1), r2 = shfl_down1(b_m1);
+            const bool even_q = ((x + q) & 1) == 0;
+            double2 s2;
+            if (EDGE == CHEBTD_ZIGZAG)
+                s2 = cadd(cadd(l2, r2), csel(even_q, b_0, b_m2));
+            else
+                s2 = cadd(cadd(b_m2, b_0), csel(even_q, r2, l2));
+            const double d1 = op.s2 * (e_m1 + op.dshift);
+            const double2 h2 = make_double2(fma(d1, b_m1.x, op.off2 * s2.x), fma(d1, b_m1.y, op.off2 * s2.y));
+            const double2 c = cfma(cg2, gb_m1, csub(h2, a_m1));
+            if (own) {
+                stg(out2, iq, c);
+                // own-row operands of row q were loaded with the previous row
+                const double t1 = a_m1.x * cur.vk.x + a_m1.y * cur.vk.y;
+                const double t2 = b_m1.x * cur.vkm1.x + b_m1.y * cur.vkm1.y;
+                // grouped as two single-level updates, level k first, so
+                // every pairing of the levels gives the same bits
+                const double gk = cur.grad + gf * t1;
+                stg(grad, iq, gk + gf * t2);
+            }
+        }
+        a_m1 = a_0;
+        a_0 = a_p1;
+        b_m2 = b_m1;
+        b_m1 = b_0;
+        e_m1 = cur.e;
+        gb_m1 = cur.gb;
+    };
+    int32_t r = ys - 1;
+    for (; r + 1 <= ye; r += 2) {
+        row_step(r, p0, p1);
+        row_step(r + 1, p1, p0);
+    }
+    if (r <= ye) row_step(r, p0, p1);
+}
+
+template <int EDGE, bool HAS_U2>
+__global__ __launch_bounds__(256) void k_adj_pair(OpPair op, const double2 *__restrict__ uk2,
+                                                  const double2 *__restrict__ uk1, double2 *__restrict__ out1,
+                                                  double2 *__restrict__ out2, const double2 *__restrict__ gbar,
+                                                  const double2 *__restrict__ vk, const double2 *__restrict__ vkm1,
+                                                  double2 cg1, double2 cg2, double gf, double *__restrict__ grad)
+{
+    const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
+    const int32_t strip = gw % op.nstrips, chunk = gw / op.nstrips;
+    if (chunk < op.nchunks)
+        adj_pair_walk<EDGE, HAS_U2>(op, strip, chunk, uk2, uk1, out1, out2, gbar, vk, vkm1, cg1, cg2, gf, grad);
+}
+
+hipError_t launch_recompute_pair(const Ctx &c, hipStream_t s, bool head, const double2 *vkm1, const double2 *vk,
+                                 double2 *out1, double2 *out2)
+{
+    const OpPair op = make_pair_op(c, c.pair_rows);
+    const int64_t nb = pair_grid_blocks(c, c.pair_rows);
+    if (nb <= 0 || nb > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    if (head && zig)
+        hipLaunchKernelGGL((k_recompute_pair<CHEBTD_ZIGZAG, true>), grid, block, 0, s, op, vkm1, vk, out1, out2);
+    else if (head)
+        hipLaunchKernelGGL((k_recompute_pair<CHEBTD_ARMCHAIR, true>), grid, block, 0, s, op, vkm1, vk, out1, out2);
+    else if (zig)
+        hipLaunchKernelGGL((k_recompute_pair<CHEBTD_ZIGZAG, false>), grid, block, 0, s, op, vkm1, vk, out1, out2);
+    else
+        hipLaunchKernelGGL((k_recompute_pair<CHEBTD_ARMCHAIR, false>), grid, block, 0, s, op, vkm1, vk, out1,
+                           out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_pair(const Ctx &c, hipStream_t s, bool has_u2, const double2 *uk2, const double2 *uk1,
+                           double2 *out1, double2 *out2, const double2 *gbar, const double2 *vk,
+                           const double2 *vkm1, double2 cg1, double2 cg2, double *grad)
+{
+    const OpPair op = make_pair_op(c, c.pair_rows);
+    const int64_t nb = pair_grid_blocks(c, c.pair_rows);
+    if (nb <= 0 || nb > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    const double gf = 2.0 / c.a;
+    if (zig && has_u2)
+        hipLaunchKernelGGL((k_adj_pair<CHEBTD_ZIGZAG, true>), grid, block, 0, s, op, uk2, uk1, out1, out2, gbar, vk,
+                           vkm1, cg1, cg2, gf, grad);
+    else if (zig)
+        hipLaunchKernelGGL((k_adj_pair<CHEBTD_ZIGZAG, false>), grid, block, 0, s, op, uk2, uk1, out1, out2, gbar,
+                           vk, vkm1, cg1, cg2, gf, grad);
+    else if (has_u2)
+        hipLaunchKernelGGL((k_adj_pair<CHEBTD_ARMCHAIR, true>), grid, block, 0, s, op, uk2, uk1, out1, out2, gbar,
+                           vk, vkm1, cg1, cg2, gf, grad);
+    else
+        hipLaunchKernelGGL((k_adj_pair<CHEBTD_ARMCHAIR, false>), grid, block, 0, s, op, uk2, uk1, out1, out2, gbar,
+                           vk, vkm1, cg1, cg2, gf, grad);
+    return hipGetLastError();
 }
 
 hipError_t launch_recompute(const Ctx &c, hipStream_t s, const double2 *vk, const double2 *vkm1,

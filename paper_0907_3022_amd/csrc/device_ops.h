@@ -26,6 +26,7 @@ __device__ __forceinline__ double2 ldg(const double2 *p, int64_t i)
     return make_double2(q[2 * i], q[2 * i + 1]);
 }
 __device__ __forceinline__ double ldg(const double *p, int64_t i) { return ((gconst_f64)p)[i]; }
+__device__ __forceinline__ void stg(double *p, int64_t i, double v) { ((g_f64)p)[i] = v; }
 __device__ __forceinline__ void stg(double2 *p, int64_t i, double2 v)
 {
     const g_f64 q = (g_f64)p;

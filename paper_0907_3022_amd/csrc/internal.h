@@ -203,6 +203,13 @@ hipError_t launch_csr_check(hipStream_t s, const int64_t *rowptr, const int32_t 
 // adjoint kernels (adjoint.hip)
 hipError_t launch_recompute(const Ctx &c, hipStream_t s, const double2 *vk, const double2 *vkm1,
                             double2 *vkp1, int first);
+// two orders per pass for chains and ribbons (adjoint.hip): the forward
+// vectors without accumulation, and reverse levels k, k-1 together
+hipError_t launch_recompute_pair(const Ctx &c, hipStream_t s, bool head, const double2 *vkm1, const double2 *vk,
+                                 double2 *out1, double2 *out2);
+hipError_t launch_adj_pair(const Ctx &c, hipStream_t s, bool has_u2, const double2 *uk2, const double2 *uk1,
+                           double2 *out1, double2 *out2, const double2 *gbar, const double2 *vk,
+                           const double2 *vkm1, double2 cg1, double2 cg2, double *grad);
 hipError_t launch_adj_init(hipStream_t s, const double2 *gbar, double2 g, double2 *u, int64_t n);
 hipError_t launch_adj_level(const Ctx &c, hipStream_t s, const double2 *u1, double2 *u2_in,
                             const double2 *gbar_in, double2 *out, const double2 *vk, double2 gk,

@@ -59,8 +59,10 @@ struct Prefetch {
 
 // The wavefront's share: strip `strip` (62 columns), rows
 // [chunk*op.rows, min((chunk+1)*op.rows, W)).  nrm/en accumulate the head's
-// norm and energy terms of the lane's own sites.
-template <int EDGE, bool HEAD>
+// norm and energy terms of the lane's own sites.  Without ACC only the two
+// new vectors are written (the adjoint's recomputation of the forward
+// vectors): acc, the weights, ckpt and the sums are not touched.
+template <int EDGE, bool HEAD, bool ACC = true>
 __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32_t chunk,
                                           const double2 *__restrict__ vkm1, const double2 *__restrict__ vk,
                                           double2 *__restrict__ out1, double2 *__restrict__ out2,
@@ -113,7 +115,7 @@ __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32
         nx.km1 = HEAD ? zero : ld(vkm1, r + 1);
         nx.e = ld_on(r + 1);
         nx.ext = ld_ext(r + 1);
-        if (!HEAD) {
+        if (ACC && !HEAD) {
             const bool ok = own && r >= ys && r < ye;
             nx.acc = ldg(acc, ok ? (int64_t)r * L + x : 0);
         }
@@ -151,8 +153,8 @@ __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32
             const double d1 = op.s2 * (e_m1 + op.dshift);
             const double2 h2 = make_double2(fma(d1, b_m1.x, op.off2 * s2.x), fma(d1, b_m1.y, op.off2 * s2.y));
             const double2 c = csub(h2, a_m1);
-            if (own) {
-                stg(out2, iq, c);
+            if (own) stg(out2, iq, c);
+            if (ACC && own) {
                 double2 a;
                 if (HEAD) {
                     a = cfma(g0, a_m1, zero);

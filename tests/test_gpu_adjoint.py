@@ -86,6 +86,35 @@ def test_adjoint_matches_oracle(torch, cheb, case, mode):
     assert rel_l2(u0, ur) <= 1e-10
 
 
+# z = a dt from 1e-9 to 0.3 gives M = 1, 2, 3, 4, 5, 6, 10: the reverse sweep
+# pairs levels two by two where it can and leaves single levels (odd counts,
+# level 0, the level next to u_M) to the one-level kernel
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", ["chain", "zigzag", "armchair"])
+@pytest.mark.parametrize("z", [1e-9, 1e-7, 3e-4, 1e-3, 0.01, 0.02, 0.3])
+def test_adjoint_low_orders(torch, cheb, case, mode, z):
+    if case == "chain":
+        dx, V, psi0, mask = chain_inputs(257)
+        H = O.chain1d(V, dx)
+        geom, kind = dict(dx=dx), "chain"
+    else:
+        V, psi0, mask = ribbon_inputs(9, 70)
+        H = O.honeycomb(9, 70, V, edge=case)
+        geom, kind = dict(width=9, length=70, edge=case), "honeycomb"
+    lo, hi = H.gershgorin()
+    dt = z / (0.5 * 1.01 * (hi - lo))
+    K = 3
+    Lg, g, u0, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, (lo, hi), dt, K, mode)
+    plan = O.Plan(lo, hi, dt)
+    assert prop.M == plan.M
+    Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
+    assert Lg == pytest.approx(Lr, rel=1e-10)
+    # at tiny dt dL/dV is O(dt^2) while its terms are O(1): both sides carry
+    # rounding noise of ~1e-16 per term, hence the absolute floor
+    assert np.linalg.norm(g - gr) <= 1e-8 * np.linalg.norm(gr) + 1e-12
+    assert rel_l2(u0, ur) <= 1e-10
+
+
 def test_adjoint_modes_agree_bitwise_free(torch, cheb):
     # the two memory schedules rebuild the same v_k by the same kernels
     w, l = 16, 200
