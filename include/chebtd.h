@@ -312,7 +312,9 @@ int chebtd_batch_info(const chebtd_ctx *ctx, int *nsys, int *M_host);
 #define CHEBTD_ADJ_STEP 0  /* recompute each step's M+1 vectors into a     */
                            /* buffer, then sweep back                       */
 #define CHEBTD_ADJ_SQRTM 1 /* keep (v_{j-1}, v_j) every ceil(sqrt(M))      */
-                           /* orders and recompute segment by segment       */
+                           /* orders (rounded up to even for chains and    */
+                           /* ribbons, which recompute two orders a pass)  */
+                           /* and recompute segment by segment              */
 
 /* Allocate the adjoint's storage: psi checkpoints for up to max_steps steps
  * and the recompute buffers of `mode`.  Needs a plan (chain or honeycomb). */

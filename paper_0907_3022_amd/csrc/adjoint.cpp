@@ -1,8 +1,9 @@
 // Host side of the adjoint: storage schedules and the reverse sweep over
 // time steps.  The forward run keeps psi at the start of every step; the
 // backward run rebuilds that step's Chebyshev vectors from it (all M+1 of
-// them, or in segments of ceil(sqrt(M)) orders from (v_{j-1}, v_j) pairs)
-// and runs the reverse recursion level by level (adjoint.hip).
+// them, or in segments of about sqrt(M) orders from (v_{j-1}, v_j) pairs)
+// and runs the reverse recursion, two levels per pass where it can
+// (adjoint.hip).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -152,7 +153,10 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
     a->mode = mode;
     a->max_steps = max_steps;
     a->M = M;
+    // ceil(sqrt(M)) orders per segment, rounded up to even so that the
+    // two-orders-per-pass recomputation ends exactly on segment boundaries
     a->seg = std::max(1, (int)std::ceil(std::sqrt((double)std::max(M, 1))));
+    if (pair_supported(*c)) a->seg += a->seg & 1;
     int rc;
     if ((rc = ensure(c, a->ckpt, vb * (size_t)max_steps, "adjoint checkpoints"))) return rc;
     if ((rc = ensure(c, a->u, 4 * vb, "adjoint vectors"))) return rc;
@@ -188,7 +192,7 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
     double2 *vb = static_cast<double2 *>(a->vbuf.p);
     URot urot;
     for (int q = 0; q < 4; ++q) urot.buf[q] = static_cast<double2 *>(a->u.p) + (size_t)q * n;
-    const bool pairs = pair_supported(*c);
+    const bool pairs_on = pair_supported(*c);
     hipError_t e = hipSuccess;
     for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {
         double2 *psi_s = ck + (size_t)st * n;
@@ -204,7 +208,7 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
             // v_0 = psi_s (the checkpoint itself), v_1 .. v_M into the buffer
             auto vk = [&](int k) -> double2 * { return k == 0 ? psi_s : vb + (size_t)k * n; };
             int k = 0;  // v_0 .. v_k are known
-            if (pairs && M - 1 >= 2) {
+            if (pairs_on && M - 1 >= 2) {
                 e = launch_recompute_pair(*c, s, true, nullptr, psi_s, vk(1), vk(2));
                 k = 2;
                 for (; k + 2 <= M - 1 && e == hipSuccess; k += 2)
@@ -217,9 +221,52 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
             // forward pass keeping (v_{qS-1}, v_{qS}) for segments q >= 1
             const int S = a->seg, nseg = (M + S - 1) / S;
             double2 *pairs = static_cast<double2 *>(a->pairs.p);
+            const int kmax = (nseg - 1) * S;  // the last boundary order needed
+            if (pairs_on && S % 2 == 0 && S >= 4) {
+                // two orders per pass; a pass that ends on a boundary writes
+                // straight into that boundary's pair, the others rotate
+                // through four scratch vectors
+                const double2 *in1 = nullptr, *in2 = psi_s;  // (v_{k-1}, v_k)
+                for (int k = 0; k < kmax && e == hipSuccess; k += 2) {
+                    double2 *o1 = nullptr, *o2 = nullptr;
+                    if ((k + 2) % S == 0) {
+                        const int q = (k + 2) / S;
+                        o1 = pairs + (size_t)(2 * q) * n;
+                        o2 = pairs + (size_t)(2 * q + 1) * n;
+                    } else {
+                        for (int j = 0; j < 4; ++j) {
+                            double2 *p = vb + (size_t)j * n;
+                            if (p == in1 || p == in2) continue;
+                            if (!o1)
+                                o1 = p;
+                            else if (!o2)
+                                o2 = p;
+                        }
+                    }
+                    e = launch_recompute_pair(*c, s, k == 0, in1, in2, o1, o2);
+                    in1 = o1;
+                    in2 = o2;
+                }
+                // segments in reverse: v_{k0-1}, v_{k0} come from the pair
+                // storage, v_{k0+1} .. v_{k1-1} into buffer slots 1 ..
+                for (int q = nseg - 1; q >= 0 && e == hipSuccess; --q) {
+                    const int k0 = q * S, k1 = std::min(k0 + S, M);
+                    double2 *prev = q > 0 ? pairs + (size_t)(2 * q) * n : nullptr;
+                    double2 *first = q > 0 ? pairs + (size_t)(2 * q + 1) * n : psi_s;
+                    auto vk = [&](int k) -> double2 * { return k == k0 ? first : vb + (size_t)(k - k0) * n; };
+                    auto vkm = [&](int k) -> double2 * { return k == k0 ? prev : vk(k - 1); };
+                    int j = 0;  // v_{k0} .. v_{k0+j} are known
+                    for (; k0 + j + 2 <= k1 - 1 && e == hipSuccess; j += 2)
+                        e = launch_recompute_pair(*c, s, k0 + j == 0, vkm(k0 + j), vk(k0 + j), vk(k0 + j + 1),
+                                                  vk(k0 + j + 2));
+                    if (k0 + j + 1 <= k1 - 1 && e == hipSuccess)
+                        e = launch_recompute(*c, s, vk(k0 + j), vkm(k0 + j), vk(k0 + j + 1), k0 + j == 0);
+                    if (e == hipSuccess) e = sweep_levels(c, s, k0, k1, vk, gbar, dLdV_dev, urot);
+                }
+                continue;
+            }
             double2 *w0 = vb, *w1 = vb + n, *w2 = vb + 2 * (size_t)n;  // rotating scratch
             // v_0 = psi_s; compute up to v_{(nseg-1) S}
-            const int kmax = (nseg - 1) * S;
             const double2 *km1 = nullptr, *kc = psi_s;
             double2 *rot[3] = {w0, w1, w2};
             for (int k = 0; k < kmax && e == hipSuccess; ++k) {
