@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_recompute_pair(OpPair op, const double2
                                                         const double2 *__restrict__ vk, double2 *__restrict__ out1,
                                                         double2 *__restrict__ out2)
 {
-    const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
+    const int32_t gw = __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % op.nstrips, chunk = gw / op.nstrips;
     const double2 zero = make_double2(0.0, 0.0);
     double nrm = 0.0, en = 0.0;
@@ -183,9 +183,7 @@ __device__ __forceinline__ void adj_pair_walk(const OpPair &op, int32_t strip, i
         const bool rowok = r >= 0 && r < W;
         const int64_t ir = (int64_t)r * L + x;
         // ---- level k at row r ----
-        double2 left = shfl_up1(a_0), right = shfl_down1(a_0);
-        left = csel(lane == 0, ext, left);
-        right = csel(lane == 63, ext, right);
+        const double2 left = from_left(a_0, ext), right = from_right(a_0, ext);
         const bool even_r = ((x + r) & 1) == 0;
         double2 s;
         if (EDGE == CHEBTD_ZIGZAG)
@@ -201,7 +199,7 @@ __device__ __forceinline__ void adj_pair_walk(const OpPair &op, int32_t strip, i
         if (r - 1 >= ys) {
             const int32_t q = r - 1;
             const int64_t iq = (int64_t)q * L + x;
-            const double2 l2 = shfl_up1(b_m1), r2 = shfl_down1(b_m1);
+            const double2 l2 = from_left0(b_m1), r2 = from_right0(b_m1);
             const bool even_q = ((x + q) & 1) == 0;
             double2 s2;
             if (EDGE == CHEBTD_ZIGZAG)
@@ -244,7 +242,7 @@ __global__ __launch_bounds__(256) void k_adj_pair(OpPair op, const double2 *__re
                                                   const double2 *__restrict__ vk, const double2 *__restrict__ vkm1,
                                                   double2 cg1, double2 cg2, double gf, double *__restrict__ grad)
 {
-    const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
+    const int32_t gw = __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % op.nstrips, chunk = gw / op.nstrips;
     if (chunk < op.nchunks)
         adj_pair_walk<EDGE, HAS_U2>(op, strip, chunk, uk2, uk1, out1, out2, gbar, vk, vkm1, cg1, cg2, gf, grad);

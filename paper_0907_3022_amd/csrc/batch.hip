@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ s
 {
     const int32_t lb = logical_block(1);
     const SysDev sd = sys[blk_sys[lb]];
-    const int32_t gw = blk_wave0[lb] + (int32_t)(threadIdx.x >> 6);
+    const int32_t gw = __builtin_amdgcn_readfirstlane(blk_wave0[lb] + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % sd.nstrips;
     const int32_t chunk = gw / sd.nstrips;
     if (chunk >= sd.nchunks) return;  // uniform per wavefront; the kernel has no barrier

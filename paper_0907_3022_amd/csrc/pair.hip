@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                                               double *partials)
 {
     __shared__ double red[2 * 4];
-    const int32_t gw = logical_block(op.xcd_remap) * 4 + (threadIdx.x >> 6);
+    const int32_t gw = __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % op.nstrips;
     const int32_t chunk = gw / op.nstrips;
     double nrm = 0.0, en = 0.0;

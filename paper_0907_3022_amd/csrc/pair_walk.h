@@ -38,13 +38,43 @@ __device__ __forceinline__ double2 csel(bool c, double2 a, double2 b)
     return make_double2(c ? a.x : b.x, c ? a.y : b.y);
 }
 
-__device__ __forceinline__ double2 shfl_up1(double2 v)
+// Whole-wavefront shifts by one lane through DPP (a register move, no LDS
+// round trip): from_left gives lane l the value of lane l-1 and lane 0 the
+// value `edge`; from_right gives lane l the value of lane l+1 and lane 63
+// `edge`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v, double edge)
 {
-    return make_double2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffff), (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ __forceinline__ double2 shfl_down1(double2 v)
+constexpr int kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+__device__ __forceinline__ double2 from_left(double2 v, double2 edge)
 {
-    return make_double2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+    return make_double2(dpp_shift<kWaveShr1>(v.x, edge.x), dpp_shift<kWaveShr1>(v.y, edge.y));
+}
+__device__ __forceinline__ double2 from_right(double2 v, double2 edge)
+{
+    return make_double2(dpp_shift<kWaveShl1>(v.x, edge.x), dpp_shift<kWaveShl1>(v.y, edge.y));
+}
+// the same shifts where the edge lane's result is not used (it reads 0)
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift0(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double2 from_left0(double2 v)
+{
+    return make_double2(dpp_shift0<kWaveShr1>(v.x), dpp_shift0<kWaveShr1>(v.y));
+}
+__device__ __forceinline__ double2 from_right0(double2 v)
+{
+    return make_double2(dpp_shift0<kWaveShl1>(v.x), dpp_shift0<kWaveShl1>(v.y));
 }
 
 // Operands of one row loaded one iteration ahead: v_k of the row below,
@@ -94,6 +124,7 @@ __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32
     const bool ext_lane = (lane == 0 || lane == 63) && xe >= 0 && xe < L;
     auto ok_ext = [&](int32_t r) -> bool { return ext_lane && r >= 0 && r < W; };
     auto ld_ext = [&](int32_t r) -> double2 { return ldg(vk, ok_ext(r) ? (int64_t)r * L + xe : 0); };
+    auto st = [&](double2 *v, int32_t r, double2 val) { stg(v, (int64_t)r * L + x, val); };
     // operands of row r (v_k row r+1, v_{k-1}, on-site and outside value of
     // row r, acc of row r-1) are loaded one iteration ahead; v_{k-1}, the
     // on-site term and acc are only used where they are in range
@@ -123,11 +154,8 @@ __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32
         const double2 ext = csel(ok_ext(r), cur.ext, zero);
         const double e_0 = cur.e;
         const bool rowok = r >= 0 && r < W;
-        const int64_t ir = (int64_t)r * L + x;
         // ---- first order at row r: v_{k+1} = 2 H~ v_k - v_{k-1} ----
-        double2 left = shfl_up1(a_0), right = shfl_down1(a_0);
-        left = csel(lane == 0, ext, left);
-        right = csel(lane == 63, ext, right);
+        const double2 left = from_left(a_0, ext), right = from_right(a_0, ext);
         const bool even_r = ((x + r) & 1) == 0;
         double2 s;
         if (EDGE == CHEBTD_ZIGZAG)
@@ -138,12 +166,12 @@ __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32
         const double2 h = make_double2(fma(d0, a_0.x, op.off2 * s.x), fma(d0, a_0.y, op.off2 * s.y));
         double2 b_0 = HEAD ? cscale(0.5, h) : csub(h, cur.km1);
         b_0 = csel(colok && rowok, b_0, zero);
-        if (own && r >= ys && r < ye) stg(out1, ir, b_0);
+        if (own && r >= ys && r < ye) st(out1, r, b_0);
         // ---- second order at row q = r-1: v_{k+2} = 2 H~ v_{k+1} - v_k ----
         if (r - 1 >= ys) {
             const int32_t q = r - 1;
-            const int64_t iq = (int64_t)q * L + x;
-            const double2 l2 = shfl_up1(b_m1), r2 = shfl_down1(b_m1);
+            // lanes 0 and 63 get no second order: their edge value is unused
+            const double2 l2 = from_left0(b_m1), r2 = from_right0(b_m1);
             const bool even_q = ((x + q) & 1) == 0;
             double2 s2;
             if (EDGE == CHEBTD_ZIGZAG)
@@ -153,19 +181,19 @@ __device__ __forceinline__ void pair_walk(const OpPair &op, int32_t strip, int32
             const double d1 = op.s2 * (e_m1 + op.dshift);
             const double2 h2 = make_double2(fma(d1, b_m1.x, op.off2 * s2.x), fma(d1, b_m1.y, op.off2 * s2.y));
             const double2 c = csub(h2, a_m1);
-            if (own) stg(out2, iq, c);
+            if (own) st(out2, q, c);
             if (ACC && own) {
                 double2 a;
                 if (HEAD) {
                     a = cfma(g0, a_m1, zero);
-                    if (ckpt) stg(ckpt, iq, a_m1);
+                    if (ckpt) st(ckpt, q, a_m1);
                     nrm += a_m1.x * a_m1.x + a_m1.y * a_m1.y;
                     en += a_m1.x * b_m1.x + a_m1.y * b_m1.y;
                 } else {
                     a = cur.acc;  // acc of row q, loaded with the previous row
                 }
                 a = cfma(g1, b_m1, a);
-                stg(acc, iq, cfma(g2, c, a));
+                st(acc, q, cfma(g2, c, a));
             }
         }
         a_m1 = a_0;
