@@ -107,6 +107,40 @@ __device__ __forceinline__ int32_t logical_block(int32_t remap)
     return xcd * per + (xcd < rem ? xcd : rem) + slot;
 }
 
+// The per-step norm and energy from the step head's block partials, summed
+// in a fixed order by one 256-thread block (the same bits whichever kernel
+// runs it): norm_out/energy_out[counter[0]] and counter[0]++, or dst2[0..1].
+struct NeFinal {
+    const double *partials;
+    int nparts;
+    double a, b;
+    double *norm_out, *energy_out;
+    int64_t *counter;
+};
+
+__device__ __forceinline__ void finalize_ne_block(const NeFinal &f, double *dst2, double *red)
+{
+    double s0 = 0.0, s1 = 0.0;
+    for (int p = threadIdx.x; p < f.nparts; p += blockDim.x) {
+        s0 += f.partials[2 * p];
+        s1 += f.partials[2 * p + 1];
+    }
+    block_sum2(s0, s1, red);
+    if (threadIdx.x == 0) {
+        const double energy = f.a * s1 + f.b * s0;
+        if (f.counter) {
+            const int64_t st = f.counter[0];
+            if (f.norm_out) f.norm_out[st] = s0;
+            if (f.energy_out) f.energy_out[st] = energy;
+            f.counter[0] = st + 1;
+        }
+        if (dst2) {
+            dst2[0] = s0;
+            dst2[1] = energy;
+        }
+    }
+}
+
 template <int EDGE>
 struct HoneyRow {
     __device__ static __forceinline__ int64_t row_xy(const OpHoney &op, int32_t &x, int32_t &y)

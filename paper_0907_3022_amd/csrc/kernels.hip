@@ -170,25 +170,8 @@ __global__ __launch_bounds__(256) void k_finalize_ne(const double *__restrict__ 
                                                      double *dst2)
 {
     __shared__ double red[2 * 4];
-    double s0 = 0.0, s1 = 0.0;
-    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
-        s0 += partials[2 * p];
-        s1 += partials[2 * p + 1];
-    }
-    block_sum2(s0, s1, red);
-    if (threadIdx.x == 0) {
-        const double energy = a * s1 + b * s0;
-        if (counter) {
-            const int64_t s = counter[0];
-            if (norm_out) norm_out[s] = s0;
-            if (energy_out) energy_out[s] = energy;
-            counter[0] = s + 1;
-        }
-        if (dst2) {
-            dst2[0] = s0;
-            dst2[1] = energy;
-        }
-    }
+    NeFinal f{partials, nparts, a, b, norm_out, energy_out, counter};
+    finalize_ne_block(f, dst2, red);
 }
 
 __global__ void k_reset_counter(int64_t *counter) { counter[0] = 0; }

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 
+#include "device_ops.h"
 #include "internal.h"
 
 namespace chebtd {
@@ -29,8 +30,10 @@ int pair_rows_for_width(int64_t W);
 bool pair_supported(const Ctx &c);
 // head: v1 = H~ vk, v2 = 2 H~ v1 - vk, acc = g0 vk + g1 v1 + g2 v2 (+ partials, ckpt)
 // else: v_{k+1} = 2 H~ vk - vkm1, v_{k+2} = 2 H~ v_{k+1} - vk, acc += g1 v_{k+1} + g2 v_{k+2}
+// fin (non-head passes, may be null): block 0 also finishes the step's norm
+// and energy from the head's partials
 hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1, const double2 *vk,
                        double2 *out1, double2 *out2, double2 *acc, double2 g0, double2 g1, double2 g2,
-                       double2 *ckpt, double *partials);
+                       double2 *ckpt, double *partials, const NeFinal *fin = nullptr);
 
 }  // namespace chebtd

@@ -23,9 +23,10 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
                                               const double2 *__restrict__ vk, double2 *__restrict__ out1,
                                               double2 *__restrict__ out2, double2 *__restrict__ acc,
                                               double2 g0, double2 g1, double2 g2, double2 *__restrict__ ckpt,
-                                              double *partials)
+                                              double *partials, NeFinal fin)
 {
     __shared__ double red[2 * 4];
+    if (!HEAD && fin.partials && blockIdx.x == 0) finalize_ne_block(fin, nullptr, red);
     const int32_t gw = __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % op.nstrips;
     const int32_t chunk = gw / op.nstrips;
@@ -80,8 +81,10 @@ bool pair_supported(const Ctx &c)
 
 hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1, const double2 *vk,
                        double2 *out1, double2 *out2, double2 *acc, double2 g0, double2 g1, double2 g2,
-                       double2 *ckpt, double *partials)
+                       double2 *ckpt, double *partials, const NeFinal *fin_in)
 {
+    NeFinal fin{};
+    if (fin_in && !head) fin = *fin_in;
     const OpPair op = make_pair_op(c, rows);
     const int64_t nb = pair_grid_blocks(c, rows);
     if (nb <= 0 || nb > INT32_MAX) return hipErrorInvalidValue;
@@ -90,17 +93,17 @@ hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const d
     if (head) {
         if (zig)
             hipLaunchKernelGGL((k_pair<CHEBTD_ZIGZAG, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, g0,
-                               g1, g2, ckpt, partials);
+                               g1, g2, ckpt, partials, fin);
         else
             hipLaunchKernelGGL((k_pair<CHEBTD_ARMCHAIR, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
-                               g0, g1, g2, ckpt, partials);
+                               g0, g1, g2, ckpt, partials, fin);
     } else {
         if (zig)
             hipLaunchKernelGGL((k_pair<CHEBTD_ZIGZAG, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
-                               g0, g1, g2, ckpt, partials);
+                               g0, g1, g2, ckpt, partials, fin);
         else
             hipLaunchKernelGGL((k_pair<CHEBTD_ARMCHAIR, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
-                               g0, g1, g2, ckpt, partials);
+                               g0, g1, g2, ckpt, partials, fin);
     }
     return hipGetLastError();
 }

@@ -45,16 +45,20 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
     hipError_t e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, A, C, nxt, weight(c, 0), weight(c, 1),
                                weight(c, 2), ckpt, partials);
     if (e != hipSuccess) return e;
-    if (norm_out || energy_out) {
-        e = launch_finalize_ne(s, partials, (int)pair_grid_blocks(*c, c->pair_rows), c->a, c->b, norm_out,
-                               energy_out, static_cast<int64_t *>(c->counter.p), nullptr);
+    // the step's norm and energy: finished by block 0 of the next pass when
+    // there is one (no extra launch), else by their own kernel
+    const NeFinal fin{partials, (int)pair_grid_blocks(*c, c->pair_rows), c->a, c->b, norm_out, energy_out,
+                      static_cast<int64_t *>(c->counter.p)};
+    const bool want_ne = norm_out || energy_out;
+    if (want_ne && c->M < 4) {
+        e = launch_finalize_ne(s, partials, fin.nparts, c->a, c->b, norm_out, energy_out, fin.counter, nullptr);
         if (e != hipSuccess) return e;
     }
     double2 *X = A, *Y = C, *F1 = D, *F2 = cur;  // (v_{k-1}, v_k) and the free pair
     int k = 2;
     for (; k + 2 <= c->M; k += 2) {
         e = launch_pair(*c, s, c->pair_rows, false, X, Y, F1, F2, nxt, make_double2(0.0, 0.0), weight(c, k + 1),
-                        weight(c, k + 2), nullptr, nullptr);
+                        weight(c, k + 2), nullptr, nullptr, (want_ne && k == 2) ? &fin : nullptr);
         if (e != hipSuccess) return e;
         double2 *t1 = X, *t2 = Y;
         X = F1;
