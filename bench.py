@@ -47,7 +47,7 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_ops.h", "pair.hip"):
+    for f in ("kernels.hip", "device_ops.h", "pair.hip", "pair_walk.h", "pair.h"):
         with open(os.path.join(ROOT, "paper_0907_3022_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
