@@ -465,110 +465,6 @@ __global__ void k_holstein_obs_final(const double *partials, int nparts, int L, 
 }
 
 // ---------------------------------------------------------------------------
-// One-workgroup persistent kernel for short chains (n <= 1024 R): the whole
-// K-step run stays in registers.  Thread t owns rows [t R, t R + R); the
-// neighbour rows of its block come from lanes t-1 and t+1 (cross-lane
-// shuffles) and, at wavefront edges, from LDS slots written once per order.
-// One barrier per recursion order; the LDS slots alternate between two
-// banks so that a slot is never rewritten before every wavefront read it.
-// ---------------------------------------------------------------------------
-template <int R>
-__global__ __launch_bounds__(1024) void k_chain_small(OpChain op, const double2 *psi_in,
-                                                      double2 *psi_out,
-                                                      const double2 *__restrict__ gamma, int M,
-                                                      int64_t K, double a, double b,
-                                                      double *norm_out, double *energy_out,
-                                                      double2 *ckpt)
-{
-    __shared__ double2 edge_lo[2][16];  // first row of each wavefront
-    __shared__ double2 edge_hi[2][16];  // last row of each wavefront
-    __shared__ double red[2 * 16];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    const int64_t row0 = (int64_t)tid * R;
-
-    double d[R];
-    double2 cur[R], prev[R], acc[R];
-    bool ok[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t i = row0 + r;
-        ok[r] = i < op.n;
-        d[r] = ok[r] ? op.s2 * (op.V[i] + op.dsh) : 0.0;
-        cur[r] = ok[r] ? psi_in[i] : make_double2(0.0, 0.0);
-    }
-    int bank = 0;
-
-    // (2 H~ x) for this thread's rows, x given in registers
-    auto apply2 = [&](const double2 (&x)[R], double2 (&y)[R]) {
-        // neighbours across lanes
-        double2 left, right;
-        left.x = __shfl_up(x[R - 1].x, 1, 64);
-        left.y = __shfl_up(x[R - 1].y, 1, 64);
-        right.x = __shfl_down(x[0].x, 1, 64);
-        right.y = __shfl_down(x[0].y, 1, 64);
-        if (lane == 0) edge_lo[bank][wave] = x[0];
-        if (lane == 63) edge_hi[bank][wave] = x[R - 1];
-        __syncthreads();
-        if (lane == 0) left = wave > 0 ? edge_hi[bank][wave - 1] : make_double2(0.0, 0.0);
-        if (lane == 63) right = wave + 1 < nwave ? edge_lo[bank][wave + 1] : make_double2(0.0, 0.0);
-        bank ^= 1;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double2 l = r == 0 ? left : x[r - 1];
-            const double2 rr = r == R - 1 ? right : x[r + 1];
-            const double sx = l.x + rr.x, sy = l.y + rr.y;
-            y[r] = ok[r] ? make_double2(fma(d[r], x[r].x, op.off2 * sx), fma(d[r], x[r].y, op.off2 * sy))
-                         : make_double2(0.0, 0.0);
-        }
-    };
-
-    for (int64_t s = 0; s < K; ++s) {
-        // step head
-        double2 h[R];
-        apply2(cur, h);
-        double nrm = 0.0, e = 0.0;
-        const double2 g0 = gamma[0];
-        const double2 g1 = M >= 1 ? gamma[1] : make_double2(0.0, 0.0);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            h[r] = cscale(0.5, h[r]);
-            if (ckpt && ok[r]) ckpt[(size_t)s * op.n + row0 + r] = cur[r];
-            nrm += cur[r].x * cur[r].x + cur[r].y * cur[r].y;
-            e += cur[r].x * h[r].x + cur[r].y * h[r].y;
-            double2 z = make_double2(0.0, 0.0);
-            z = cfma(g0, cur[r], z);
-            acc[r] = cfma(g1, h[r], z);
-            prev[r] = cur[r];
-            cur[r] = h[r];
-        }
-        block_sum2(nrm, e, red);
-        if (tid == 0) {
-            if (norm_out) norm_out[s] = nrm;
-            if (energy_out) energy_out[s] = a * e + b * nrm;
-        }
-        // hot loop
-        for (int k = 1; k <= M - 1; ++k) {
-            const double2 g = gamma[k + 1];
-            double2 y[R];
-            apply2(cur, y);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double2 nv = csub(y[r], prev[r]);
-                acc[r] = cfma(g, nv, acc[r]);
-                prev[r] = cur[r];
-                cur[r] = ok[r] ? nv : make_double2(0.0, 0.0);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) cur[r] = acc[r];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (ok[r]) psi_out[row0 + r] = cur[r];
-}
-
-// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 int64_t grid_blocks(const Ctx &c)
@@ -741,27 +637,6 @@ hipError_t launch_holstein_obs(hipStream_t s, const double2 *psi, const uint8_t 
                        partials);
     hipLaunchKernelGGL(k_holstein_obs_final, dim3((3 * L + 63) / 64), dim3(64), 0, s, partials, nb, L,
                        n_out, nph_out, chi_out);
-    return hipGetLastError();
-}
-
-bool chain_small_fits(int64_t n) { return n >= 1 && n <= 4096; }
-
-hipError_t launch_chain_small(const Ctx &c, hipStream_t s, double2 *psi, double2 *out,
-                              const double2 *gamma_dev, int64_t K, double *norm_out,
-                              double *energy_out, double2 *ckpt)
-{
-    const OpChain op = make_chain(c);
-    if (c.n <= 1024)
-        hipLaunchKernelGGL(k_chain_small<1>, dim3(1), dim3(1024), 0, s, op, psi, out, gamma_dev, c.M,
-                           K, c.a, c.b, norm_out, energy_out, ckpt);
-    else if (c.n <= 2048)
-        hipLaunchKernelGGL(k_chain_small<2>, dim3(1), dim3(1024), 0, s, op, psi, out, gamma_dev, c.M,
-                           K, c.a, c.b, norm_out, energy_out, ckpt);
-    else if (c.n <= 4096)
-        hipLaunchKernelGGL(k_chain_small<4>, dim3(1), dim3(1024), 0, s, op, psi, out, gamma_dev, c.M,
-                           K, c.a, c.b, norm_out, energy_out, ckpt);
-    else
-        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
