@@ -269,9 +269,12 @@ def bench_polaron_paper(torch, P):
     ctx.holstein(L, p["nph"], p["t"], p["w0"], g, Delta, False)
     build_s = time.perf_counter() - t0
     n = ctx.n
+    nconf = n // L
     psi = torch.zeros(n, dtype=torch.complex128, device="cuda")
-    # bare electron packet with the phonon vacuum (configuration rank 0)
-    psi[:L] = torch.from_numpy(W.holstein_packet(L, 1, p["packet_site"], p["width"], p["k"])[:L]).cuda()
+    # bare electron packet with the phonon vacuum (configuration rank 0 of
+    # every site's block of states, index site * nconf)
+    packet = W.holstein_packet(L, 1, p["packet_site"], p["width"], p["k"])
+    psi[::nconf] = torch.from_numpy(packet).cuda()
     lo, hi = ctx.gershgorin()
     ctx.set_bounds(lo, hi)
     M = ctx.plan(p["dt"])

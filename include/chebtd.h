@@ -122,7 +122,10 @@ int chebtd_h_csr(chebtd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr_
  *       - sum_i g_i w0 (b_i^+ + b_i) n_i + w0 sum_i b_i^+ b_i.
  * Basis: phonon configurations ordered by total phonon number, then
  * lexicographically ascending in (n_1..n_L) (n_1 most significant); state
- * index = rank * L + electron site.  g_host, Delta_host: float64[L] host
+ * index = electron site * nconf + rank, nconf = C(L+nph, nph), so that the
+ * configurations of one site are contiguous (the electron hops and phonon
+ * partners of neighbouring states then lie close together in memory).
+ * g_host, Delta_host: float64[L] host
  * arrays (copied).  The operator is applied matrix-free (the memory-saving
  * scheme of Sect. 3.3): the context builds on the host, and owns on the
  * device, per-state tables of the raised and lowered phonon configuration

@@ -335,7 +335,8 @@ int orc_build_honeycomb(int64_t W, int64_t L, int edge, double t, const double *
 /* phonon Fock states with total phonon number <= nph (the truncation of     */
 /* Sect. 3.3).  Phonon configurations are ordered by total phonon number,    */
 /* then lexicographically ascending in (n_1, ..., n_L) with n_1 most         */
-/* significant.  State index = rank(phonon config) * L + electron site.      */
+/* significant.  State index = electron site * nconf + rank(phonon config):  */
+/* the configurations of one electron site are contiguous.                  */
 /* The oracle enumerates the configurations explicitly and looks them up by  */
 /* binary search over an encoded key.                                        */
 /* ------------------------------------------------------------------------ */
@@ -462,31 +463,32 @@ int orc_build_holstein(int L, int nph, double t, double w0, const double *g,
     if (basis_build(&B, L, nph)) return -1;
     triplist l = {0};
     uint8_t *nb = (uint8_t *)malloc((size_t)L);
-    for (int64_t r = 0; r < B.count; ++r) {
+    const int64_t C = B.count;  /* state (i, r) sits at i * C + r */
+    for (int64_t r = 0; r < C; ++r) {
         const uint8_t *n = B.occ + r * L;
         int T = 0;
         for (int j = 0; j < L; ++j) T += n[j];
         for (int i = 0; i < L; ++i) {
-            int64_t row = r * L + i;
+            int64_t row = (int64_t)i * C + r;
             tl_push(&l, row, row, Delta[i] + w0 * T, 0.0);
             /* electron transfer to the neighbouring sites */
             int left = i - 1, right = i + 1;
             if (periodic) { left = (i - 1 + L) % L; right = (i + 1) % L; }
-            if (left >= 0) tl_push(&l, row, r * L + left, -t, 0.0);
-            if (right < L) tl_push(&l, row, r * L + right, -t, 0.0);
+            if (left >= 0) tl_push(&l, row, (int64_t)left * C + r, -t, 0.0);
+            if (right < L) tl_push(&l, row, (int64_t)right * C + r, -t, 0.0);
             /* column n + e_i: <n| b_i |n + e_i> = sqrt(n_i + 1) */
             if (T < nph) {
                 memcpy(nb, n, (size_t)L); nb[i]++;
                 int64_t rp = basis_lookup(&B, nb);
                 double amp = -g[i] * w0 * sqrt((double)n[i] + 1.0);
-                tl_push(&l, row, rp * L + i, amp, 0.0);
+                tl_push(&l, row, (int64_t)i * C + rp, amp, 0.0);
             }
             /* column n - e_i: <n| b_i^+ |n - e_i> = sqrt(n_i) */
             if (n[i] > 0) {
                 memcpy(nb, n, (size_t)L); nb[i]--;
                 int64_t rm = basis_lookup(&B, nb);
                 double amp = -g[i] * w0 * sqrt((double)n[i]);
-                tl_push(&l, row, rm * L + i, amp, 0.0);
+                tl_push(&l, row, (int64_t)i * C + rm, amp, 0.0);
             }
         }
     }
@@ -749,30 +751,31 @@ int orc_holstein_obs(int L, int nph, const double *psi_ri, double *n_i,
     const cplx *psi = (const cplx *)psi_ri;
     uint8_t *nb = (uint8_t *)malloc((size_t)L);
     for (int i = 0; i < L; ++i) { n_i[i] = 0.0; nph_i[i] = 0.0; chi_i[i] = 0.0; }
-    for (int64_t r = 0; r < B.count; ++r) {
+    const int64_t C = B.count;  /* state (i, r) sits at i * C + r */
+    for (int64_t r = 0; r < C; ++r) {
         const uint8_t *n = B.occ + r * L;
         int T = 0;
         for (int j = 0; j < L; ++j) T += n[j];
         double w = 0.0; /* total weight of this phonon configuration */
         for (int i = 0; i < L; ++i) {
-            cplx p = psi[r * L + i];
+            cplx p = psi[(int64_t)i * C + r];
             double pp = creal(conj(p) * p);
             n_i[i] += pp;
             w += pp;
         }
         for (int j = 0; j < L; ++j) nph_i[j] += n[j] * w;
         for (int i = 0; i < L; ++i) {
-            cplx p = psi[r * L + i];
-            cplx bp = 0.0; /* ((b_i + b_i^+) psi)(r, i) */
+            cplx p = psi[(int64_t)i * C + r];
+            cplx bp = 0.0; /* ((b_i + b_i^+) psi)(i, r) */
             if (T < nph) {
                 memcpy(nb, n, (size_t)L); nb[i]++;
                 int64_t rp = basis_lookup(&B, nb);
-                bp += sqrt((double)n[i] + 1.0) * psi[rp * L + i];
+                bp += sqrt((double)n[i] + 1.0) * psi[(int64_t)i * C + rp];
             }
             if (n[i] > 0) {
                 memcpy(nb, n, (size_t)L); nb[i]--;
                 int64_t rm = basis_lookup(&B, nb);
-                bp += sqrt((double)n[i]) * psi[rm * L + i];
+                bp += sqrt((double)n[i]) * psi[(int64_t)i * C + rm];
             }
             chi_i[i] += creal(conj(p) * bp);
         }

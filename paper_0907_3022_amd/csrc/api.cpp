@@ -286,7 +286,11 @@ int chebtd_holstein_occupations(int L, int nph, int64_t *count_out, uint8_t *occ
     std::string err;
     int rc = holstein_tables(L, nph, 0, h, err);
     if (rc) return fail(nullptr, rc, err);
-    std::memcpy(occ, h.occ.data(), h.occ.size());
+    // the per-state table is site-major (occ of state site*nconf + r); the
+    // export is configuration-major, occ[r*L + j]
+    const int64_t C = h.nconf;
+    for (int64_t r = 0; r < C; ++r)
+        for (int j = 0; j < L; ++j) occ[r * L + j] = h.occ[(size_t)j * (size_t)C + (size_t)r];
     return CHEBTD_OK;
 }
 

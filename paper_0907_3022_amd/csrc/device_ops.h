@@ -207,39 +207,56 @@ struct HolRow {
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         return i < op.n ? i : -1;
     }
+    // state i = site * nconf + r, for i = blockIdx.x * blockDim.x + threadIdx.x:
+    // one division per wavefront (the block's first state), then a step or
+    // two for threads past a site boundary (n < 2^31: 32-bit arithmetic)
+    __device__ static __forceinline__ void split(const OpHol &op, int64_t i, uint32_t &site, uint32_t &r)
+    {
+        const uint32_t b0 = (uint32_t)(blockIdx.x * blockDim.x);
+        uint32_t s = __builtin_amdgcn_readfirstlane(b0 / op.nconf);
+        uint32_t rr = (uint32_t)i - s * op.nconf;
+        while (rr >= op.nconf) {
+            rr -= op.nconf;
+            ++s;
+        }
+        site = s;
+        r = rr;
+    }
     __device__ static __forceinline__ double2 apply2(const OpHol &op, int64_t i, const double2 *v, double2 vi)
     {
-        // n < 2^31, so 32-bit division suffices
-        const uint32_t ui = (uint32_t)i, L = (uint32_t)op.L;
-        const uint32_t r = ui / L, site = ui - r * L;
+        uint32_t site, r;
+        split(op, i, site, r);
+        const uint32_t L = (uint32_t)op.L, C = op.nconf;
         const double diag = op.Delta[site] + op.w0 * (double)op.tot[r];
-        // electron hops to the neighbouring sites
+        // electron hops to the neighbouring sites: same configuration, the
+        // neighbouring site's block of states
         double hx = 0.0, hy = 0.0;
         const bool has_l = op.periodic || site > 0, has_r = op.periodic || site + 1 < L;
         const uint32_t sl = site == 0 ? L - 1 : site - 1, sr = site + 1 == L ? 0 : site + 1;
-        const uint32_t base = r * L;
         if (has_l) {
-            const double2 u = v[base + sl];
+            const double2 u = v[sl * C + r];
             hx += u.x;
             hy += u.y;
         }
         if (has_r) {
-            const double2 u = v[base + sr];
+            const double2 u = v[sr * C + r];
             hx += u.x;
             hy += u.y;
         }
-        // phonon creation/annihilation at the electron's site
+        // phonon creation/annihilation at the electron's site: the partner
+        // configurations in the same site's block
         const int32_t ru = op.up[i], rd = op.dn[i];
         const uint32_t ni = op.occ[i];
+        const uint32_t base = site * C;
         double px = 0.0, py = 0.0;
         if (ru >= 0) {
-            const double2 u = v[(uint32_t)ru * L + site];
+            const double2 u = v[base + (uint32_t)ru];
             const double w = op.sq[ni + 1];
             px = fma(w, u.x, px);
             py = fma(w, u.y, py);
         }
         if (rd >= 0) {
-            const double2 u = v[(uint32_t)rd * L + site];
+            const double2 u = v[base + (uint32_t)rd];
             const double w = op.sq[ni];
             px = fma(w, u.x, px);
             py = fma(w, u.y, py);
@@ -299,6 +316,7 @@ inline OpHol make_hol(const Ctx &c)
     op.L = c.hol_L;
     op.periodic = c.hol_periodic;
     op.n = c.n;
+    op.nconf = (uint32_t)c.hol_nconf;
     return op;
 }
 

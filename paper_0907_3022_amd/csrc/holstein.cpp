@@ -150,7 +150,7 @@ int holstein_tables(int L, int nph, int periodic, HolsteinTables &out, std::stri
                 for (int j = 0; j < L; ++j) T += cfg[(size_t)j];
                 out.tot[(size_t)r] = (uint8_t)T;
                 for (int i = 0; i < L; ++i) {
-                    const size_t row = (size_t)(r * L + i);
+                    const size_t row = (size_t)i * (size_t)nconf + (size_t)r;
                     out.occ[row] = cfg[(size_t)i];
                     if (T < nph) {
                         tmp = cfg;
@@ -183,82 +183,53 @@ int holstein_count(int L, int nph, int64_t *count)
 int holstein_build(int L, int nph, double t, double w0, const double *g, const double *Delta,
                    int periodic, HolsteinCsr &out, std::string &err)
 {
-    if (L < 1 || L > 64 || nph < 0 || nph > 255) {
-        err = "holstein: need 1 <= L <= 64 and 0 <= nph <= 255";
-        return CHEBTD_E_ARG;
-    }
-    if (periodic && L < 3) {
-        err = "holstein: a ring needs L >= 3";
-        return CHEBTD_E_ARG;
-    }
     if (!g || !Delta) {
         err = "holstein: g and Delta must be non-null";
         return CHEBTD_E_ARG;
     }
-    Binom C(L + nph + 1, L);
-    if (!C.ok) {
-        err = "holstein: basis too large";
-        return CHEBTD_E_ARG;
-    }
-    const int64_t nconf = C(L + nph, L);
-    const int64_t n = nconf * (int64_t)L;
-    if (n >= (int64_t)INT32_MAX) {
-        err = "holstein: dimension exceeds int32 column indices";
-        return CHEBTD_E_ARG;
-    }
+    HolsteinTables tb;
+    const int rc = holstein_tables(L, nph, periodic, tb, err);
+    if (rc) return rc;
+    const int64_t C = tb.nconf, n = tb.n;
     out.n = n;
-    out.nconf = nconf;
+    out.nconf = C;
     out.rowptr.assign((size_t)n + 1, 0);
     out.col.clear();
     out.val.clear();
     out.col.reserve((size_t)n * 5);
     out.val.reserve((size_t)n * 10);
-    std::vector<uint8_t> cfg((size_t)L, 0), tmp((size_t)L);
     struct Entry {
         int64_t c;
         double v;
     };
-    Entry row[6];
-    int64_t r = 0;
-    do {
-        int T = 0;
-        for (int j = 0; j < L; ++j) T += cfg[(size_t)j];
-        for (int i = 0; i < L; ++i) {
-            const int64_t rowi = r * L + i;
+    Entry row[5];
+    // rows in state order: site-major, configurations by rank within a site
+    for (int i = 0; i < L; ++i) {
+        int lft = i - 1, rgt = i + 1;
+        if (periodic) {
+            lft = (i + L - 1) % L;
+            rgt = (i + 1) % L;
+        }
+        for (int64_t r = 0; r < C; ++r) {
+            const int64_t s = (int64_t)i * C + r;
+            const int T = tb.tot[(size_t)r];
+            const int ni = tb.occ[(size_t)s];
             int cnt = 0;
-            row[cnt++] = {rowi, Delta[i] + w0 * T};
-            int lft = i - 1, rgt = i + 1;
-            if (periodic) {
-                lft = (i + L - 1) % L;
-                rgt = (i + 1) % L;
-            }
-            if (lft >= 0) row[cnt++] = {r * L + lft, -t};
-            if (rgt < L) row[cnt++] = {r * L + rgt, -t};
-            if (T < nph) {
-                tmp = cfg;
-                tmp[(size_t)i]++;
-                const int64_t ru = rank_of(C, tmp.data(), L);
-                row[cnt++] = {ru * L + i, -g[i] * w0 * std::sqrt((double)cfg[(size_t)i] + 1.0)};
-            }
-            if (cfg[(size_t)i] > 0) {
-                tmp = cfg;
-                tmp[(size_t)i]--;
-                const int64_t rd = rank_of(C, tmp.data(), L);
-                row[cnt++] = {rd * L + i, -g[i] * w0 * std::sqrt((double)cfg[(size_t)i])};
-            }
+            row[cnt++] = {s, Delta[i] + w0 * T};
+            if (lft >= 0) row[cnt++] = {(int64_t)lft * C + r, -t};
+            if (rgt < L) row[cnt++] = {(int64_t)rgt * C + r, -t};
+            if (tb.up[(size_t)s] >= 0)
+                row[cnt++] = {(int64_t)i * C + tb.up[(size_t)s], -g[i] * w0 * std::sqrt((double)ni + 1.0)};
+            if (tb.dn[(size_t)s] >= 0)
+                row[cnt++] = {(int64_t)i * C + tb.dn[(size_t)s], -g[i] * w0 * std::sqrt((double)ni)};
             std::sort(row, row + cnt, [](const Entry &x, const Entry &y) { return x.c < y.c; });
             for (int q = 0; q < cnt; ++q) {
                 out.col.push_back((int32_t)row[q].c);
                 out.val.push_back(row[q].v);
                 out.val.push_back(0.0);
             }
-            out.rowptr[(size_t)rowi + 1] = (int64_t)out.col.size();
+            out.rowptr[(size_t)s + 1] = (int64_t)out.col.size();
         }
-        ++r;
-    } while (next_config(cfg.data(), L, nph));
-    if (r != nconf) {
-        err = "holstein: internal enumeration mismatch";
-        return CHEBTD_E_STATE;
     }
     out.nnz = (int64_t)out.col.size();
     return CHEBTD_OK;

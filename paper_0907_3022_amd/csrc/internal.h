@@ -38,6 +38,7 @@ struct OpHoney {
 // Matrix-free Holstein operator, eq. (ghm): per state (r, i) the raised and
 // lowered phonon configurations of site i and its occupation, per
 // configuration the total phonon number.
+// state index i = site * nconf + r (rank r of the phonon configuration)
 struct OpHol {
     const int32_t *up;     // rank of n + e_i, or -1     [state]
     const int32_t *dn;     // rank of n - e_i, or -1     [state]
@@ -49,6 +50,7 @@ struct OpHol {
     double w0, t, b, s2;
     int32_t L, periodic;
     int64_t n;
+    uint32_t nconf;
 };
 
 struct OpCsr {

@@ -11,6 +11,8 @@
 // floating-point atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 
 #include "internal.h"
@@ -139,14 +141,71 @@ __global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2
     iter_body(i, HoneyRow<EDGE>::apply2(op, i, x, y, vk, vi), vprev, acc, g);
 }
 
-__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, const double2 *__restrict__ vk,
-                                                     double2 *vprev, double2 *__restrict__ acc,
-                                                     double2 g)
+// Holstein recursion order, one thread per (group of electron sites,
+// phonon configuration r): the thread walks its sites keeping v_k of the
+// previous, current and next site in registers, so each v_k value is read
+// once (the electron hops need the neighbouring sites' blocks, which lie
+// nconf states apart).  Consecutive threads take consecutive r: every
+// load and store of a site is contiguous across the wavefront except the
+// phonon partners v(s, up_s(r)) and v(s, dn_s(r)).
+// Thread t = grp * nconf + r covers sites [grp*spt, min(grp*spt + spt, L)).
+__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, const double2 *__restrict__ vk,
+                                                     double2 *vprev, double2 *__restrict__ acc, double2 g)
 {
-    const int64_t i = HolRow::row(op);
-    if (i < 0) return;
-    const double2 vi = vk[i];
-    iter_body(i, HolRow::apply2(op, i, vk, vi), vprev, acc, g);
+    const uint32_t C = op.nconf, L = (uint32_t)op.L;
+    const uint32_t ngrp = (L + (uint32_t)spt - 1) / (uint32_t)spt;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (uint64_t)C * ngrp) return;
+    // (grp, r) from t: one division per wavefront, then at most a few steps
+    const uint32_t b0 = (uint32_t)(blockIdx.x * blockDim.x);
+    uint32_t grp = __builtin_amdgcn_readfirstlane(b0 / C);
+    uint32_t r = (uint32_t)t - grp * C;
+    while (r >= C) {
+        r -= C;
+        ++grp;
+    }
+    const uint32_t s0 = grp * (uint32_t)spt, s1 = min(s0 + (uint32_t)spt, L);
+    const double2 zero = make_double2(0.0, 0.0);
+    const double wt = op.w0 * (double)op.tot[r] - op.b;
+    // v_k at sites s-1, s, s+1 of configuration r
+    double2 left = zero;
+    if (s0 > 0)
+        left = vk[(size_t)(s0 - 1) * C + r];
+    else if (op.periodic)
+        left = vk[(size_t)(L - 1) * C + r];
+    double2 cur = vk[(size_t)s0 * C + r];
+    for (uint32_t s = s0; s < s1; ++s) {
+        const size_t i = (size_t)s * C + r;
+        double2 right = zero;
+        if (s + 1 < L)
+            right = vk[i + C];
+        else if (op.periodic)
+            right = vk[r];
+        const int32_t ru = op.up[i], rd = op.dn[i];
+        const uint32_t ni = op.occ[i];
+        const size_t base = (size_t)s * C;
+        double px = 0.0, py = 0.0;
+        if (ru >= 0) {
+            const double2 u = vk[base + (uint32_t)ru];
+            const double w = op.sq[ni + 1];
+            px = fma(w, u.x, px);
+            py = fma(w, u.y, py);
+        }
+        if (rd >= 0) {
+            const double2 u = vk[base + (uint32_t)rd];
+            const double w = op.sq[ni];
+            px = fma(w, u.x, px);
+            py = fma(w, u.y, py);
+        }
+        const double d = op.Delta[s] + wt, gw = op.gw0[s];
+        // hops: left and right are zero where an open chain ends
+        const double hx = left.x + right.x, hy = left.y + right.y;
+        const double hvx = fma(d, cur.x, fma(-op.t, hx, -gw * px));
+        const double hvy = fma(d, cur.y, fma(-op.t, hy, -gw * py));
+        iter_body((int64_t)i, make_double2(op.s2 * hvx, op.s2 * hvy), vprev, acc, g);
+        left = cur;
+        cur = right;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_iter_csr(OpCsr op, const double2 *__restrict__ vk,
@@ -356,7 +415,9 @@ __global__ __launch_bounds__(kBlock) void k_gersh(GershSrc g, double *partials)
             for (int q = 0; q < nb; ++q) r += fabs(g.t);
         } else if (g.kind == 4) {
             const OpHol &h = g.hol;
-            const uint32_t L = (uint32_t)h.L, cfg = (uint32_t)i / L, site = (uint32_t)i - cfg * L;
+            const uint32_t L = (uint32_t)h.L;
+            uint32_t site, cfg;
+            HolRow::split(h, i, site, cfg);
             d = h.Delta[site] + h.w0 * (double)h.tot[cfg];
             const int hops = h.periodic ? 2 : (site > 0) + (site + 1 < L);
             r = hops * fabs(h.t);
@@ -400,11 +461,12 @@ __global__ __launch_bounds__(256) void k_minmax_final(const double *partials, in
 }
 
 // ---------------------------------------------------------------------------
-// Holstein observables (Fig. 3): one thread per phonon configuration r with
-// its L electron sites contiguous in psi.  Per site s the block reduces
-//   <n_s>        += |psi(r,s)|^2
-//   <b_s^+ b_s>  += n_s(r) * sum_j |psi(r,j)|^2
-//   chi_ss       += 2 Re[conj(psi(r,s)) sqrt(n_s(r)+1) psi(up_s(r), s)]
+// Holstein observables (Fig. 3): one thread per phonon configuration r; the
+// L states (s, r) sit nconf apart, so a wavefront reads contiguous runs.
+// Per site s the block reduces
+//   <n_s>        += |psi(s,r)|^2
+//   <b_s^+ b_s>  += n_s(r) * sum_j |psi(j,r)|^2
+//   chi_ss       += 2 Re[conj(psi(s,r)) sqrt(n_s(r)+1) psi(s, up_s(r))]
 // into partials[block][3L].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_holstein_obs(const double2 *__restrict__ psi,
@@ -418,20 +480,21 @@ __global__ __launch_bounds__(kBlock) void k_holstein_obs(const double2 *__restri
     double w = 0.0;
     if (valid) {
         for (int j = 0; j < L; ++j) {
-            const double2 v = psi[r * L + j];
+            const double2 v = psi[(int64_t)j * nconf + r];
             w += v.x * v.x + v.y * v.y;
         }
     }
     for (int s = 0; s < L; ++s) {
         double dn = 0.0, dph = 0.0, dchi = 0.0;
         if (valid) {
-            const double2 v = psi[r * L + s];
-            const int ns = occ[r * L + s];
+            const int64_t i = (int64_t)s * nconf + r;
+            const double2 v = psi[i];
+            const int ns = occ[i];
             dn = v.x * v.x + v.y * v.y;
             dph = ns * w;
-            const int32_t ru = up[r * L + s];
+            const int32_t ru = up[i];
             if (ru >= 0) {
-                const double2 u = psi[(int64_t)ru * L + s];
+                const double2 u = psi[(int64_t)s * nconf + ru];
                 dchi = 2.0 * sqrt((double)ns + 1.0) * (v.x * u.x + v.y * u.y);
             }
         }
@@ -449,19 +512,23 @@ __global__ __launch_bounds__(kBlock) void k_holstein_obs(const double2 *__restri
     }
 }
 
-__global__ void k_holstein_obs_final(const double *partials, int nparts, int L, double *n_out,
-                                     double *nph_out, double *chi_out)
+// One block per output o of the 3L: fixed-order sum of partials[p][o].
+__global__ __launch_bounds__(256) void k_holstein_obs_final(const double *partials, int nparts, int L,
+                                                            double *n_out, double *nph_out, double *chi_out)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= 3 * L) return;
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += partials[(size_t)p * 3 * L + o];
-    if (o < L)
-        n_out[o] = s;
-    else if (o < 2 * L)
-        nph_out[o - L] = s;
-    else
-        chi_out[o - 2 * L] = s;
+    __shared__ double red[2 * 4];
+    const int o = blockIdx.x;
+    double s = 0.0, z = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += partials[(size_t)p * 3 * L + o];
+    block_sum2(s, z, red);
+    if (threadIdx.x == 0) {
+        if (o < L)
+            n_out[o] = s;
+        else if (o < 2 * L)
+            nph_out[o - L] = s;
+        else
+            chi_out[o - 2 * L] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -523,9 +590,20 @@ hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *
     case HKind::Csr:
         hipLaunchKernelGGL(k_iter_csr, grid, block, 0, s, make_csr(c), vk, vprev, acc, g);
         break;
-    case HKind::Holstein:
-        hipLaunchKernelGGL(k_iter_hol, grid, block, 0, s, make_hol(c), vk, vprev, acc, g);
+    case HKind::Holstein: {
+        // sites per thread (measured on MI355X): all of them up to ~1M
+        // configurations (L = 10 ring, 185k: 27.9 us against 31.6 us for two
+        // per thread); beyond, groups of at most 9 sites keep the wavefronts
+        // in flight on fewer site blocks at a time (L = 18 polaron, 34.6M
+        // configurations: 12.0 ms against 14.7 ms for all 18)
+        const int64_t C = c.hol_nconf, L = c.hol_L;
+        const int64_t groups = C <= ((int64_t)1 << 20) ? 1 : (L + 8) / 9;
+        const int spt = (int)((L + groups - 1) / groups);
+        const int64_t ngrp = (L + spt - 1) / spt;
+        const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), block, 0, s, make_hol(c), spt, vk, vprev, acc, g);
         break;
+    }
     default:
         return hipErrorInvalidValue;
     }
@@ -635,8 +713,8 @@ hipError_t launch_holstein_obs(hipStream_t s, const double2 *psi, const uint8_t 
     const int nb = holstein_obs_blocks(nconf);
     hipLaunchKernelGGL(k_holstein_obs, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, occ, up, nconf, L,
                        partials);
-    hipLaunchKernelGGL(k_holstein_obs_final, dim3((3 * L + 63) / 64), dim3(64), 0, s, partials, nb, L,
-                       n_out, nph_out, chi_out);
+    hipLaunchKernelGGL(k_holstein_obs_final, dim3(3 * L), dim3(256), 0, s, partials, nb, L, n_out, nph_out,
+                       chi_out);
     return hipGetLastError();
 }
 

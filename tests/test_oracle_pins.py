@@ -176,7 +176,8 @@ def test_armchair_ribbon_matches_paper_device_size(golden_dir):
 def _holstein_kron(L, nph, t, w0, g, Delta, periodic):
     """eq. (ghm) built as a tensor product (electron x per-site Fock spaces cut
     at nph), then restricted to total phonon number <= nph.  Basis order:
-    total phonon number, then lexicographic in (n_1..n_L), electron site fastest."""
+    electron site slowest, then total phonon number, then lexicographic in
+    (n_1..n_L)."""
     d = nph + 1
     b = np.diag(np.sqrt(np.arange(1, d)), 1)  # annihilation on one mode
     I = np.eye(d)
@@ -210,7 +211,7 @@ def _holstein_kron(L, nph, t, w0, g, Delta, periodic):
     configs = [c for c in itertools.product(range(d), repeat=L) if sum(c) <= nph]
     configs.sort(key=lambda c: (sum(c), c))
     flat = [np.ravel_multi_index(c, (d,) * L) for c in configs]
-    idx = np.array([r * L + i for r in flat for i in range(L)])
+    idx = np.array([r * L + i for i in range(L) for r in flat])
     return H[np.ix_(idx, idx)], configs
 
 
@@ -440,7 +441,7 @@ def test_holstein_observables_brute_force():
     d = nph + 1
     b = np.diag(np.sqrt(np.arange(1, d)), 1)
     flat = [np.ravel_multi_index(c, (d,) * L) for c in configs]
-    idx = np.array([r * L + i for r in flat for i in range(L)])
+    idx = np.array([r * L + i for i in range(L) for r in flat])
     for i in range(L):
         ni = np.zeros((L, L))
         ni[i, i] = 1.0

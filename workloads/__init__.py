@@ -112,8 +112,9 @@ def right_half_mask_ribbon(width: int, length: int) -> np.ndarray:
 # Holstein polaron (Sect. 3.3, eq. (ghm))
 # --------------------------------------------------------------------------
 def holstein_vacuum_site(L: int, site: int, nconf: int) -> np.ndarray:
-    """Bare electron at `site` with no phonons (index rank(vacuum)=0 times L + site)."""
-    return single_site(nconf * L, site)
+    """Bare electron at `site` with no phonons: state index site * nconf + rank,
+    and the phonon vacuum has rank 0."""
+    return single_site(nconf * L, site * nconf)
 
 
 def holstein_packet(L: int, nconf: int, centre: float, width: float, k: float) -> np.ndarray:
@@ -122,7 +123,7 @@ def holstein_packet(L: int, nconf: int, centre: float, width: float, k: float) -
     e = np.exp(-((i - centre) ** 2) / (4.0 * width * width) + 1j * k * i)
     e /= np.linalg.norm(e)
     psi = np.zeros(nconf * L, dtype=np.complex128)
-    psi[:L] = e
+    psi[::nconf] = e  # rank 0 (vacuum) of every site
     return psi
 
 
