@@ -481,14 +481,19 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
         struct Cand {
             int mode, tile, block, wg;
         };
+        // per-launch schedules first; the persistent ones last, dropped once
+        // one of them takes more than twice the best time so far
         std::vector<Cand> cands;
         for (int tile : {1024, 2048, 4096, 8192})
             for (int block : {256, 512}) {
                 if (tile % block) continue;
-                cands.push_back({CHEBTD_SCHED_LEVELS, tile, block, 1});
                 if (b->pairs_ok) cands.push_back({CHEBTD_SCHED_PAIRS, tile, block, 1});
-                for (int wg : {2, 4}) cands.push_back({CHEBTD_SCHED_PERSISTENT, tile, block, wg});
+                cands.push_back({CHEBTD_SCHED_LEVELS, tile, block, 1});
             }
+        for (int tile : {1024, 2048, 4096, 8192})
+            for (int block : {256, 512})
+                if (tile % block == 0)
+                    for (int wg : {2, 4}) cands.push_back({CHEBTD_SCHED_PERSISTENT, tile, block, wg});
         double best_ms = 1e300;
         for (const Cand &cd : cands) {
             rc = chebtd_batch_set_schedule(ctx, cd.mode, cd.tile, cd.block, cd.wg);
@@ -508,6 +513,7 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
             }
             if (!rc) rc = check_timeout(c, b);
             if (rc) break;
+            const bool slow_persistent = cd.mode == CHEBTD_SCHED_PERSISTENT && ms > 2.0 * best_ms;
             if (ms < best_ms) {
                 best_ms = ms;
                 best[0] = cd.mode;
@@ -520,6 +526,7 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
                 rc = hip_fail(c, e, "autotune restore");
                 break;
             }
+            if (slow_persistent) break;
         }
         if (!rc) {
             e = copy_all(false);
