@@ -5,14 +5,18 @@ The headline line times K time steps of the 128 x 8192 zigzag graphene
 ribbon (1,048,576 sites, Anderson disorder W = 0.5, dt = 1, Chebyshev order
 M = 20 from the 1e-15 Bessel cutoff).  One step is the whole hot path: the
 step head (v_1 = H~ psi, acc = gamma_0 psi + gamma_1 v_1, norm and energy
-reductions) and M - 1 fused recursion launches
-v_{k+1} = 2 H~ v_k - v_{k-1}, acc += gamma_{k+1} v_{k+1}.  The plan (bounds,
-Bessel weights) is computed once per dt, outside the timed region, as the
-method prescribes.
+reductions) and the recursion v_{k+1} = 2 H~ v_k - v_{k-1},
+acc += gamma_{k+1} v_{k+1} up to order M, several orders per pass over memory
+(the pass split the library plans: 5+5+5+5 at M = 20).  The plan (bounds,
+Bessel weights, passes) is computed once per dt, outside the timed region, as
+the method prescribes.
 
 value = Hamiltonian applications (H~ v products) per second.
-roofline: the recursion kernel's algorithmic bytes (88 B per site and order)
-over its mean launch time measured with HIP events on the library's stream.
+roofline: the dominant recursion kernel's algorithmic bytes (104 B per site
+and pass, whatever the orders per pass: v_{k-1}, v_k, on-site term and acc
+read, the last two vectors and acc written; 88 B per site for a
+single-order pass) over its mean launch time measured with HIP events on the
+library's stream.
 cpu_baseline: the serial CPU oracle on a few steps of the same workload.
 """
 from __future__ import annotations
@@ -34,7 +38,7 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 STENCIL_BYTES = 88       # per site and order: v_k, v_{k-1}, v_{k+1}, acc r/w, on-site term
-PAIR_BYTES = 104         # per site and two orders: v_{k-1}, v_k, on-site, acc r/w, v_{k+1}, v_{k+2}
+PAIR_BYTES = 104         # per site and multi-order pass: v_{k-1}, v_k, on-site, acc r/w, last two vectors
 CSR_VEC_BYTES = 80       # vector traffic per row and order for CSR
 CSR_NNZ_BYTES = 20       # complex128 value + int32 column
 CSR_ROW_BYTES = 8        # rowptr
@@ -47,7 +51,7 @@ def log(msg):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_ops.h", "pair.hip", "pair_walk.h", "pair.h"):
+    for f in ("kernels.hip", "device_ops.h", "pair.hip", "pair_walk.h", "deep_walk.h", "pair.h"):
         with open(os.path.join(ROOT, "paper_0907_3022_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -112,6 +116,7 @@ def bench_main(torch, P, steps, warmup, mode_flags):
     psi2 = psi.clone()
     t_single = timed(torch, lambda: ctx.propagate(psi2, steps, nrm, en, flags | P.SINGLE_ORDER))
     return dict(ctx=ctx, n=n, M=M, seconds=t, ms_iter=ms_iter, kernel=kname, orders=orders,
+                passes=ctx.plan_passes(),
                 ms_single=ms_single, kernel_single=kname_single, seconds_single=t_single,
                 norm_drift=drift, psi=psi, eps=eps_d)
 
@@ -311,8 +316,8 @@ def bench_sweep(torch, P, sizes):
         ms, kname, orders = ctx.time_recursion_kernel(50)
         ms1, kname1, _ = ctx.time_recursion_kernel(50, P.SINGLE_ORDER)
         n = width * length
-        per = PAIR_BYTES if orders == 2 else STENCIL_BYTES
-        res.append(dict(sites=n, shape=f"{width}x{length}", kernel=kname, kernel_ms=ms,
+        per = PAIR_BYTES if orders >= 2 else STENCIL_BYTES
+        res.append(dict(sites=n, shape=f"{width}x{length}", kernel=kname, kernel_ms=ms, passes=ctx.plan_passes(),
                         orders_per_launch=orders, GBs=per * n / (ms * 1e-3) / 1e9,
                         ns_per_site_order=ms * 1e6 / n / orders,
                         single_order_kernel_ms=ms1, single_order_GBs=STENCIL_BYTES * n / (ms1 * 1e-3) / 1e9))
@@ -495,7 +500,7 @@ def main():
     r = bench_main(torch, P, args.steps, args.warmup, mode_flags)
     hv = args.steps * r["M"]
     value = hv / r["seconds"] if r["seconds"] > 0 else 0.0
-    unit_bytes = PAIR_BYTES if r["orders"] == 2 else STENCIL_BYTES
+    unit_bytes = PAIR_BYTES if r["orders"] >= 2 else STENCIL_BYTES
     achieved = unit_bytes * r["n"] / (r["ms_iter"] * 1e-3) / 1e9
     traffic = traffic_record(r["kernel"])
     line = {
@@ -513,7 +518,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "zigzag_ribbon_128x8192", "sites": r["n"], "disorder_W": 0.5,
                    "dt": 1.0, "chebyshev_order": r["M"], "time_steps": args.steps,
-                   "launch_mode": mode_name, "complex128": True},
+                   "launch_mode": mode_name, "orders_per_pass": r["passes"], "complex128": True},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": r["kernel"], "kernel_ms_per_launch": r["ms_iter"],

@@ -180,6 +180,19 @@ int chebtd_plan_order(chebtd_ctx *ctx, double dt, int M);
 int chebtd_get_plan(const chebtd_ctx *ctx, double *gamma_host, double *a, double *b,
                     double *dt, int *M);
 
+/* The passes of one step on the multi-order path (1D chains longer than
+ * the one-workgroup chain kernel, honeycomb ribbons; M >= 2): the Chebyshev
+ * orders each pass advances, in launch order.  The first pass is the step
+ * head (it also forms v_1 from psi); 2 runs the two-orders kernel, 3..6 the
+ * deep kernel (that many orders of the recursion of Sect. 2.2 in one pass
+ * over memory), 1 a single-order pass, only ever last.  The split is the
+ * cheapest by each pass's time relative to a two-order pass, fixed by M and
+ * the lattice (environment CHEBTD_DEPTH=D limits it to passes of 1, 2 and D
+ * orders).  passes_out (int[capacity], may be NULL) receives up to capacity
+ * entries; count_out receives the number of passes (0 when the plan runs
+ * one order per launch).  Needs a plan. */
+int chebtd_plan_passes(const chebtd_ctx *ctx, int *passes_out, int capacity, int *count_out);
+
 /* ======================================================================= */
 /* Propagation                                                              */
 /* ======================================================================= */
@@ -336,8 +349,10 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev);
  * times on the context's stream between two hipEvents, on scratch vectors
  * (allocated and freed here), and return the mean time per launch in
  * milliseconds, the kernel's name and the recursion orders one launch
- * advances (2 for the two-orders-per-pass kernel, else 1; CHEBTD_SINGLE_ORDER
- * in `flags` times the one-order kernel).  Needs a plan.  Synchronises.
+ * advances.  On the multi-order path that is the pass the step runs most
+ * often after its head (chebtd_plan_passes; 2 for the two-orders kernel, 3..6
+ * for the deep kernel), else 1; CHEBTD_SINGLE_ORDER in `flags` times the
+ * one-order kernel.  Needs a plan.  Synchronises.
  * name_out and orders_out may be NULL. */
 int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, double *ms_per_launch,
                                  const char **name_out, int *orders_out);

@@ -173,6 +173,15 @@ class Context:
                                               None, None))
         return dict(gamma=g, a=a.value, b=b.value, dt=dt.value, M=M.value)
 
+    def plan_passes(self):
+        """Orders per pass of one step on the multi-order path ([] when the
+        plan runs one order per launch)."""
+        n = C.c_int()
+        self._check(self._lib.chebtd_plan_passes(self.h, None, 0, C.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.int32)
+        self._check(self._lib.chebtd_plan_passes(self.h, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)))
+        return [int(v) for v in out[:n.value]]
+
     # -- propagation ------------------------------------------------------------
     def propagate(self, psi, K: int, norm=None, energy=None, flags: int = 0):
         torch = _torch()

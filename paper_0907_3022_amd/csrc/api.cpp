@@ -3,6 +3,7 @@
 // arXiv:0907.3022; every arithmetic step of it runs in the HIP kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -71,7 +72,12 @@ int ensure_partials(Ctx *c)
 {
     int64_t nb = (c->n + kBlock - 1) / kBlock;
     nb = std::max<int64_t>(nb, grid_blocks(*c));
-    if (pair_supported(*c)) nb = std::max<int64_t>(nb, pair_grid_blocks(*c, c->pair_rows));
+    if (pair_supported(*c)) {
+        nb = std::max<int64_t>(nb, pair_grid_blocks(*c, c->pair_rows));
+        // the head pass writes one partial pair per block
+        if (!c->passes.empty() && c->passes[0] > 2)
+            nb = std::max<int64_t>(nb, deep_grid_blocks(*c, c->deep_rows[c->passes[0]], c->passes[0]));
+    }
     size_t bytes = (size_t)std::max<int64_t>(nb, 1) * 2 * sizeof(double);
     if (c->holstein) {
         size_t hb = (size_t)holstein_obs_blocks(c->hol_nconf) * 3 * c->hol_L * sizeof(double);
@@ -101,6 +107,68 @@ int choose_pair_rows(const Ctx &c)
 {
     if (c.kind != HKind::Honeycomb) return 1;
     return pair_rows_for_width(c.W);
+}
+
+// Rows per wavefront chunk of the D-orders kernel.  Level j of the walk also
+// computes D - j halo rows on each side of its chunk, so short chunks repeat
+// work; lattices of 4M sites and more have wavefronts to spare and take 32
+// rows, smaller ones 8 (4 for D <= 4) to keep the chip busy.  Measured on
+// MI355X for ribbons of 128x8192, 512x32768 and 1024x65536 sites.
+// CHEBTD_DEEP_ROWS overrides.
+int choose_deep_rows(const Ctx &c, int D)
+{
+    if (c.kind != HKind::Honeycomb) return 1;
+    if (const char *env = std::getenv("CHEBTD_DEEP_ROWS")) {
+        const int r = std::atoi(env);
+        if (r >= 1) return r;
+    }
+    const int r = c.n >= (int64_t(4) << 20) ? 32 : (D <= 4 ? 4 : 8);
+    return (int)std::min<int64_t>(c.W, r);
+}
+
+// Orders per pass for one step of M >= 2 orders on a brick-wall lattice: the
+// cheapest split of M into passes of 2 .. kMaxDepth orders and at most one
+// single-order pass, by each pass's time relative to a two-order pass.  The
+// relative times were measured on MI355X (ribbon of 128x8192 sites, chain of
+// 2^20 sites); larger lattices favour deep passes at least as much.  The
+// split is fixed by M and the lattice alone, so results never depend on
+// timing.  CHEBTD_DEPTH=D limits the passes to 1, 2 and D orders (2: pair
+// kernel only).
+std::vector<int> plan_passes(const Ctx &c, int M)
+{
+    static const double ribbon_cost[kMaxDepth + 1] = {0.0, 0.78, 1.0, 1.21, 1.29, 1.43, 1.65};
+    static const double chain_cost[kMaxDepth + 1] = {0.0, 0.78, 1.0, 1.39, 1.86, 2.79, 3.57};
+    const double *cost = c.kind == HKind::Honeycomb ? ribbon_cost : chain_cost;
+    bool allowed[kMaxDepth + 1];
+    for (int d = 0; d <= kMaxDepth; ++d) allowed[d] = d >= 1;
+    if (const char *env = std::getenv("CHEBTD_DEPTH")) {
+        const int D = std::max(2, std::min(kMaxDepth, std::atoi(env)));
+        for (int d = 3; d <= kMaxDepth; ++d) allowed[d] = d == D;
+    }
+    // best[m]: cheapest passes for m orders; at most one single-order pass,
+    // which only a split of an odd m needs
+    std::vector<double> best(M + 1, 1e300);
+    std::vector<int> last(M + 1, 0);
+    best[0] = 0.0;
+    for (int m = 1; m <= M; ++m)
+        for (int d = 2; d <= kMaxDepth && d <= m; ++d)
+            if (allowed[d] && best[m - d] + cost[d] < best[m]) {
+                best[m] = best[m - d] + cost[d];
+                last[m] = d;
+            }
+    // the single-order pass, if any, comes last
+    int m = M, tail = 0;
+    double total = best[M];
+    if (M >= 3 && best[M - 1] + cost[1] < total) {
+        m = M - 1;
+        tail = 1;
+    }
+    // every m reached below has a finite cost, hence a last pass of >= 2 orders
+    std::vector<int> out;
+    for (; m > 0; m -= last[m]) out.push_back(last[m]);
+    std::sort(out.begin(), out.end(), [](int x, int y) { return x > y; });
+    if (tail) out.push_back(1);
+    return out;
 }
 
 void invalidate_h(Ctx *c)
@@ -393,12 +461,14 @@ static int plan_common(Ctx *c, double dt, int M)
         return rc;
     // two more vectors let brick-wall Hamiltonians advance two orders per pass
     c->use_pairs = false;
+    c->passes.clear();
     c->pair_rows = choose_pair_rows(*c);
-    if ((rc = ensure_partials(c))) return rc;
     if (pair_supported(*c) && M >= 2) {
         if ((rc = ensure(c, c->vC, vbytes, "work vector C")) || (rc = ensure(c, c->vD, vbytes, "work vector D")))
             return rc;
         c->use_pairs = true;
+        c->passes = plan_passes(*c, M);
+        for (int d = 3; d <= kMaxDepth; ++d) c->deep_rows[d] = choose_deep_rows(*c, d);
     }
     if ((rc = ensure_partials(c))) return rc;
     c->dt = dt;
@@ -447,6 +517,19 @@ int chebtd_get_plan(const chebtd_ctx *ctx, double *gamma_host, double *a, double
     if (b) *b = c->b;
     if (dt) *dt = c->dt;
     if (M) *M = c->M;
+    return CHEBTD_OK;
+}
+
+int chebtd_plan_passes(const chebtd_ctx *ctx, int *passes_out, int capacity, int *count_out)
+{
+    if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
+    const Ctx *c = static_cast<const Ctx *>(ctx);
+    if (!c->has_plan) return fail(const_cast<Ctx *>(c), CHEBTD_E_STATE, "chebtd_plan_passes: no plan");
+    if (capacity < 0 || (capacity > 0 && !passes_out))
+        return fail(const_cast<Ctx *>(c), CHEBTD_E_ARG, "chebtd_plan_passes: bad output array");
+    const int n = c->use_pairs ? (int)c->passes.size() : 0;
+    for (int i = 0; i < n && i < capacity; ++i) passes_out[i] = c->passes[i];
+    if (count_out) *count_out = n;
     return CHEBTD_OK;
 }
 

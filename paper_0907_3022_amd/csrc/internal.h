@@ -12,6 +12,8 @@
 
 namespace chebtd {
 
+constexpr int kMaxDepth = 6;  // most Chebyshev orders one deep-walk pass carries
+
 // ---------------------------------------------------------------------------
 // Operators: each applies 2 H~ = (2/a)(H - b) to row i of a complex vector.
 // The step head needs H~ itself and takes exactly half (a power-of-two
@@ -122,6 +124,11 @@ struct Ctx {
     DevBuf vA, vB, vC, vD;
     bool use_pairs = false;  // brick-wall H with M >= 2 and pair buffers present
     int pair_rows = 16;      // rows per wavefront chunk of the pair kernel
+    // orders per pass of one step on the multi-order path, the head's first
+    // and a single-order pass (if any) last: 2 runs the pair kernel, 3 ..
+    // kMaxDepth the deep kernel
+    std::vector<int> passes;
+    int deep_rows[kMaxDepth + 1] = {};  // rows per wavefront chunk of the deep kernel, by depth
     // reduction scratch: partial sums, step counter, results
     DevBuf partials;   // double[2 * max_blocks]
     DevBuf results;    // double[16]

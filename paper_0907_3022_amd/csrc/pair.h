@@ -30,6 +30,14 @@ int pair_rows_for_width(int64_t W);
 bool pair_supported(const Ctx &c);
 // head: v1 = H~ vk, v2 = 2 H~ v1 - vk, acc = g0 vk + g1 v1 + g2 v2 (+ partials, ckpt)
 // else: v_{k+1} = 2 H~ vk - vkm1, v_{k+2} = 2 H~ v_{k+1} - vk, acc += g1 v_{k+1} + g2 v_{k+2}
+// D = 3 or 4 orders per pass (deep_walk.h): the same buffers and roles as
+// launch_pair, with the weights g_k .. g_{k+D} in g (g[0] used by the head)
+OpPair make_deep_op(const Ctx &c, int rows, int D);
+int64_t deep_grid_blocks(const Ctx &c, int rows, int D);
+hipError_t launch_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, const double2 *vkm1,
+                       const double2 *vk, double2 *out1, double2 *out2, double2 *acc, const double2 *g,
+                       double2 *ckpt, double *partials, const NeFinal *fin);
+
 // fin (non-head passes, may be null): block 0 also finishes the step's norm
 // and energy from the head's partials
 hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1, const double2 *vk,

@@ -15,6 +15,7 @@
 #include "internal.h"
 #include "pair.h"
 #include "pair_walk.h"
+#include "deep_walk.h"
 
 namespace chebtd {
 
@@ -33,6 +34,31 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
     double nrm = 0.0, en = 0.0;
     if (chunk < op.nchunks)  // uniform per wavefront
         pair_walk<EDGE, HEAD>(op, strip, chunk, vkm1, vk, out1, out2, acc, g0, g1, g2, ckpt, nrm, en);
+    if (HEAD) {
+        block_sum2(nrm, en, red);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = nrm;
+            partials[2 * blockIdx.x + 1] = en;
+        }
+    }
+}
+
+template <int EDGE, int D, bool HEAD>
+__global__ __launch_bounds__(256) void k_deep(OpPair op, const double2 *__restrict__ vkm1,
+                                              const double2 *__restrict__ vk, double2 *__restrict__ out1,
+                                              double2 *__restrict__ out2, double2 *__restrict__ acc,
+                                              DeepWeights<D> gw, double2 *__restrict__ ckpt, double *partials,
+                                              NeFinal fin)
+{
+    __shared__ double red[2 * 4];
+    if (!HEAD && fin.partials && blockIdx.x == 0) finalize_ne_block(fin, nullptr, red);
+    const int32_t gwv =
+        __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
+    const int32_t strip = gwv % op.nstrips;
+    const int32_t chunk = gwv / op.nstrips;
+    double nrm = 0.0, en = 0.0;
+    if (chunk < op.nchunks)  // uniform per wavefront
+        deep_walk<EDGE, D, HEAD>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
     if (HEAD) {
         block_sum2(nrm, en, red);
         if (threadIdx.x == 0) {
@@ -106,6 +132,71 @@ hipError_t launch_pair(const Ctx &c, hipStream_t s, int rows, bool head, const d
                                g0, g1, g2, ckpt, partials, fin);
     }
     return hipGetLastError();
+}
+
+}  // namespace chebtd
+
+namespace chebtd {
+
+OpPair make_deep_op(const Ctx &c, int rows, int D)
+{
+    OpPair op = make_pair_op(c, rows);
+    op.nstrips = (op.L + deep_strip(D) - 1) / deep_strip(D);
+    return op;
+}
+
+int64_t deep_grid_blocks(const Ctx &c, int rows, int D)
+{
+    const OpPair op = make_deep_op(c, rows, D);
+    const int64_t waves = (int64_t)op.nstrips * op.nchunks;
+    return (waves + 3) / 4;
+}
+
+namespace {
+
+template <int D>
+hipError_t launch_deep_d(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1, const double2 *vk,
+                         double2 *out1, double2 *out2, double2 *acc, const double2 *g, double2 *ckpt,
+                         double *partials, const NeFinal *fin_in)
+{
+    const OpPair op = make_deep_op(c, rows, D);
+    const int64_t nb = deep_grid_blocks(c, rows, D);
+    if (nb <= 0 || nb > INT32_MAX) return hipErrorInvalidValue;
+    DeepWeights<D> gw;
+    for (int j = 0; j <= D; ++j) gw.g[j] = g[j];
+    NeFinal fin{};
+    if (fin_in && !head) fin = *fin_in;
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    if (head && zig)
+        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, gw,
+                           ckpt, partials, fin);
+    else if (head)
+        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, gw,
+                           ckpt, partials, fin);
+    else if (zig)
+        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, gw,
+                           ckpt, partials, fin);
+    else
+        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
+                           gw, ckpt, partials, fin);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, const double2 *vkm1,
+                       const double2 *vk, double2 *out1, double2 *out2, double2 *acc, const double2 *g,
+                       double2 *ckpt, double *partials, const NeFinal *fin)
+{
+    switch (D) {
+        case 2: return launch_deep_d<2>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
+        case 3: return launch_deep_d<3>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
+        case 4: return launch_deep_d<4>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
+        case 5: return launch_deep_d<5>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
+        case 6: return launch_deep_d<6>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace chebtd

@@ -31,46 +31,84 @@ double2 weight(const Ctx *c, int k)
     return make_double2(c->gamma[2 * (size_t)k], c->gamma[2 * (size_t)k + 1]);
 }
 
-// One time step with two orders per pass (brick-wall H, M >= 2): the head
-// pass forms v_1, v_2 and starts acc; each further pass forms the next two
-// orders from the previous two; an odd M ends with one single-order pass.
-// Pass outputs alternate between (vA, vC) and (vD, cur): cur is free once the
-// head pass has read it.
+// Orders of the multi-order pass a step runs most often after its head (ties:
+// the deeper), or the head's own when no such pass follows it.
+int dominant_pass(const Ctx &c)
+{
+    int count[kMaxDepth + 1] = {};
+    for (size_t i = 1; i < c.passes.size(); ++i)
+        if (c.passes[i] >= 2) ++count[c.passes[i]];
+    int best = c.passes.empty() ? 2 : c.passes[0];
+    int most = 0;
+    for (int d = 2; d <= kMaxDepth; ++d)
+        if (count[d] > 0 && count[d] >= most) {
+            most = count[d];
+            best = d;
+        }
+    return best;
+}
+
+// One time step with several orders per pass (brick-wall H, M >= 2), in the
+// passes the plan chose: the head pass forms v_1 .. v_D and starts acc; each
+// further pass forms its orders from the previous two vectors (2 orders: the
+// pair kernel, 3 .. kMaxDepth: the deep kernel); a single-order pass, if
+// any, comes last.  Pass outputs alternate between (vA, vC) and (vD, cur):
+// cur is free once the head pass has read it.
 hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt,
                               double *norm_out, double *energy_out)
 {
     double2 *A = static_cast<double2 *>(c->vA.p), *C = static_cast<double2 *>(c->vC.p),
             *D = static_cast<double2 *>(c->vD.p);
     double *partials = static_cast<double *>(c->partials.p);
-    hipError_t e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, A, C, nxt, weight(c, 0), weight(c, 1),
-                               weight(c, 2), ckpt, partials);
+    const std::vector<int> &P = c->passes;
+    const int h = P[0];
+    double2 g[kMaxDepth + 1];
+    hipError_t e;
+    int64_t head_blocks;
+    if (h > 2) {
+        for (int j = 0; j <= h; ++j) g[j] = weight(c, j);
+        e = launch_deep(*c, s, h, c->deep_rows[h], true, nullptr, cur, A, C, nxt, g, ckpt, partials, nullptr);
+        head_blocks = deep_grid_blocks(*c, c->deep_rows[h], h);
+    } else {
+        e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, A, C, nxt, weight(c, 0), weight(c, 1),
+                        weight(c, 2), ckpt, partials);
+        head_blocks = pair_grid_blocks(*c, c->pair_rows);
+    }
     if (e != hipSuccess) return e;
-    // the step's norm and energy: finished by block 0 of the next pass when
-    // there is one (no extra launch), else by their own kernel
-    const NeFinal fin{partials, (int)pair_grid_blocks(*c, c->pair_rows), c->a, c->b, norm_out, energy_out,
+    // the step's norm and energy: finished by block 0 of the next multi-order
+    // pass when there is one (no extra launch), else by their own kernel
+    const NeFinal fin{partials, (int)head_blocks, c->a, c->b, norm_out, energy_out,
                       static_cast<int64_t *>(c->counter.p)};
     const bool want_ne = norm_out || energy_out;
-    if (want_ne && c->M < 4) {
+    const bool has_next = P.size() > 1 && P[1] >= 2;
+    if (want_ne && !has_next) {
         e = launch_finalize_ne(s, partials, fin.nparts, c->a, c->b, norm_out, energy_out, fin.counter, nullptr);
         if (e != hipSuccess) return e;
     }
     double2 *X = A, *Y = C, *F1 = D, *F2 = cur;  // (v_{k-1}, v_k) and the free pair
-    int k = 2;
-    for (; k + 2 <= c->M; k += 2) {
-        e = launch_pair(*c, s, c->pair_rows, false, X, Y, F1, F2, nxt, make_double2(0.0, 0.0), weight(c, k + 1),
-                        weight(c, k + 2), nullptr, nullptr, (want_ne && k == 2) ? &fin : nullptr);
+    int k = h;
+    for (size_t i = 1; i < P.size(); ++i) {
+        const int d = P[i];
+        const NeFinal *f = (want_ne && i == 1) ? &fin : nullptr;
+        if (d == 1) {  // the last order: v_M = 2 H~ v_{M-1} - v_{M-2} over v_{M-2}
+            e = launch_iter(*c, s, Y, X, nxt, weight(c, k + 1));
+        } else if (d == 2) {
+            e = launch_pair(*c, s, c->pair_rows, false, X, Y, F1, F2, nxt, make_double2(0.0, 0.0),
+                            weight(c, k + 1), weight(c, k + 2), nullptr, nullptr, f);
+        } else {
+            g[0] = make_double2(0.0, 0.0);
+            for (int j = 1; j <= d; ++j) g[j] = weight(c, k + j);
+            e = launch_deep(*c, s, d, c->deep_rows[d], false, X, Y, F1, F2, nxt, g, nullptr, nullptr, f);
+        }
         if (e != hipSuccess) return e;
+        k += d;
         double2 *t1 = X, *t2 = Y;
         X = F1;
         Y = F2;
         F1 = t1;
         F2 = t2;
     }
-    if (k < c->M) {  // one order left: v_M = 2 H~ v_{M-1} - v_{M-2} over v_{M-2}
-        e = launch_iter(*c, s, Y, X, nxt, weight(c, c->M));
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return k == c->M ? hipSuccess : hipErrorInvalidValue;
 }
 
 // Enqueue one time step: cur -> nxt.  cur is overwritten with v_2, v_4, ...
@@ -349,15 +387,22 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
     if (!c->has_plan) return fail(c, CHEBTD_E_STATE, "chebtd_time_recursion_kernel: no plan");
     if (launches < 1 || !ms_per_launch) return fail(c, CHEBTD_E_ARG, "need launches >= 1 and an output");
     const bool pairs = c->use_pairs && !(flags & CHEBTD_SINGLE_ORDER);
+    // the multi-order kernel the step spends most of its passes in
+    const int dp = pairs ? dominant_pass(*c) : 2;
     static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr",
                                   "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol"};
-    const char *nm = pairs ? (c->kind == HKind::Honeycomb && c->edge == CHEBTD_ARMCHAIR ? names[5] : names[4])
+    static const char *deep_names[2][kMaxDepth + 1] = {
+        {"", "", "", "k_deep<0,3,false>", "k_deep<0,4,false>", "k_deep<0,5,false>", "k_deep<0,6,false>"},
+        {"", "", "", "k_deep<1,3,false>", "k_deep<1,4,false>", "k_deep<1,5,false>", "k_deep<1,6,false>"}};
+    const bool arm = c->kind == HKind::Honeycomb && c->edge == CHEBTD_ARMCHAIR;
+    const char *nm = (pairs && dp > 2) ? deep_names[arm ? 1 : 0][dp]
+                     : pairs ? (arm ? names[5] : names[4])
                      : c->kind == HKind::Chain    ? names[0]
                      : c->kind == HKind::Csr      ? names[3]
                      : c->kind == HKind::Holstein ? names[6]
                      : (c->edge == CHEBTD_ZIGZAG ? names[1] : names[2]);
     if (name_out) *name_out = nm;
-    if (orders_out) *orders_out = pairs ? 2 : 1;
+    if (orders_out) *orders_out = pairs ? dp : 1;
     // scratch: four vectors and an accumulator, zeroed
     DevBuf scratch;
     const size_t vb = (size_t)c->n * sizeof(double2);
@@ -367,7 +412,15 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
     double2 *V0 = static_cast<double2 *>(scratch.p), *V1 = V0 + c->n, *V2 = V1 + c->n, *V3 = V2 + c->n,
             *acc = V3 + c->n;
     hipError_t e = hipMemsetAsync(scratch.p, 0, 5 * vb, s);
+    double2 gd[kMaxDepth + 1];
+    for (int j = 0; j <= dp; ++j) gd[j] = weight(c, j < 1 ? 1 : j);
+    gd[0] = make_double2(0.0, 0.0);
     auto one = [&](int i) -> hipError_t {
+        if (pairs && dp > 2)
+            return (i & 1) ? launch_deep(*c, s, dp, c->deep_rows[dp], false, V2, V3, V0, V1, acc, gd, nullptr,
+                                         nullptr, nullptr)
+                           : launch_deep(*c, s, dp, c->deep_rows[dp], false, V0, V1, V2, V3, acc, gd, nullptr,
+                                         nullptr, nullptr);
         if (pairs)
             return (i & 1) ? launch_pair(*c, s, c->pair_rows, false, V2, V3, V0, V1, acc, make_double2(0, 0),
                                          weight(c, 1), weight(c, 2), nullptr, nullptr)

@@ -1,0 +1,170 @@
+"""D = 3 .. 6 Chebyshev orders per pass (the deep walk) against the CPU
+oracle, and against the two-orders-per-pass path, for ribbons and chains."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from test_gpu_parity import chain_case, dev, gpu_context, honey_case, host, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available()
+    return T
+
+
+@pytest.fixture(scope="module")
+def cheb():
+    import paper_0907_3022_amd as P
+    P.load_library()
+    return P
+
+
+@pytest.fixture
+def depth_env():
+    saved = {k: os.environ.get(k) for k in ("CHEBTD_DEPTH", "CHEBTD_DEEP_ROWS")}
+
+    def setter(depth, rows=None):
+        if depth is None:  # the library's own choice of passes
+            os.environ.pop("CHEBTD_DEPTH", None)
+        else:
+            os.environ["CHEBTD_DEPTH"] = str(depth)
+        if rows is None:
+            os.environ.pop("CHEBTD_DEEP_ROWS", None)
+        else:
+            os.environ["CHEBTD_DEEP_ROWS"] = str(rows)
+    yield setter
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+def run(torch, cheb, case, dt, K, M=None, flags=0):
+    H = case["H"]
+    emin, emax = H.gershgorin()
+    plan = O.Plan(emin, emax, dt, M=M)
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax, 0.01)
+    Mg = ctx.plan(dt) if M is None else (ctx.plan_order(dt, M) and M)
+    assert Mg == plan.M
+    psi = dev(torch, case["psi0"])
+    nrm = torch.zeros(K, dtype=torch.float64, device="cuda")
+    en = torch.zeros(K, dtype=torch.float64, device="cuda")
+    # forced low orders are not unitary: skip the end-of-call norm check
+    ctx.propagate(psi, K, nrm, en, flags | (cheb.NO_CHECK if M is not None else 0))
+    torch.cuda.synchronize()
+    return ctx, host(psi), host(nrm), host(en), plan
+
+
+# ragged ribbons: fewer rows than a chunk, partial strips, one column past a strip
+@pytest.mark.parametrize("depth", [None, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("shape", [(1, 300, "zigzag"), (3, 59, "zigzag"), (8, 200, "armchair"),
+                                   (17, 117, "zigzag"), (24, 61, "armchair")])
+@pytest.mark.parametrize("M", [3, 4, 5, 6, 7, 11, 20])
+def test_deep_ribbon_matches_oracle(torch, cheb, depth_env, depth, shape, M):
+    w, l, edge = shape
+    depth_env(depth)
+    case = honey_case(w, l, edge)
+    say(f"[gpu] deep D={depth} ribbon {w}x{l} {edge} M={M}")
+    _, psi, nrm, en, plan = run(torch, cheb, case, 1.0, 3, M=M)
+    ref, rn, re = O.propagate(case["H"], plan, case["psi0"], 3, want_obs=True)
+    assert rel_l2(psi, ref) <= 1e-10
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    np.testing.assert_allclose(en, re, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("depth", [3, 4, 6])
+@pytest.mark.parametrize("rows", [1, 2, 5, 8, 16, 32])
+def test_deep_chunk_heights(torch, cheb, depth_env, depth, rows):
+    depth_env(depth, rows)
+    case = honey_case(37, 130, "zigzag")
+    _, psi, _, _, plan = run(torch, cheb, case, 1.0, 2)
+    ref = O.propagate(case["H"], plan, case["psi0"], 2)
+    assert rel_l2(psi, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("depth", [3, 4, 5, 6])
+@pytest.mark.parametrize("n", [4097, 20011])
+def test_deep_chain_matches_oracle(torch, cheb, depth_env, depth, n):
+    # longer than the one-workgroup chain kernel: the chain runs as a ribbon of one row
+    depth_env(depth)
+    case = chain_case(n)
+    _, psi, _, _, plan = run(torch, cheb, case, 0.002, 2)
+    ref = O.propagate(case["H"], plan, case["psi0"], 2)
+    assert rel_l2(psi, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("depth", [3, 4, 5, 6])
+def test_deep_graph_replays_bitwise_and_agrees_with_pairs(torch, cheb, depth_env, depth):
+    case = honey_case(16, 700)
+    depth_env(2)
+    _, p2, _, _, _ = run(torch, cheb, case, 1.0, 6)
+    depth_env(depth)
+    _, pd, nd, _, _ = run(torch, cheb, case, 1.0, 6)
+    _, pg, ng, _, _ = run(torch, cheb, case, 1.0, 6, flags=cheb.GRAPH)
+    np.testing.assert_array_equal(pd, pg)
+    np.testing.assert_array_equal(nd, ng)
+    # the same arithmetic in another order: agreement to rounding
+    assert rel_l2(pd, p2) <= 1e-13
+
+
+def test_deep_headline_ribbon_full_size(torch, cheb, depth_env):
+    p = W.GRAPHENE.params
+    case = honey_case(p["width"], p["length"], p["edge"], p["W"], p["seed"], p["sigma"], p["k0"])
+    for depth in (3, 4, 5, 6):
+        depth_env(depth)
+        _, psi, nrm, _, plan = run(torch, cheb, case, p["dt"], 2)
+        ref, rn, _ = O.propagate(case["H"], plan, case["psi0"], 2, want_obs=True)
+        assert plan.M == 20
+        assert rel_l2(psi, ref) <= 1e-10
+        np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+
+
+def check_passes(passes, M, allowed):
+    assert sum(passes) == M
+    assert passes[0] >= 2  # the head forms v_1 .. v_D
+    assert passes.count(1) <= 1 and (1 not in passes or passes[-1] == 1)
+    assert all(p in allowed for p in passes)
+
+
+@pytest.mark.parametrize("kind", ["ribbon", "chain"])
+def test_plan_passes(torch, cheb, depth_env, kind):
+    case = honey_case(16, 200) if kind == "ribbon" else chain_case(5000)
+    ctx = gpu_context(torch, cheb, case)
+    emin, emax = case["H"].gershgorin()
+    ctx.set_bounds(emin, emax, 0.01)
+    depth_env(None)
+    for M in range(2, 64):
+        ctx.plan_order(1.0, M)
+        check_passes(ctx.plan_passes(), M, {1, 2, 3, 4, 5, 6})
+    if kind == "ribbon":
+        ctx.plan_order(1.0, 20)
+        assert ctx.plan_passes() == [5, 5, 5, 5]
+    for depth in (2, 3, 4, 5, 6):
+        depth_env(depth)
+        for M in range(2, 40):
+            ctx.plan_order(1.0, M)
+            check_passes(ctx.plan_passes(), M, {1, 2, depth})
+    depth_env(None)
+    ctx.plan_order(1.0, 1)
+    assert ctx.plan_passes() == []
+
+
+def test_plan_passes_default_schedules_match_oracle(torch, cheb, depth_env):
+    # every M from 2 to 30 under the library's own split, on one ragged ribbon
+    depth_env(None)
+    case = honey_case(21, 131, "armchair")
+    for M in range(2, 31):
+        _, psi, nrm, en, plan = run(torch, cheb, case, 1.0, 2, M=M)
+        ref, rn, re = O.propagate(case["H"], plan, case["psi0"], 2, want_obs=True)
+        assert rel_l2(psi, ref) <= 1e-10, M
+        np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+        np.testing.assert_allclose(en, re, rtol=1e-10, atol=1e-12)
