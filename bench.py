@@ -7,7 +7,7 @@ M = 20 from the 1e-15 Bessel cutoff).  One step is the whole hot path: the
 step head (v_1 = H~ psi, acc = gamma_0 psi + gamma_1 v_1, norm and energy
 reductions) and the recursion v_{k+1} = 2 H~ v_k - v_{k-1},
 acc += gamma_{k+1} v_{k+1} up to order M, several orders per pass over memory
-(the pass split the library plans: 5+5+5+5 at M = 20).  The plan (bounds,
+(the split the library plans, reported as config.orders_per_pass).  The plan (bounds,
 Bessel weights, passes) is computed once per dt, outside the timed region, as
 the method prescribes.
 

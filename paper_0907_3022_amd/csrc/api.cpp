@@ -109,12 +109,15 @@ int choose_pair_rows(const Ctx &c)
     return pair_rows_for_width(c.W);
 }
 
+// Lattices of 4M sites and more count as large: the pass costs and chunk
+// heights below were measured on MI355X for ribbons of 128x8192 (small),
+// 512x32768 and 1024x65536 sites (large).
+static bool large_lattice(const Ctx &c) { return c.n >= (int64_t(4) << 20); }
+
 // Rows per wavefront chunk of the D-orders kernel.  Level j of the walk also
 // computes D - j halo rows on each side of its chunk, so short chunks repeat
-// work; lattices of 4M sites and more have wavefronts to spare and take 32
-// rows, smaller ones 8 (4 for D <= 4) to keep the chip busy.  Measured on
-// MI355X for ribbons of 128x8192, 512x32768 and 1024x65536 sites.
-// CHEBTD_DEEP_ROWS overrides.
+// work; large lattices have wavefronts to spare and take 32 rows, small ones
+// 4 (8 for D = 6) to keep the chip busy.  CHEBTD_DEEP_ROWS overrides.
 int choose_deep_rows(const Ctx &c, int D)
 {
     if (c.kind != HKind::Honeycomb) return 1;
@@ -122,28 +125,31 @@ int choose_deep_rows(const Ctx &c, int D)
         const int r = std::atoi(env);
         if (r >= 1) return r;
     }
-    const int r = c.n >= (int64_t(4) << 20) ? 32 : (D <= 4 ? 4 : 8);
+    const int r = large_lattice(c) ? 32 : (D >= 6 ? 8 : 4);
     return (int)std::min<int64_t>(c.W, r);
 }
 
 // Orders per pass for one step of M >= 2 orders on a brick-wall lattice: the
 // cheapest split of M into passes of 2 .. kMaxDepth orders and at most one
-// single-order pass, by each pass's time relative to a two-order pass.  The
-// relative times were measured on MI355X (ribbon of 128x8192 sites, chain of
-// 2^20 sites); larger lattices favour deep passes at least as much.  The
-// split is fixed by M and the lattice alone, so results never depend on
-// timing.  CHEBTD_DEPTH=D limits the passes to 1, 2 and D orders (2: pair
-// kernel only).
+// single-order pass, by each pass's time relative to a two-order pass
+// (measured on MI355X: ribbons as above, a chain of 2^20 sites).  The split
+// is fixed by M and the lattice alone, so results never depend on timing.
+// CHEBTD_DEPTH=D limits the passes to 1, 2 and D orders (2: pair kernel only).
 std::vector<int> plan_passes(const Ctx &c, int M)
 {
-    static const double ribbon_cost[kMaxDepth + 1] = {0.0, 0.78, 1.0, 1.21, 1.29, 1.43, 1.65};
-    static const double chain_cost[kMaxDepth + 1] = {0.0, 0.78, 1.0, 1.39, 1.86, 2.79, 3.57};
-    const double *cost = c.kind == HKind::Honeycomb ? ribbon_cost : chain_cost;
+    static const double small_cost[kMaxDepth + 1] = {0.0, 0.80, 1.0, 1.05, 1.14, 1.42, 1.37};
+    static const double large_cost[kMaxDepth + 1] = {0.0, 0.70, 1.0, 1.02, 1.05, 0.98, 1.10};
+    static const double chain_cost[kMaxDepth + 1] = {0.0, 0.78, 1.0, 1.27, 2.0, 2.8, 3.6};
+    const double *cost = c.kind != HKind::Honeycomb ? chain_cost : large_lattice(c) ? large_cost : small_cost;
     bool allowed[kMaxDepth + 1];
-    for (int d = 0; d <= kMaxDepth; ++d) allowed[d] = d >= 1;
+    // the deep kernel addresses the lattice with 32-bit offsets (a chain is
+    // one row of n columns)
+    const bool chain = c.kind == HKind::Chain;
+    const bool deep_ok = deep_offsets_fit(chain ? 1 : c.W, chain ? c.n : c.L);
+    for (int d = 0; d <= kMaxDepth; ++d) allowed[d] = d == 1 || d == 2 || (d > 2 && deep_ok);
     if (const char *env = std::getenv("CHEBTD_DEPTH")) {
         const int D = std::max(2, std::min(kMaxDepth, std::atoi(env)));
-        for (int d = 3; d <= kMaxDepth; ++d) allowed[d] = d == D;
+        for (int d = 3; d <= kMaxDepth; ++d) allowed[d] = d == D && deep_ok;
     }
     // best[m]: cheapest passes for m orders; at most one single-order pass,
     // which only a split of an odd m needs

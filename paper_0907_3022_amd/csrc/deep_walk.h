@@ -10,16 +10,30 @@
 //
 // The walk generalises the two-level one of pair_walk.h.  At iteration r
 // level j computes row r - (j-1) from level j-1's window of three rows and
-// level j-2's value at the same row, so every level keeps rows
-// q-2 .. q of its own values in registers.  Horizontally each level past the
-// first loses one valid lane per side: a wavefront owns the 66 - 2D columns
-// on lanes D-1 .. 64-D.  Vertically level j is needed on rows
-// ys - (D-j) .. ye - 1 + (D-j) of the chunk [ys, ye); the neighbouring
-// chunks recompute those halo rows.  acc of a row collects its D terms over
-// D iterations in a ring of partial sums.
+// level j-2's value at the same row, so levels 0 .. D-1 keep three rows each
+// in registers.  Horizontally each level past the first loses one valid lane
+// per side: a wavefront owns the 66 - 2D columns on lanes D-1 .. 64-D.
+// Vertically level j is needed on rows ys - (D-j) .. ye - 1 + (D-j) of the
+// chunk [ys, ye); the neighbouring chunks recompute those halo rows.  acc of
+// a row collects its D terms over D iterations in a ring of partial sums.
+//
+// Register rings without moves: the row a level writes at iteration i goes
+// to window slot i mod 3, the partial sum and the diagonal term of row r - t
+// sit in slot (i - t) mod D, and the operands loaded kDeepAhead iterations
+// ahead rotate through kDeepAhead + 1 sets.  The loop body is unrolled over
+// a common multiple of the ring sizes, so every slot index is a constant
+// and no value is copied between registers.
+//
+// Memory goes through buffer loads and stores whose 32-bit offsets wrap:
+// rows above or below the lattice, columns outside it and lanes that own no
+// column get offsets at or past the buffer's size, which the hardware's
+// range check turns into zeros (loads) or dropped writes (stores), so the
+// walk selects nothing per row.  deep_offsets_fit states the size limit.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "device_ops.h"
 #include "pair.h"
@@ -33,17 +47,63 @@ struct DeepWeights {
 };
 
 constexpr int deep_strip(int D) { return 66 - 2 * D; }
+constexpr int deep_gcd(int a, int b) { return b == 0 ? a : deep_gcd(b, a % b); }
+constexpr int deep_lcm(int a, int b) { return a / deep_gcd(a, b) * b; }
+// Iterations between issuing a row's loads and using them.  A wavefront
+// walks its rows one after another, so the loads of the next row alone
+// cannot cover the memory latency when few wavefronts share a SIMD.
+constexpr int kDeepAhead = 1;
+// iterations per unrolled loop body: a multiple of kDeepAhead + 1
+// (prefetch sets), 3 (row windows) and D (partial sums)
+constexpr int deep_unroll(int D) { return deep_lcm(deep_lcm(kDeepAhead + 1, 3), D); }
 
 namespace deepdev {
 
-struct Prefetch {
-    double2 a, km1, ext, acc;
-    double e;
-};
+using Rsrc = __amdgpu_buffer_rsrc_t;
+// word 3 of the buffer descriptor for gfx9-family parts: 32-bit data format,
+// raw (unswizzled) addressing
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr uint32_t kOut = 0x80000000u;  // offset bias of out-of-lattice lanes
+
+__device__ __forceinline__ Rsrc rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+// voff: the lane's offset; soff: a wave-uniform offset added to it
+__device__ __forceinline__ double2 bload2(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double bload1(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, double2 v)
+{
+    using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, (int)voff, (int)soff, 0);
+}
+
+// f(integral_constant<PH>) for PH = 0 .. U-1 while base + PH < T
+template <int PH, int U, typename F>
+__device__ __forceinline__ void phases(F &f, int32_t base, int32_t T)
+{
+    if constexpr (PH < U) {
+        if (base + PH < T) f(std::integral_constant<int, PH>{});
+        phases<PH + 1, U>(f, base, T);
+    }
+}
 
 }  // namespace deepdev
 
-template <int EDGE, int D, bool HEAD>
+// The wavefront's share: strip `strip` (66 - 2D columns), rows
+// [chunk*op.rows, min((chunk+1)*op.rows, W)).  BORDER: the strip has lanes
+// outside the lattice's columns, or the chunk's halo reaches past its first
+// or last row; values outside the lattice must then stay zero, so each level
+// is limited to its rows and masked to the lattice's columns.  Elsewhere a
+// level also computes the rows before its first needed one; those only feed
+// other such rows and are never stored.
+template <int EDGE, int D, bool HEAD, bool BORDER>
 __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32_t chunk,
                                           const double2 *__restrict__ vkm1, const double2 *__restrict__ vk,
                                           double2 *__restrict__ out1, double2 *__restrict__ out2,
@@ -52,8 +112,9 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
 {
     static_assert(D >= 2 && D <= 6, "depth");
     using namespace pairdev;
-    using deepdev::Prefetch;
+    using namespace deepdev;
     constexpr int S = deep_strip(D);
+    constexpr int U = deep_unroll(D);
     const int lane = threadIdx.x & 63;
     const int32_t W = op.W, L = op.L;
     const int32_t x = strip * S + lane - (D - 1);
@@ -61,129 +122,157 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     const bool own = colok && lane >= D - 1 && lane <= 64 - D;
     const double2 zero = make_double2(0.0, 0.0);
     const int32_t ys = chunk * op.rows;
-    const int32_t ye = min(ys + op.rows, W);
-    // unconditional loads from clamped indices; zeros outside the lattice
-    // are selected when a value is used (see pair_walk.h)
-    auto okr = [&](int32_t r) -> bool { return colok && r >= 0 && r < W; };
-    auto ld = [&](const double2 *v, int32_t r) -> double2 { return ldg(v, okr(r) ? (int64_t)r * L + x : 0); };
-    auto ld_on = [&](int32_t r) -> double { return ldg(op.onsite, okr(r) ? (int64_t)r * L + x : 0); };
+    const int32_t nrows = min(op.rows, W - ys);  // rows of the chunk
+
+    const uint32_t nb16 = (uint32_t)W * (uint32_t)L * 16u;
+    const Rsrc rk = rsrc(vk, nb16), ron = rsrc(op.onsite, nb16 / 2);
+    const Rsrc rkm1 = rsrc(HEAD ? vk : vkm1, nb16), racc = rsrc(acc, nb16);
+    // without a checkpoint buffer its descriptor has size 0 and drops every store
+    const Rsrc ro1 = rsrc(out1, nb16), ro2 = rsrc(out2, nb16), rck = rsrc(ckpt ? ckpt : acc, ckpt ? nb16 : 0u);
+    // column part of each offset: loads (lattice columns), stores (own
+    // columns), the outside value (lanes 0 and 63); kOut elsewhere
+    const uint32_t c16 = colok ? (uint32_t)x * 16u : kOut;
+    const uint32_t c8 = colok ? (uint32_t)x * 8u : kOut;
+    const uint32_t s16 = own ? (uint32_t)x * 16u : kOut;
+    // The outside value of lanes 0 and 63 (columns x-1, x+1) enters the
+    // stencil sum as one more term, zero on every other lane.  On armchair
+    // edges a lane reads it only on rows where its horizontal neighbour is on
+    // that side (lane 0 on odd x+q, lane 63 on even), so it is loaded there only.
     const int32_t xe = lane == 0 ? x - 1 : x + 1;
-    const bool ext_lane = (lane == 0 || lane == 63) && xe >= 0 && xe < L;
-    auto ok_ext = [&](int32_t r) -> bool { return ext_lane && r >= 0 && r < W; };
-    auto ld_ext = [&](int32_t r) -> double2 { return ldg(vk, ok_ext(r) ? (int64_t)r * L + xe : 0); };
-    auto ld_acc = [&](int32_t r) -> double2 {
-        const bool ok = own && r >= ys && r < ye;
-        return ldg(acc, ok ? (int64_t)r * L + x : 0);
+    const uint32_t e16 = ((lane == 0 || lane == 63) && xe >= 0 && xe < L) ? (uint32_t)xe * 16u : kOut;
+    const int32_t epar = lane == 0 ? 1 : 0;
+    auto ext_off = [&](int32_t q) -> uint32_t {
+        if (EDGE == CHEBTD_ZIGZAG) return e16;
+        return ((x + q) & 1) == epar ? e16 : kOut;
     };
-    auto st = [&](double2 *v, int32_t r, double2 val) { stg(v, (int64_t)r * L + x, val); };
-
-    const int32_t r0 = ys - (D - 1);   // first iteration: level 1 at its first needed row
-    const int32_t r1 = ye + (D - 2);   // last iteration: level D at row ye - 1
-    // level 0 (v_k) rows r-1, r; level j >= 1 rows q_j-2, q_j-1, q_j
-    double2 a_m1 = csel(okr(r0 - 1), ld(vk, r0 - 1), zero);
-    double2 a_0 = csel(okr(r0), ld(vk, r0), zero);
-    double2 lv[D + 1][3];
-#pragma unroll
-    for (int j = 0; j <= D; ++j) lv[j][0] = lv[j][1] = lv[j][2] = zero;
-    double e[D];  // on-site term of rows r, r-1, .., r-D+1
-#pragma unroll
-    for (int j = 0; j < D; ++j) e[j] = 0.0;
-    double2 P[D];  // partial acc of rows r, r-1, .., r-D+1
-#pragma unroll
-    for (int j = 0; j < D; ++j) P[j] = zero;
-    Prefetch p0, p1;
-    p0.a = ld(vk, r0 + 1);
-    p0.km1 = HEAD ? zero : ld(vkm1, r0);
-    p0.e = ld_on(r0);
-    p0.ext = ld_ext(r0);
-    p0.acc = HEAD ? zero : ld_acc(r0);
-
-    // stencil: 2 H~ of level `lo` at row q from its window (m, c, p = rows
-    // q-1, q, q+1) with the horizontal neighbours of c
-    auto stencil = [&](double2 m, double2 c, double2 p, double2 left, double2 right, int32_t q, double eq) {
-        const bool even = ((x + q) & 1) == 0;
-        double2 sum;
-        if (EDGE == CHEBTD_ZIGZAG)
-            sum = cadd(cadd(left, right), csel(even, p, m));
+    const uint32_t row16 = (uint32_t)L * 16u, row8 = (uint32_t)L * 8u;
+    // Row part of an offset, wrapping for rows above the lattice.  On the
+    // border it joins the lane's part, so that the range check sees rows
+    // outside the lattice; inside, every row exists and it rides in the
+    // instruction's scalar offset instead.
+    auto ld2 = [&](Rsrc rs, uint32_t lanepart, int32_t row) -> double2 {
+        const uint32_t ro = (uint32_t)row * row16;
+        return BORDER ? bload2(rs, ro + lanepart, 0) : bload2(rs, lanepart, ro);
+    };
+    auto ld1 = [&](Rsrc rs, uint32_t lanepart, int32_t row) -> double {
+        const uint32_t ro = (uint32_t)row * row8;
+        return BORDER ? bload1(rs, ro + lanepart, 0) : bload1(rs, lanepart, ro);
+    };
+    // store to the own columns of `row` if `ok`; otherwise the store is
+    // issued anyway, from out-of-range lanes, and dropped (a branch here
+    // would make every later wait drain all loads in flight)
+    auto st2 = [&](Rsrc rs, int32_t row, double2 v, bool ok) {
+        const uint32_t ro = (uint32_t)row * row16;
+        const uint32_t lanepart = ok ? s16 : kOut;
+        if (BORDER)
+            bstore2(rs, ro + lanepart, 0, v);
         else
-            sum = cadd(cadd(m, p), csel(even, right, left));
-        const double d = op.s2 * (eq + op.dshift);
-        return make_double2(fma(d, c.x, op.off2 * sum.x), fma(d, c.y, op.off2 * sum.y));
+            bstore2(rs, lanepart, ro, v);
     };
 
-    auto row_step = [&](int32_t r, const Prefetch &cur, Prefetch &nx) {
-        nx.a = ld(vk, r + 2);
-        nx.km1 = HEAD ? zero : ld(vkm1, r + 1);
-        nx.e = ld_on(r + 1);
-        nx.ext = ld_ext(r + 1);
-        if (!HEAD) nx.acc = ld_acc(r + 1);
-        const double2 a_p1 = csel(okr(r + 1), cur.a, zero);
-        const double2 ext = csel(ok_ext(r), cur.ext, zero);
-        // on-site ring: e[j] = row r - j
+    const int32_t r0 = ys - (D - 1);  // iteration i: level j at row r0 + i - (j-1)
+    // windows of levels 0 .. D-1 (three rows each); partial sums and
+    // diagonal terms 2 (eps - b)/a of the last D rows
+    double2 lv[D][3];
+    double2 P[D];
+    double dd[D];
 #pragma unroll
-        for (int j = D - 1; j > 0; --j) e[j] = e[j - 1];
-        e[0] = cur.e;
-        // level 0 window for this iteration: rows r-1, r, r+1
-        lv[0][0] = a_m1;
-        lv[0][1] = a_0;
-        lv[0][2] = a_p1;
+    for (int j = 0; j < D; ++j) {
+        lv[j][0] = lv[j][1] = lv[j][2] = zero;
+        P[j] = zero;
+        dd[j] = 0.0;
+    }
+    // iteration 0 reads level-0 rows r0-1 (slot 1) and r0 (slot 2)
+    lv[0][1] = ld2(rk, c16, r0 - 1);
+    lv[0][2] = ld2(rk, c16, r0);
+    // operands of iteration n (pair_walk.h's set: v_k of the row below, and
+    // v_{k-1}, on-site term, outside value and acc of row r0 + n)
+    constexpr int K = kDeepAhead + 1;
+    pairdev::Prefetch pf[K];
+    auto issue = [&](pairdev::Prefetch &nx, int32_t n) {
+        const int32_t rn = r0 + n;
+        nx.a = ld2(rk, c16, rn + 1);
+        if (!HEAD) nx.km1 = ld2(rkm1, c16, rn);
+        nx.e = ld1(ron, c8, rn);
+        nx.ext = ld2(rk, ext_off(rn), rn);
+        // acc only where it is stored again (other rows' sums are discarded)
+        const int32_t rel = n - (D - 1);
+        const bool ok = rel >= 0 && rel < nrows;
+        if (!HEAD) nx.acc = ld2(racc, ok ? s16 : kOut, rn);
+    };
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        pf[k].km1 = pf[k].acc = zero;
+        if (k < K - 1) issue(pf[k], k);
+    }
+
+    auto stencil_sum = [&](double2 m, double2 p, double2 left, double2 right, int32_t q) {
+        const bool even = ((x + q) & 1) == 0;
+        if (EDGE == CHEBTD_ZIGZAG) return cadd(cadd(left, right), csel(even, p, m));
+        return cadd(cadd(m, p), csel(even, right, left));
+    };
+
+    int32_t base = 0;  // first iteration of the unrolled body
+    auto step = [&](auto phc) {
+        constexpr int ph = decltype(phc)::value;
+        constexpr int sl0 = ph % 3, sl1 = (ph + 2) % 3, sl2 = (ph + 1) % 3;  // iterations i, i-1, i-2
+        pairdev::Prefetch &cur = pf[ph % K];
+        const int32_t i = base + ph;
+        const int32_t rr = r0 + i;
+        // operands kDeepAhead iterations on, into the set freed last iteration
+        issue(pf[(ph + K - 1) % K], i + K - 1);
+        lv[0][sl0] = cur.a;  // level 0, row rr+1
+        dd[ph % D] = op.s2 * (cur.e + op.dshift);
 #pragma unroll
         for (int j = 1; j <= D; ++j) {
-            const int32_t q = r - (j - 1);
-            double2 val = zero;
-            // level j is needed on rows ys - (D-j) .. ye - 1 + (D-j), and
-            // is zero outside the lattice's rows
-            if (q >= max(ys - (D - j), 0) && q <= min(ye - 1 + (D - j), W - 1)) {
-                const double2 c = lv[j - 1][1];
-                double2 left, right;
-                if (j == 1) {
-                    left = from_left(c, ext);
-                    right = from_right(c, ext);
+            const int32_t q = rr - (j - 1);
+            const int32_t rel = i - (D - 1) - (j - 1);     // q - ys
+            const int ps = ((ph - (j - 1)) % D + D) % D;  // ring slot of row q
+            // on the border a level outside its rows is zero
+            const bool active =
+                !BORDER || (q >= max(ys - (D - j), 0) && q <= min(ys + nrows - 1 + (D - j), W - 1));
+            double2 val;
+            {
+                const double2 c = lv[j - 1][sl1], m = lv[j - 1][sl2], p = lv[j - 1][sl0];
+                double2 s = stencil_sum(m, p, from_left0(c), from_right0(c), q);
+                if (j == 1) s = cadd(s, cur.ext);
+                const double d = dd[ps];
+                if (HEAD && j == 1) {
+                    val = make_double2(0.5 * fma(d, c.x, op.off2 * s.x), 0.5 * fma(d, c.y, op.off2 * s.y));
                 } else {
-                    left = from_left0(c);
-                    right = from_right0(c);
+                    const double2 prev = j == 1 ? cur.km1 : lv[j >= 2 ? j - 2 : 0][sl2];
+                    val = make_double2(fma(d, c.x, fma(op.off2, s.x, -prev.x)),
+                                       fma(d, c.y, fma(op.off2, s.y, -prev.y)));
                 }
-                const double2 h = stencil(lv[j - 1][0], c, lv[j - 1][2], left, right, q, e[j - 1]);
-                if (j == 1)
-                    val = HEAD ? cscale(0.5, h) : csub(h, cur.km1);
-                else
-                    val = csub(h, j == 2 ? lv[0][0] : lv[j - 2][0]);
-                val = csel(colok, val, zero);
-            }
-            lv[j][0] = lv[j][1];
-            lv[j][1] = lv[j][2];
-            lv[j][2] = val;
-            // partial acc of row q
-            if (j == 1) {
-                P[0] = cfma(gw.g[1], val, HEAD ? cfma(gw.g[0], a_0, zero) : cur.acc);
-                if (HEAD && own && r >= ys && r < ye) {
-                    if (ckpt) st(ckpt, r, a_0);
-                    nrm += a_0.x * a_0.x + a_0.y * a_0.y;
-                    en += a_0.x * val.x + a_0.y * val.y;
+                if (BORDER) val = csel(colok && active, val, zero);
+                const bool mine = rel >= 0 && rel < nrows;  // a row of the chunk
+                if (j == 1) {
+                    if (HEAD) {
+                        P[ps] = cfma(gw.g[1], val, cfma(gw.g[0], c, zero));
+                        st2(rck, q, c, mine);
+                        const bool sum = own && mine;
+                        nrm += sum ? c.x * c.x + c.y * c.y : 0.0;
+                        en += sum ? c.x * val.x + c.y * val.y : 0.0;
+                    } else {
+                        P[ps] = cfma(gw.g[1], val, cur.acc);
+                    }
+                } else {
+                    P[ps] = cfma(gw.g[j], val, P[ps]);
                 }
-            } else {
-                P[j - 1] = cfma(gw.g[j], val, P[j - 1]);
-            }
-            if (own && q >= ys && q < ye) {
-                if (j == D - 1) st(out1, q, val);
+                if (j == D - 1) st2(ro1, q, val, mine);
                 if (j == D) {
-                    st(out2, q, val);
-                    st(acc, q, P[D - 1]);
+                    st2(ro2, q, val, mine);
+                    st2(racc, q, P[ps], mine);
                 }
             }
+            if (j < D) lv[j][sl0] = val;
         }
-        // partial-acc ring: P[j] = row r - j for the next iteration
-#pragma unroll
-        for (int j = D - 1; j > 0; --j) P[j] = P[j - 1];
-        a_m1 = a_0;
-        a_0 = a_p1;
     };
-    int32_t r = r0;
-    for (; r + 1 <= r1; r += 2) {
-        row_step(r, p0, p1);
-        row_step(r + 1, p1, p0);
-    }
-    if (r <= r1) row_step(r, p0, p1);
+    // iterations: level 1 from its first needed row to level D at the last
+    // row; whole unrolled bodies without tests, then the remainder
+    const int32_t T = nrows + 2 * (D - 1);
+    for (base = 0; base + U <= T; base += U) phases<0, U>(step, 0, U);
+    if (base < T) phases<0, U>(step, base, T);
 }
 
 }  // namespace chebtd

@@ -30,10 +30,18 @@ int pair_rows_for_width(int64_t W);
 bool pair_supported(const Ctx &c);
 // head: v1 = H~ vk, v2 = 2 H~ v1 - vk, acc = g0 vk + g1 v1 + g2 v2 (+ partials, ckpt)
 // else: v_{k+1} = 2 H~ vk - vkm1, v_{k+2} = 2 H~ v_{k+1} - vk, acc += g1 v_{k+1} + g2 v_{k+2}
-// D = 3 or 4 orders per pass (deep_walk.h): the same buffers and roles as
+// D = 3 .. 6 orders per pass (deep_walk.h): the same buffers and roles as
 // launch_pair, with the weights g_k .. g_{k+D} in g (g[0] used by the head)
 OpPair make_deep_op(const Ctx &c, int rows, int D);
 int64_t deep_grid_blocks(const Ctx &c, int rows, int D);
+
+// The deep kernel's 32-bit buffer offsets stay unambiguous for a W x L
+// lattice: rows from -(D+1) to W+D+1 at 16 B per site, plus the 2^31 bias of
+// lanes outside the lattice, never wrap into the buffer (D <= 6).
+inline bool deep_offsets_fit(int64_t W, int64_t L)
+{
+    return (W + 2 * 6 + 2) * L * 16 <= (int64_t(1) << 31);
+}
 hipError_t launch_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, const double2 *vkm1,
                        const double2 *vk, double2 *out1, double2 *out2, double2 *acc, const double2 *g,
                        double2 *ckpt, double *partials, const NeFinal *fin);

@@ -57,8 +57,18 @@ __global__ __launch_bounds__(256) void k_deep(OpPair op, const double2 *__restri
     const int32_t strip = gwv % op.nstrips;
     const int32_t chunk = gwv / op.nstrips;
     double nrm = 0.0, en = 0.0;
-    if (chunk < op.nchunks)  // uniform per wavefront
-        deep_walk<EDGE, D, HEAD>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
+    if (chunk < op.nchunks) {  // uniform per wavefront
+        // wavefronts whose 64 lanes lie on lattice columns and whose rows,
+        // halo included (ys - D .. ye + D - 1), lie inside the lattice skip
+        // the border tests
+        const int32_t x0 = strip * deep_strip(D) - (D - 1);
+        const int32_t ys = chunk * op.rows, ye = min(ys + op.rows, op.W);
+        if (x0 >= 0 && x0 + 63 < op.L && ys - D >= 0 && ye + D - 1 < op.W) {
+            deep_walk<EDGE, D, HEAD, false>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
+        } else {
+            deep_walk<EDGE, D, HEAD, true>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
+        }
+    }
     if (HEAD) {
         block_sum2(nrm, en, red);
         if (threadIdx.x == 0) {
@@ -161,7 +171,7 @@ hipError_t launch_deep_d(const Ctx &c, hipStream_t s, int rows, bool head, const
 {
     const OpPair op = make_deep_op(c, rows, D);
     const int64_t nb = deep_grid_blocks(c, rows, D);
-    if (nb <= 0 || nb > INT32_MAX) return hipErrorInvalidValue;
+    if (nb <= 0 || nb > INT32_MAX || !deep_offsets_fit(op.W, op.L)) return hipErrorInvalidValue;
     DeepWeights<D> gw;
     for (int j = 0; j <= D; ++j) gw.g[j] = g[j];
     NeFinal fin{};
@@ -190,7 +200,6 @@ hipError_t launch_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, 
                        double2 *ckpt, double *partials, const NeFinal *fin)
 {
     switch (D) {
-        case 2: return launch_deep_d<2>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
         case 3: return launch_deep_d<3>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
         case 4: return launch_deep_d<4>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);
         case 5: return launch_deep_d<5>(c, s, rows, head, vkm1, vk, out1, out2, acc, g, ckpt, partials, fin);

@@ -78,6 +78,31 @@ def test_batch_matches_oracle(torch, cheb, mode, tile, block, wg, graph):
         assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-10
 
 
+def single_system(torch, cheb, s, K, depth):
+    """One system through the single-system path; depth 2 keeps it on the
+    two-orders and one-order kernels the batch shares, None lets the plan
+    split the orders as it does by default."""
+    saved = os.environ.get("CHEBTD_DEPTH")
+    if depth is None:
+        os.environ.pop("CHEBTD_DEPTH", None)
+    else:
+        os.environ["CHEBTD_DEPTH"] = str(depth)
+    try:
+        one = cheb.Context()
+        one.honeycomb(s["width"], s["length"], s["eps"], edge=s["edge"])
+        one.set_bounds(s["emin"], s["emax"])
+        one.plan(1.0)
+    finally:
+        if saved is None:
+            os.environ.pop("CHEBTD_DEPTH", None)
+        else:
+            os.environ["CHEBTD_DEPTH"] = saved
+    p = torch.from_numpy(s["psi0"].copy()).cuda()
+    one.propagate(p, K)
+    torch.cuda.synchronize()
+    return p.cpu().numpy()
+
+
 def test_batch_equals_single_system_path_bitwise(torch, cheb):
     systems = make_systems(SMALL[:6], torch)
     ctx = cheb.Context()
@@ -86,14 +111,11 @@ def test_batch_equals_single_system_path_bitwise(torch, cheb):
     ctx.batch_propagate(4)
     torch.cuda.synchronize()
     for s in systems:
-        one = cheb.Context()
-        one.honeycomb(s["width"], s["length"], s["eps"], edge=s["edge"])
-        one.set_bounds(s["emin"], s["emax"])
-        one.plan(1.0)
-        p = torch.from_numpy(s["psi0"].copy()).cuda()
-        one.propagate(p, 4)
-        torch.cuda.synchronize()
-        np.testing.assert_array_equal(p.cpu().numpy(), s["psi"].cpu().numpy())
+        got = s["psi"].cpu().numpy()
+        np.testing.assert_array_equal(single_system(torch, cheb, s, 4, 2), got)
+        # the default split (deep passes) rounds in another order
+        ref = single_system(torch, cheb, s, 4, None)
+        assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
 
 
 def test_batch_autotune_restores_state_and_caches(torch, cheb, tmp_path):
@@ -138,14 +160,7 @@ def test_batch_pairs_equals_single_system_path_bitwise(torch, cheb, K):
     Ms = ctx.batch_info()
     assert any(M % 2 for M in Ms) and any(M % 2 == 0 for M in Ms)
     for s in systems:
-        one = cheb.Context()
-        one.honeycomb(s["width"], s["length"], s["eps"], edge=s["edge"])
-        one.set_bounds(s["emin"], s["emax"])
-        one.plan(1.0)
-        p = torch.from_numpy(s["psi0"].copy()).cuda()
-        one.propagate(p, K)
-        torch.cuda.synchronize()
-        np.testing.assert_array_equal(p.cpu().numpy(), s["psi"].cpu().numpy())
+        np.testing.assert_array_equal(single_system(torch, cheb, s, K, 2), s["psi"].cpu().numpy())
 
 
 def test_batch_pairs_needs_two_orders(torch, cheb):
