@@ -116,8 +116,10 @@ static bool large_lattice(const Ctx &c) { return c.n >= (int64_t(4) << 20); }
 
 // Rows per wavefront chunk of the D-orders kernel.  Level j of the walk also
 // computes D - j halo rows on each side of its chunk, so short chunks repeat
-// work; large lattices have wavefronts to spare and take 32 rows, small ones
-// 4 (8 for D = 6) to keep the chip busy.  CHEBTD_DEEP_ROWS overrides.
+// work; large lattices have wavefronts to spare and take about 32 rows,
+// small ones 4 to 8 to keep the chip busy.  Each height makes the walk's
+// rows + 2 (D - 1) iterations a whole number of unrolled 6-iteration bodies.
+// CHEBTD_DEEP_ROWS overrides.
 int choose_deep_rows(const Ctx &c, int D)
 {
     if (c.kind != HKind::Honeycomb) return 1;
@@ -125,7 +127,9 @@ int choose_deep_rows(const Ctx &c, int D)
         const int r = std::atoi(env);
         if (r >= 1) return r;
     }
-    const int r = large_lattice(c) ? 32 : (D >= 6 ? 8 : 4);
+    static const int small_rows[kMaxDepth + 1] = {0, 0, 0, 8, 6, 10, 14};
+    static const int large_rows[kMaxDepth + 1] = {0, 0, 0, 32, 30, 28, 32};
+    const int r = (large_lattice(c) ? large_rows : small_rows)[D];
     return (int)std::min<int64_t>(c.W, r);
 }
 
@@ -137,8 +141,8 @@ int choose_deep_rows(const Ctx &c, int D)
 // CHEBTD_DEPTH=D limits the passes to 1, 2 and D orders (2: pair kernel only).
 std::vector<int> plan_passes(const Ctx &c, int M)
 {
-    static const double small_cost[kMaxDepth + 1] = {0.0, 0.80, 1.0, 1.05, 1.14, 1.42, 1.37};
-    static const double large_cost[kMaxDepth + 1] = {0.0, 0.70, 1.0, 1.02, 1.05, 0.98, 1.10};
+    static const double small_cost[kMaxDepth + 1] = {0.0, 0.80, 1.0, 1.22, 1.30, 1.26, 1.40};
+    static const double large_cost[kMaxDepth + 1] = {0.0, 0.70, 1.0, 1.02, 1.08, 1.00, 1.09};
     static const double chain_cost[kMaxDepth + 1] = {0.0, 0.78, 1.0, 1.27, 2.0, 2.8, 3.6};
     const double *cost = c.kind != HKind::Honeycomb ? chain_cost : large_lattice(c) ? large_cost : small_cost;
     bool allowed[kMaxDepth + 1];

@@ -19,10 +19,10 @@
 //
 // Register rings without moves: the row a level writes at iteration i goes
 // to window slot i mod 3, the partial sum and the diagonal term of row r - t
-// sit in slot (i - t) mod D, and the operands loaded kDeepAhead iterations
-// ahead rotate through kDeepAhead + 1 sets.  The loop body is unrolled over
-// a common multiple of the ring sizes, so every slot index is a constant
-// and no value is copied between registers.
+// sit in slot (i - t) mod deep_ring(D), and the operands loaded kDeepAhead
+// iterations ahead rotate through kDeepAhead + 1 sets.  The loop body is
+// unrolled over a common multiple of the ring sizes, so every slot index is
+// a constant and no value is copied between registers.
 //
 // Memory goes through buffer loads and stores whose 32-bit offsets wrap:
 // rows above or below the lattice, columns outside it and lanes that own no
@@ -53,9 +53,19 @@ constexpr int deep_lcm(int a, int b) { return a / deep_gcd(a, b) * b; }
 // walks its rows one after another, so the loads of the next row alone
 // cannot cover the memory latency when few wavefronts share a SIMD.
 constexpr int kDeepAhead = 1;
+// Slots of the partial-sum and diagonal rings: at least D, and a divisor of
+// 6 so that the unrolled body stays 6 iterations long for every depth.
+constexpr int deep_ring(int D) { return 6 % D == 0 ? D : 6; }
 // iterations per unrolled loop body: a multiple of kDeepAhead + 1
-// (prefetch sets), 3 (row windows) and D (partial sums)
-constexpr int deep_unroll(int D) { return deep_lcm(deep_lcm(kDeepAhead + 1, 3), D); }
+// (prefetch sets), 3 (row windows) and the ring size
+constexpr int deep_unroll(int D) { return deep_lcm(deep_lcm(kDeepAhead + 1, 3), deep_ring(D)); }
+// Iterations a walk of `rows` rows runs: whole unrolled bodies covering the
+// rows + 2 (D - 1) it needs.  Chunk heights with rows + 2 (D - 1) a multiple
+// of the body waste none.
+constexpr int deep_iterations(int D, int rows)
+{
+    return (rows + 2 * (D - 1) + deep_unroll(D) - 1) / deep_unroll(D) * deep_unroll(D);
+}
 
 namespace deepdev {
 
@@ -84,13 +94,13 @@ __device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, do
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, (int)voff, (int)soff, 0);
 }
 
-// f(integral_constant<PH>) for PH = 0 .. U-1 while base + PH < T
+// f(integral_constant<PH>) for PH = 0 .. U-1
 template <int PH, int U, typename F>
-__device__ __forceinline__ void phases(F &f, int32_t base, int32_t T)
+__device__ __forceinline__ void phases(F &f)
 {
     if constexpr (PH < U) {
-        if (base + PH < T) f(std::integral_constant<int, PH>{});
-        phases<PH + 1, U>(f, base, T);
+        f(std::integral_constant<int, PH>{});
+        phases<PH + 1, U>(f);
     }
 }
 
@@ -158,27 +168,30 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
         const uint32_t ro = (uint32_t)row * row8;
         return BORDER ? bload1(rs, ro + lanepart, 0) : bload1(rs, lanepart, ro);
     };
-    // store to the own columns of `row` if `ok`; otherwise the store is
+    // Store to the own columns of `row` if `ok`; otherwise the store is
     // issued anyway, from out-of-range lanes, and dropped (a branch here
-    // would make every later wait drain all loads in flight)
+    // would make every later wait drain all loads in flight).  The whole
+    // offset goes in the lane's register and the scalar offset is 0: the
+    // compiler then keeps the store's data registers unwritten for the wait
+    // state that 128-bit stores need, which it assumes unnecessary when the
+    // scalar offset is a register.  With that form, data written right after
+    // the store intermittently reached memory in place of the stored values.
     auto st2 = [&](Rsrc rs, int32_t row, double2 v, bool ok) {
         const uint32_t ro = (uint32_t)row * row16;
-        const uint32_t lanepart = ok ? s16 : kOut;
-        if (BORDER)
-            bstore2(rs, ro + lanepart, 0, v);
-        else
-            bstore2(rs, lanepart, ro, v);
+        bstore2(rs, ro + (ok ? s16 : kOut), 0, v);
     };
 
     const int32_t r0 = ys - (D - 1);  // iteration i: level j at row r0 + i - (j-1)
     // windows of levels 0 .. D-1 (three rows each); partial sums and
-    // diagonal terms 2 (eps - b)/a of the last D rows
+    // diagonal terms 2 (eps - b)/a of the last RS rows
+    constexpr int RS = deep_ring(D);
     double2 lv[D][3];
-    double2 P[D];
-    double dd[D];
+    double2 P[RS];
+    double dd[RS];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        lv[j][0] = lv[j][1] = lv[j][2] = zero;
+    for (int j = 0; j < D; ++j) lv[j][0] = lv[j][1] = lv[j][2] = zero;
+#pragma unroll
+    for (int j = 0; j < RS; ++j) {
         P[j] = zero;
         dd[j] = 0.0;
     }
@@ -222,12 +235,12 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
         // operands kDeepAhead iterations on, into the set freed last iteration
         issue(pf[(ph + K - 1) % K], i + K - 1);
         lv[0][sl0] = cur.a;  // level 0, row rr+1
-        dd[ph % D] = op.s2 * (cur.e + op.dshift);
+        dd[ph % RS] = op.s2 * (cur.e + op.dshift);
 #pragma unroll
         for (int j = 1; j <= D; ++j) {
             const int32_t q = rr - (j - 1);
             const int32_t rel = i - (D - 1) - (j - 1);     // q - ys
-            const int ps = ((ph - (j - 1)) % D + D) % D;  // ring slot of row q
+            const int ps = ((ph - (j - 1)) % RS + RS) % RS;  // ring slot of row q
             // on the border a level outside its rows is zero
             const bool active =
                 !BORDER || (q >= max(ys - (D - j), 0) && q <= min(ys + nrows - 1 + (D - j), W - 1));
@@ -268,11 +281,12 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
             if (j < D) lv[j][sl0] = val;
         }
     };
-    // iterations: level 1 from its first needed row to level D at the last
-    // row; whole unrolled bodies without tests, then the remainder
+    // Iterations: level 1 from its first needed row until level D has
+    // passed the last row, in whole unrolled bodies without tests.  Those
+    // past the end compute only rows below the chunk (never stored); they
+    // read at most D + 1 rows past it, which the range check covers.
     const int32_t T = nrows + 2 * (D - 1);
-    for (base = 0; base + U <= T; base += U) phases<0, U>(step, 0, U);
-    if (base < T) phases<0, U>(step, base, T);
+    for (base = 0; base < T; base += U) phases<0, U>(step);
 }
 
 }  // namespace chebtd

@@ -58,12 +58,13 @@ __global__ __launch_bounds__(256) void k_deep(OpPair op, const double2 *__restri
     const int32_t chunk = gwv / op.nstrips;
     double nrm = 0.0, en = 0.0;
     if (chunk < op.nchunks) {  // uniform per wavefront
-        // wavefronts whose 64 lanes lie on lattice columns and whose rows,
-        // halo included (ys - D .. ye + D - 1), lie inside the lattice skip
-        // the border tests
+        // wavefronts whose 64 lanes lie on lattice columns and whose every
+        // row read (ys - D up to the rows below the chunk that the last
+        // unrolled body loads) lies inside the lattice skip the border tests
         const int32_t x0 = strip * deep_strip(D) - (D - 1);
         const int32_t ys = chunk * op.rows, ye = min(ys + op.rows, op.W);
-        if (x0 >= 0 && x0 + 63 < op.L && ys - D >= 0 && ye + D - 1 < op.W) {
+        const int32_t last = ys - (D - 1) + deep_iterations(D, ye - ys) + kDeepAhead;
+        if (x0 >= 0 && x0 + 63 < op.L && ys - D >= 0 && last < op.W) {
             deep_walk<EDGE, D, HEAD, false>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
         } else {
             deep_walk<EDGE, D, HEAD, true>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
