@@ -422,12 +422,13 @@ def bench_adjoint(torch, P, K):
         gbar2 = (2.0 * m * psi).contiguous()
         dV2 = torch.zeros_like(Vd)
         t_bwd2 = timed(torch, lambda: ctx.adjoint(gbar2, dV2))
-        same = bool(torch.equal(dV, dV2))
+        # the schedules group levels into passes differently: equal to rounding
+        sched_diff = float((dV - dV2).norm() / dV.norm()) if float(dV.norm()) > 0 else 0.0
         out[name] = dict(n=int(Vd.numel()), M=M, steps=K, forward_s=t_plain,
                          forward_with_checkpoints_s=t_fwd, backward_s=t_bwd,
                          backward_over_forward=t_bwd / t_plain,
                          backward_sqrtM_s=t_bwd2, backward_sqrtM_over_forward=t_bwd2 / t_plain,
-                         schedules_agree_bitwise=same,
+                         schedules_rel_diff=sched_diff,
                          transmission=float((m * psi.abs() ** 2).sum().item()))
         ctx.close()
     return out

@@ -338,7 +338,10 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode);
 
 /* After chebtd_propagate(..., K, ..., CHEBTD_KEEP_CHECKPOINTS): gbar_dev
  * (complex128[n]) holds dL/dpsi_K on entry and the adjoint of psi_0 on
- * return; dLdV_dev (float64[n]) is accumulated into (+=). */
+ * return; dLdV_dev (float64[n]) is accumulated into (+=).  On ribbons the
+ * reverse sweep runs several levels per pass over memory and CHEBTD_ADJ_STEP
+ * recomputes several orders per pass, so the two modes group the levels
+ * differently and agree to rounding, not bit for bit. */
 int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev);
 
 /* ======================================================================= */

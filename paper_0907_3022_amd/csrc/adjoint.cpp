@@ -6,7 +6,9 @@
 // (adjoint.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -94,18 +96,62 @@ struct URot {
     }
 };
 
+// Orders per recomputation pass (each order stored): 6 on ribbons where the
+// deep kernel's offsets fit, else 2 (a chain, one row, gains nothing from
+// deeper passes: measured on MI355X); CHEBTD_REC_DEPTH overrides.
+int rec_depth(const Ctx &c)
+{
+    int D = c.kind == HKind::Honeycomb ? 6 : 2;
+    if (const char *env = std::getenv("CHEBTD_REC_DEPTH")) D = std::max(2, std::min(kMaxDepth, std::atoi(env)));
+    if (!pair_supported(c)) return 1;
+    const OpPair op = make_pair_op(c, 1);
+    return deep_offsets_fit(op.W, op.L) ? D : 2;
+}
+
+// Adjoint levels per pass: 5 on ribbons, 2 on chains (measured on MI355X for
+// the 256 x 4096 ribbon and the 65536-site chain: 5 levels per pass cut the
+// ribbon's backward sweep from 151 to 94 ms, a chain only gets slower),
+// limited by the lattice's offsets; CHEBTD_ADJ_DEPTH (2 .. 6) overrides.
+int adj_depth(const Ctx &c)
+{
+    int D = c.kind == HKind::Honeycomb ? 5 : 2;
+    if (const char *env = std::getenv("CHEBTD_ADJ_DEPTH")) D = std::max(2, std::min(kMaxDepth, std::atoi(env)));
+    if (!pair_supported(c)) return 1;
+    while (D > 2 && !adj_deep_fits(c, D)) --D;
+    return D;
+}
+
 // Reverse sweep of one step for levels k = kend-1 .. kbeg, with the forward
-// vectors v_k available as vk(k).  Levels k, k-1 >= 1 go two per pass on
-// chains and ribbons (pair_supported); a level left alone writes u_k over
-// u_{k+2} (own site only); level 0 writes u_0 over gbar.
+// vectors v_k available as vk(k).  Levels k .. k-D+1 >= 1 go D per pass on
+// chains and ribbons where their forward vectors are stored n apart, else
+// two per pass (pair_supported); a level left alone writes u_k over u_{k+2}
+// (own site only); level 0 writes u_0 over gbar.
 template <class VK>
 hipError_t sweep_levels(Ctx *c, hipStream_t s, int kbeg, int kend, VK vk, double2 *gbar, double *grad, URot &u)
 {
     const bool pairs = pair_supported(*c);
+    const int D = adj_depth(*c);
+    const int64_t n = c->n;
+    auto spaced = [&](int lo, int hi) {  // v_lo .. v_hi stored n apart
+        for (int k = lo + 1; k <= hi; ++k)
+            if (vk(k) != vk(lo) + (k - lo) * n) return false;
+        return true;
+    };
     hipError_t e = hipSuccess;
     int k = kend - 1;
     while (k >= kbeg && e == hipSuccess) {
-        if (pairs && k - 1 >= std::max(kbeg, 1)) {
+        if (D > 2 && k - D + 1 >= std::max(kbeg, 1) && spaced(k - D + 1, k)) {
+            double2 *o1, *o2;
+            u.spare(&o1, &o2);
+            double2 cw[kMaxDepth];
+            for (int j = 1; j <= D; ++j) cw[j - 1] = conj_weight(c, k - j + 1);
+            e = launch_adj_deep(*c, s, D, c->deep_rows[D], u.has2 ? u.uk2 : nullptr, u.uk1, o1, o2, gbar, grad,
+                                vk(k - D + 1), cw);
+            u.uk2 = o1;  // u_{k-D+2}
+            u.uk1 = o2;  // u_{k-D+1}
+            u.has2 = true;
+            k -= D;
+        } else if (pairs && k - 1 >= std::max(kbeg, 1)) {
             double2 *o1, *o2;
             u.spare(&o1, &o2);
             e = launch_adj_pair(*c, s, u.has2, u.uk2, u.uk1, o1, o2, gbar, vk(k), vk(k - 1), conj_weight(c, k),
@@ -208,7 +254,20 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
             // v_0 = psi_s (the checkpoint itself), v_1 .. v_M into the buffer
             auto vk = [&](int k) -> double2 * { return k == 0 ? psi_s : vb + (size_t)k * n; };
             int k = 0;  // v_0 .. v_k are known
-            if (pairs_on && M - 1 >= 2) {
+            const int DR = rec_depth(*c);
+            if (DR > 2 && M - 1 >= DR) {
+                // D orders per pass, every one stored
+                double2 *all[kMaxDepth];
+                for (int j = 0; j < DR; ++j) all[j] = vk(j + 1);
+                e = launch_recompute_deep(*c, s, DR, c->deep_rows[DR], true, nullptr, psi_s, all);
+                k = DR;
+                for (; k + DR <= M - 1 && e == hipSuccess; k += DR) {
+                    for (int j = 0; j < DR; ++j) all[j] = vk(k + j + 1);
+                    e = launch_recompute_deep(*c, s, DR, c->deep_rows[DR], false, vk(k - 1), vk(k), all);
+                }
+                for (; k + 2 <= M - 1 && e == hipSuccess; k += 2)
+                    e = launch_recompute_pair(*c, s, false, vk(k - 1), vk(k), vk(k + 1), vk(k + 2));
+            } else if (pairs_on && M - 1 >= 2) {
                 e = launch_recompute_pair(*c, s, true, nullptr, psi_s, vk(1), vk(2));
                 k = 2;
                 for (; k + 2 <= M - 1 && e == hipSuccess; k += 2)

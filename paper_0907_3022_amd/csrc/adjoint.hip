@@ -13,6 +13,7 @@
 
 #include "device_ops.h"
 #include "internal.h"
+#include "deep_walk.h"
 #include "pair.h"
 #include "pair_walk.h"
 
@@ -338,6 +339,115 @@ hipError_t launch_adj_level(const Ctx &c, hipStream_t s, const double2 *u1, doub
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// D levels (orders) per pass: the deep walk of deep_walk.h in its
+// recomputation and adjoint modes.
+// ---------------------------------------------------------------------------
+
+// Forward vectors, each level stored: head v_1 .. v_D from psi; else
+// v_{k+1} .. v_{k+D} from (v_{k-1}, v_k).
+template <int EDGE, int D, bool HEAD>
+__global__ __launch_bounds__(256) void k_recompute_deep(OpPair op, DeepArgs<D> args)
+{
+    double nrm = 0.0, en = 0.0;
+    deep_dispatch<EDGE, D, HEAD, kDeepAll>(op, args, nrm, en);
+}
+
+// Reverse levels k .. k-D+1 (all >= 1) from (u_{k+2}, u_{k+1}), writing
+// u_{k-D+2}, u_{k-D+1} and adding the levels' shares to dL/dV.
+template <int EDGE, int D>
+__global__ __launch_bounds__(256) void k_adj_deep(OpPair op, DeepArgs<D> args)
+{
+    double nrm = 0.0, en = 0.0;
+    deep_dispatch<EDGE, D, false, kDeepAdj>(op, args, nrm, en);
+}
+
+namespace {
+
+template <int D>
+hipError_t launch_recompute_deep_d(const Ctx &c, hipStream_t s, int rows, bool head, const double2 *vkm1,
+                                   const double2 *vk, double2 *const *all)
+{
+    const OpPair op = make_deep_op(c, rows, D);
+    const int64_t nb = deep_grid_blocks(c, rows, D);
+    if (nb <= 0 || nb > INT32_MAX || !deep_offsets_fit(op.W, op.L)) return hipErrorInvalidValue;
+    DeepArgs<D> A{};
+    A.vkm1 = vkm1;
+    A.vk = vk;
+    for (int j = 0; j < D; ++j) A.all[j] = all[j];
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    if (head && zig)
+        hipLaunchKernelGGL((k_recompute_deep<CHEBTD_ZIGZAG, D, true>), grid, block, 0, s, op, A);
+    else if (head)
+        hipLaunchKernelGGL((k_recompute_deep<CHEBTD_ARMCHAIR, D, true>), grid, block, 0, s, op, A);
+    else if (zig)
+        hipLaunchKernelGGL((k_recompute_deep<CHEBTD_ZIGZAG, D, false>), grid, block, 0, s, op, A);
+    else
+        hipLaunchKernelGGL((k_recompute_deep<CHEBTD_ARMCHAIR, D, false>), grid, block, 0, s, op, A);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_adj_deep_d(const Ctx &c, hipStream_t s, int rows, const double2 *uk2, const double2 *uk1,
+                             double2 *out1, double2 *out2, const double2 *gbar, double *grad,
+                             const double2 *fwd, const double2 *cw)
+{
+    const OpPair op = make_deep_op(c, rows, D);
+    const int64_t nb = deep_grid_blocks(c, rows, D);
+    if (nb <= 0 || nb > INT32_MAX || !adj_deep_fits(c, D)) return hipErrorInvalidValue;
+    DeepArgs<D> A{};
+    A.vkm1 = uk2;
+    A.vk = uk1;
+    A.out1 = out1;
+    A.out2 = out2;
+    A.gbar = gbar;
+    A.grad = grad;
+    A.gf = 2.0 / c.a;
+    A.fwd = fwd;
+    for (int j = 0; j < D; ++j) A.w.g[j + 1] = cw[j];
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    if (zig)
+        hipLaunchKernelGGL((k_adj_deep<CHEBTD_ZIGZAG, D>), grid, block, 0, s, op, A);
+    else
+        hipLaunchKernelGGL((k_adj_deep<CHEBTD_ARMCHAIR, D>), grid, block, 0, s, op, A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_recompute_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, const double2 *vkm1,
+                                 const double2 *vk, double2 *const *all)
+{
+    switch (D) {
+        case 3: return launch_recompute_deep_d<3>(c, s, rows, head, vkm1, vk, all);
+        case 4: return launch_recompute_deep_d<4>(c, s, rows, head, vkm1, vk, all);
+        case 5: return launch_recompute_deep_d<5>(c, s, rows, head, vkm1, vk, all);
+        case 6: return launch_recompute_deep_d<6>(c, s, rows, head, vkm1, vk, all);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool adj_deep_fits(const Ctx &c, int D)
+{
+    const OpPair op = make_pair_op(c, 1);
+    return deep_offsets_fit(op.W, op.L) && (int64_t)D * op.W * op.L * 16 <= (int64_t(1) << 30);
+}
+
+hipError_t launch_adj_deep(const Ctx &c, hipStream_t s, int D, int rows, const double2 *uk2, const double2 *uk1,
+                           double2 *out1, double2 *out2, const double2 *gbar, double *grad,
+                           const double2 *fwd, const double2 *cw)
+{
+    switch (D) {
+        case 3: return launch_adj_deep_d<3>(c, s, rows, uk2, uk1, out1, out2, gbar, grad, fwd, cw);
+        case 4: return launch_adj_deep_d<4>(c, s, rows, uk2, uk1, out1, out2, gbar, grad, fwd, cw);
+        case 5: return launch_adj_deep_d<5>(c, s, rows, uk2, uk1, out1, out2, gbar, grad, fwd, cw);
+        case 6: return launch_adj_deep_d<6>(c, s, rows, uk2, uk1, out1, out2, gbar, grad, fwd, cw);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace chebtd

@@ -24,6 +24,14 @@
 // unrolled over a common multiple of the ring sizes, so every slot index is
 // a constant and no value is copied between registers.
 //
+// The same walk serves three uses (MODE): the propagation step above; the
+// recomputation of a step's Chebyshev vectors for the adjoint, each level
+// stored to its own vector and nothing accumulated; and the adjoint's reverse
+// recursion, level j forming
+//   u_{k-j+1} = conj(g_{k-j+1}) gbar + 2 H~ u_{k-j+2} - u_{k-j+3}
+// from u_{k+1} (level 0) and u_{k+2}, while dL/dV of a row collects
+// (2/a) Re[conj(u_{k-j+2}) v_{k-j+1}] from every level in a ring like acc's.
+//
 // Memory goes through buffer loads and stores whose 32-bit offsets wrap:
 // rows above or below the lattice, columns outside it and lanes that own no
 // column get offsets at or past the buffer's size, which the hardware's
@@ -44,6 +52,27 @@ namespace chebtd {
 template <int D>
 struct DeepWeights {
     double2 g[D + 1];  // g_{k}, g_{k+1} .. g_{k+D} (g_k only used by the head: gamma_0)
+};
+
+constexpr int kDeepProp = 0;  // propagation: acc += sum_j g_{k+j} v_{k+j}
+constexpr int kDeepAll = 1;   // recomputation: level j stored to all[j-1]
+constexpr int kDeepAdj = 2;   // adjoint levels and dL/dV
+
+// Operands of one pass.  vkm1, vk: the two vectors entering level 1 (the
+// adjoint's u_{k+2}, u_{k+1}; vkm1 may be null for the head, or for the
+// adjoint's first pass, where u_{k+2} = 0); out1, out2: levels D-1 and D.
+template <int D>
+struct DeepArgs {
+    const double2 *vkm1, *vk;
+    double2 *out1, *out2;
+    double2 *acc;            // propagation: read (not by the head) and written
+    double2 *ckpt;           // propagation head: a copy of psi, or null
+    double2 *all[D];         // recomputation: level j's vector
+    const double2 *gbar;     // adjoint: dL/dpsi* of the step's result
+    double *grad;            // adjoint: dL/dV, read and written
+    const double2 *fwd;      // adjoint: v_{k-D+1}; level j's v_{k-j+1} lies (D-j) n after it
+    double gf;               // adjoint: 2/a
+    DeepWeights<D> w;        // propagation g_k .. g_{k+D}; adjoint conj(g_{k-j+1}) in w.g[j]
 };
 
 constexpr int deep_strip(int D) { return 66 - 2 * D; }
@@ -93,6 +122,19 @@ __device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, do
     using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, (int)voff, (int)soff, 0);
 }
+__device__ __forceinline__ void bstore1(Rsrc r, uint32_t voff, uint32_t soff, double v)
+{
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)voff, (int)soff, 0);
+}
+
+// Operands of row rn loaded ahead: v_k of row rn+1 (the next level-0 row),
+// and v_{k-1}, the on-site term, the outside value and acc (adjoint: gbar
+// and dL/dV) of row rn.
+struct DeepPrefetch {
+    double2 a, km1, ext, acc;
+    double e, gr;
+};
 
 // f(integral_constant<PH>) for PH = 0 .. U-1
 template <int PH, int U, typename F>
@@ -113,14 +155,14 @@ __device__ __forceinline__ void phases(F &f)
 // is limited to its rows and masked to the lattice's columns.  Elsewhere a
 // level also computes the rows before its first needed one; those only feed
 // other such rows and are never stored.
-template <int EDGE, int D, bool HEAD, bool BORDER>
-__device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32_t chunk,
-                                          const double2 *__restrict__ vkm1, const double2 *__restrict__ vk,
-                                          double2 *__restrict__ out1, double2 *__restrict__ out2,
-                                          double2 *__restrict__ acc, const DeepWeights<D> &gw,
-                                          double2 *__restrict__ ckpt, double &nrm, double &en)
+template <int EDGE, int D, bool HEAD, bool BORDER, int MODE>
+__device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32_t chunk, const DeepArgs<D> &A,
+                                          double &nrm, double &en)
 {
     static_assert(D >= 2 && D <= 6, "depth");
+    static_assert(MODE == kDeepProp || !HEAD || MODE == kDeepAll, "the adjoint has no head pass");
+    constexpr bool PROP = MODE == kDeepProp, ALL = MODE == kDeepAll, ADJ = MODE == kDeepAdj;
+    const DeepWeights<D> &gw = A.w;
     using namespace pairdev;
     using namespace deepdev;
     constexpr int S = deep_strip(D);
@@ -135,10 +177,18 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     const int32_t nrows = min(op.rows, W - ys);  // rows of the chunk
 
     const uint32_t nb16 = (uint32_t)W * (uint32_t)L * 16u;
-    const Rsrc rk = rsrc(vk, nb16), ron = rsrc(op.onsite, nb16 / 2);
-    const Rsrc rkm1 = rsrc(HEAD ? vk : vkm1, nb16), racc = rsrc(acc, nb16);
-    // without a checkpoint buffer its descriptor has size 0 and drops every store
-    const Rsrc ro1 = rsrc(out1, nb16), ro2 = rsrc(out2, nb16), rck = rsrc(ckpt ? ckpt : acc, ckpt ? nb16 : 0u);
+    // A missing buffer gets a descriptor of size 0: its loads read zeros and
+    // its stores are dropped.
+    auto rsrc_or_0 = [&](const void *p, uint32_t bytes) { return rsrc(p ? p : A.vk, p ? bytes : 0u); };
+    const Rsrc rk = rsrc(A.vk, nb16), ron = rsrc(op.onsite, nb16 / 2);
+    const Rsrc rkm1 = rsrc_or_0(HEAD ? nullptr : A.vkm1, nb16);
+    const Rsrc ro1 = rsrc_or_0(ALL ? nullptr : A.out1, nb16), ro2 = rsrc_or_0(ALL ? nullptr : A.out2, nb16);
+    const Rsrc racc = rsrc_or_0(PROP ? A.acc : ADJ ? A.gbar : nullptr, nb16);
+    const Rsrc rck = rsrc_or_0(PROP && HEAD ? A.ckpt : nullptr, nb16);
+    const Rsrc rgr = rsrc_or_0(ADJ ? A.grad : nullptr, nb16 / 2);
+    // the adjoint's D forward vectors, n apart (D n 16 B <= 2^30, so the
+    // out-of-range bias never wraps into them)
+    const Rsrc rfw = rsrc_or_0(ADJ ? A.fwd : nullptr, (uint32_t)D * nb16);
     // column part of each offset: loads (lattice columns), stores (own
     // columns), the outside value (lanes 0 and 63); kOut elsewhere
     const uint32_t c16 = colok ? (uint32_t)x * 16u : kOut;
@@ -180,19 +230,26 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
         const uint32_t ro = (uint32_t)row * row16;
         bstore2(rs, ro + (ok ? s16 : kOut), 0, v);
     };
+    const uint32_t s8 = own ? (uint32_t)x * 8u : kOut;
+    auto st1 = [&](Rsrc rs, int32_t row, double v, bool ok) {
+        const uint32_t ro = (uint32_t)row * row8;
+        bstore1(rs, ro + (ok ? s8 : kOut), 0, v);
+    };
 
     const int32_t r0 = ys - (D - 1);  // iteration i: level j at row r0 + i - (j-1)
     // windows of levels 0 .. D-1 (three rows each); partial sums and
     // diagonal terms 2 (eps - b)/a of the last RS rows
     constexpr int RS = deep_ring(D);
     double2 lv[D][3];
-    double2 P[RS];
+    double2 P[RS];   // propagation: partial acc; adjoint: gbar of the row
+    double G[RS];    // adjoint: partial dL/dV
     double dd[RS];
 #pragma unroll
     for (int j = 0; j < D; ++j) lv[j][0] = lv[j][1] = lv[j][2] = zero;
 #pragma unroll
     for (int j = 0; j < RS; ++j) {
         P[j] = zero;
+        G[j] = 0.0;
         dd[j] = 0.0;
     }
     // iteration 0 reads level-0 rows r0-1 (slot 1) and r0 (slot 2)
@@ -201,21 +258,27 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     // operands of iteration n (pair_walk.h's set: v_k of the row below, and
     // v_{k-1}, on-site term, outside value and acc of row r0 + n)
     constexpr int K = kDeepAhead + 1;
-    pairdev::Prefetch pf[K];
-    auto issue = [&](pairdev::Prefetch &nx, int32_t n) {
+    DeepPrefetch pf[K];
+    auto issue = [&](DeepPrefetch &nx, int32_t n) {
         const int32_t rn = r0 + n;
         nx.a = ld2(rk, c16, rn + 1);
         if (!HEAD) nx.km1 = ld2(rkm1, c16, rn);
         nx.e = ld1(ron, c8, rn);
         nx.ext = ld2(rk, ext_off(rn), rn);
-        // acc only where it is stored again (other rows' sums are discarded)
+        // acc and dL/dV only where they are stored again (other rows' sums
+        // are discarded); the adjoint's gbar on every row a level computes
         const int32_t rel = n - (D - 1);
         const bool ok = rel >= 0 && rel < nrows;
-        if (!HEAD) nx.acc = ld2(racc, ok ? s16 : kOut, rn);
+        if (PROP && !HEAD) nx.acc = ld2(racc, ok ? s16 : kOut, rn);
+        if (ADJ) {
+            nx.acc = ld2(racc, c16, rn);
+            nx.gr = ld1(rgr, ok ? s8 : kOut, rn);
+        }
     };
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         pf[k].km1 = pf[k].acc = zero;
+        pf[k].gr = 0.0;
         if (k < K - 1) issue(pf[k], k);
     }
 
@@ -229,13 +292,29 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     auto step = [&](auto phc) {
         constexpr int ph = decltype(phc)::value;
         constexpr int sl0 = ph % 3, sl1 = (ph + 2) % 3, sl2 = (ph + 1) % 3;  // iterations i, i-1, i-2
-        pairdev::Prefetch &cur = pf[ph % K];
+        DeepPrefetch &cur = pf[ph % K];
         const int32_t i = base + ph;
         const int32_t rr = r0 + i;
-        // operands kDeepAhead iterations on, into the set freed last iteration
+        // operands kDeepAhead iterations on, into the set freed last iteration;
+        // the barrier keeps the scheduler from sinking these loads towards
+        // their use in the next iteration (which it does to save registers)
         issue(pf[(ph + K - 1) % K], i + K - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        // adjoint: the forward vectors of this iteration's rows, used after
+        // the levels (own columns of chunk rows only)
+        double2 fv[ADJ ? D : 1];
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int j = 1; j <= D; ++j) {
+                const int32_t rel = i - (D - 1) - (j - 1);
+                const uint32_t lanepart = rel >= 0 && rel < nrows ? s16 : kOut;
+                const uint32_t ro = (uint32_t)(rr - (j - 1)) * row16 + (uint32_t)(D - j) * nb16;
+                fv[j - 1] = BORDER ? bload2(rfw, ro + lanepart, 0) : bload2(rfw, lanepart, ro);
+            }
+        }
         lv[0][sl0] = cur.a;  // level 0, row rr+1
         dd[ph % RS] = op.s2 * (cur.e + op.dshift);
+        if (ADJ) P[ph % RS] = cur.acc;  // gbar of row rr
 #pragma unroll
         for (int j = 1; j <= D; ++j) {
             const int32_t q = rr - (j - 1);
@@ -257,28 +336,46 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
                     val = make_double2(fma(d, c.x, fma(op.off2, s.x, -prev.x)),
                                        fma(d, c.y, fma(op.off2, s.y, -prev.y)));
                 }
+                if (ADJ) val = cfma(gw.g[j], P[ps], val);
                 if (BORDER) val = csel(colok && active, val, zero);
                 const bool mine = rel >= 0 && rel < nrows;  // a row of the chunk
-                if (j == 1) {
-                    if (HEAD) {
-                        P[ps] = cfma(gw.g[1], val, cfma(gw.g[0], c, zero));
-                        st2(rck, q, c, mine);
-                        const bool sum = own && mine;
-                        nrm += sum ? c.x * c.x + c.y * c.y : 0.0;
-                        en += sum ? c.x * val.x + c.y * val.y : 0.0;
+                if (PROP) {
+                    if (j == 1) {
+                        if (HEAD) {
+                            P[ps] = cfma(gw.g[1], val, cfma(gw.g[0], c, zero));
+                            st2(rck, q, c, mine);
+                            const bool sum = own && mine;
+                            nrm += sum ? c.x * c.x + c.y * c.y : 0.0;
+                            en += sum ? c.x * val.x + c.y * val.y : 0.0;
+                        } else {
+                            P[ps] = cfma(gw.g[1], val, cur.acc);
+                        }
                     } else {
-                        P[ps] = cfma(gw.g[1], val, cur.acc);
+                        P[ps] = cfma(gw.g[j], val, P[ps]);
                     }
-                } else {
-                    P[ps] = cfma(gw.g[j], val, P[ps]);
                 }
-                if (j == D - 1) st2(ro1, q, val, mine);
-                if (j == D) {
+                if (ALL) st2(rsrc(A.all[j - 1], nb16), q, val, mine);
+                if (!ALL && j == D - 1) st2(ro1, q, val, mine);
+                if (!ALL && j == D) {
                     st2(ro2, q, val, mine);
-                    st2(racc, q, P[ps], mine);
+                    if (PROP) st2(racc, q, P[ps], mine);
                 }
             }
             if (j < D) lv[j][sl0] = val;
+        }
+        if constexpr (ADJ) {
+            // dL/dV of row rr - (j-1): level j's share, from the centre of
+            // level j-1's window (u_{k-j+2}, before this iteration moved it)
+            // and v_{k-j+1}; levels in order, as single-level passes add them
+#pragma unroll
+            for (int j = 1; j <= D; ++j) {
+                const int32_t rel = i - (D - 1) - (j - 1);
+                const int ps = ((ph - (j - 1)) % RS + RS) % RS;
+                const double2 c = lv[j - 1][sl1];
+                const double t = c.x * fv[j - 1].x + c.y * fv[j - 1].y;
+                G[ps] = (j == 1 ? cur.gr : G[ps]) + A.gf * t;
+                if (j == D) st1(rgr, rr - (D - 1), G[ps], rel >= 0 && rel < nrows);
+            }
         }
     };
     // Iterations: level 1 from its first needed row until level D has
@@ -287,6 +384,27 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     // read at most D + 1 rows past it, which the range check covers.
     const int32_t T = nrows + 2 * (D - 1);
     for (base = 0; base < T; base += U) phases<0, U>(step);
+}
+
+// One wavefront per (strip, chunk) of a 256-thread block: wavefronts whose
+// 64 lanes lie on lattice columns and whose every row read (ys - D up to the
+// rows below the chunk that the last unrolled body loads) lies inside the
+// lattice skip the border tests.
+template <int EDGE, int D, bool HEAD, int MODE>
+__device__ __forceinline__ void deep_dispatch(const OpPair &op, const DeepArgs<D> &A, double &nrm, double &en)
+{
+    const int32_t gwv =
+        __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
+    const int32_t strip = gwv % op.nstrips;
+    const int32_t chunk = gwv / op.nstrips;
+    if (chunk >= op.nchunks) return;  // uniform per wavefront
+    const int32_t x0 = strip * deep_strip(D) - (D - 1);
+    const int32_t ys = chunk * op.rows, ye = min(ys + op.rows, op.W);
+    const int32_t last = ys - (D - 1) + deep_iterations(D, ye - ys) + kDeepAhead;
+    if (x0 >= 0 && x0 + 63 < op.L && ys - D >= 0 && last < op.W)
+        deep_walk<EDGE, D, HEAD, false, MODE>(op, strip, chunk, A, nrm, en);
+    else
+        deep_walk<EDGE, D, HEAD, true, MODE>(op, strip, chunk, A, nrm, en);
 }
 
 }  // namespace chebtd

@@ -220,6 +220,18 @@ hipError_t launch_adj_pair(const Ctx &c, hipStream_t s, bool has_u2, const doubl
                            double2 *out1, double2 *out2, const double2 *gbar, const double2 *vk,
                            const double2 *vkm1, double2 cg1, double2 cg2, double *grad);
 hipError_t launch_adj_init(hipStream_t s, const double2 *gbar, double2 g, double2 *u, int64_t n);
+// D = 3 .. 6 levels per pass (deep walk): recomputation storing v_{k+1} ..
+// v_{k+D} to all[0 .. D-1] (head: v_1 .. v_D from psi = vk); adjoint levels
+// k .. k-D+1 >= 1 from (u_{k+2} = uk2, may be null; u_{k+1} = uk1) into
+// out1 = u_{k-D+2}, out2 = u_{k-D+1}, with the forward vectors v_{k-D+1} ..
+// v_k stored n apart from fwd = v_{k-D+1} and cw[j-1] = conj(g_{k-j+1});
+// adj_deep_fits tells whether the lattice allows D adjoint levels per pass.
+hipError_t launch_recompute_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, const double2 *vkm1,
+                                 const double2 *vk, double2 *const *all);
+bool adj_deep_fits(const Ctx &c, int D);
+hipError_t launch_adj_deep(const Ctx &c, hipStream_t s, int D, int rows, const double2 *uk2, const double2 *uk1,
+                           double2 *out1, double2 *out2, const double2 *gbar, double *grad, const double2 *fwd,
+                           const double2 *cw);
 hipError_t launch_adj_level(const Ctx &c, hipStream_t s, const double2 *u1, double2 *u2_in,
                             const double2 *gbar_in, double2 *out, const double2 *vk, double2 gk,
                             double gscale, int has_u2, double *grad);

@@ -44,32 +44,12 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
 }
 
 template <int EDGE, int D, bool HEAD>
-__global__ __launch_bounds__(256) void k_deep(OpPair op, const double2 *__restrict__ vkm1,
-                                              const double2 *__restrict__ vk, double2 *__restrict__ out1,
-                                              double2 *__restrict__ out2, double2 *__restrict__ acc,
-                                              DeepWeights<D> gw, double2 *__restrict__ ckpt, double *partials,
-                                              NeFinal fin)
+__global__ __launch_bounds__(256) void k_deep(OpPair op, DeepArgs<D> args, double *partials, NeFinal fin)
 {
     __shared__ double red[2 * 4];
     if (!HEAD && fin.partials && blockIdx.x == 0) finalize_ne_block(fin, nullptr, red);
-    const int32_t gwv =
-        __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
-    const int32_t strip = gwv % op.nstrips;
-    const int32_t chunk = gwv / op.nstrips;
     double nrm = 0.0, en = 0.0;
-    if (chunk < op.nchunks) {  // uniform per wavefront
-        // wavefronts whose 64 lanes lie on lattice columns and whose every
-        // row read (ys - D up to the rows below the chunk that the last
-        // unrolled body loads) lies inside the lattice skip the border tests
-        const int32_t x0 = strip * deep_strip(D) - (D - 1);
-        const int32_t ys = chunk * op.rows, ye = min(ys + op.rows, op.W);
-        const int32_t last = ys - (D - 1) + deep_iterations(D, ye - ys) + kDeepAhead;
-        if (x0 >= 0 && x0 + 63 < op.L && ys - D >= 0 && last < op.W) {
-            deep_walk<EDGE, D, HEAD, false>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
-        } else {
-            deep_walk<EDGE, D, HEAD, true>(op, strip, chunk, vkm1, vk, out1, out2, acc, gw, ckpt, nrm, en);
-        }
-    }
+    deep_dispatch<EDGE, D, HEAD, kDeepProp>(op, args, nrm, en);
     if (HEAD) {
         block_sum2(nrm, en, red);
         if (threadIdx.x == 0) {
@@ -173,24 +153,26 @@ hipError_t launch_deep_d(const Ctx &c, hipStream_t s, int rows, bool head, const
     const OpPair op = make_deep_op(c, rows, D);
     const int64_t nb = deep_grid_blocks(c, rows, D);
     if (nb <= 0 || nb > INT32_MAX || !deep_offsets_fit(op.W, op.L)) return hipErrorInvalidValue;
-    DeepWeights<D> gw;
-    for (int j = 0; j <= D; ++j) gw.g[j] = g[j];
+    DeepArgs<D> A{};
+    A.vkm1 = vkm1;
+    A.vk = vk;
+    A.out1 = out1;
+    A.out2 = out2;
+    A.acc = acc;
+    A.ckpt = ckpt;
+    for (int j = 0; j <= D; ++j) A.w.g[j] = g[j];
     NeFinal fin{};
     if (fin_in && !head) fin = *fin_in;
     const dim3 grid((unsigned)nb), block(256);
     const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
     if (head && zig)
-        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, gw,
-                           ckpt, partials, fin);
+        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, true>), grid, block, 0, s, op, A, partials, fin);
     else if (head)
-        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, true>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, gw,
-                           ckpt, partials, fin);
+        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, true>), grid, block, 0, s, op, A, partials, fin);
     else if (zig)
-        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc, gw,
-                           ckpt, partials, fin);
+        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, false>), grid, block, 0, s, op, A, partials, fin);
     else
-        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, false>), grid, block, 0, s, op, vkm1, vk, out1, out2, acc,
-                           gw, ckpt, partials, fin);
+        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, false>), grid, block, 0, s, op, A, partials, fin);
     return hipGetLastError();
 }
 
