@@ -365,11 +365,18 @@ def bench_batched(torch, P, K, seq_steps=10):
     ctx.close()
     batched_rate = site_orders * K / t
     seq_rate = site_orders * seq_steps / seq_t
-    mode = ["levels", "persistent", "pairs"][best[0]]
-    # algorithmic bytes of one step: 88 per site and order, or for the pairs
-    # schedule 104 per site and pass of two orders plus 88 for an odd tail
-    if mode == "pairs":
-        step_bytes = sum(s["width"] * s["length"] * (PAIR_BYTES * (int(M) // 2) + STENCIL_BYTES * (int(M) % 2))
+    mode = ["levels", "persistent", "pairs", "deep"][best[0]]
+    # algorithmic bytes of one step: 88 per site and order, or 104 per site
+    # and multi-order pass plus 88 for an odd tail (the deep schedule: M //
+    # depth passes of `depth` orders per system, then pairs)
+    if mode in ("pairs", "deep"):
+        depth = int(os.environ.get("CHEBTD_BATCH_DEPTH", "5")) if mode == "deep" else 2
+
+        def passes(M):
+            nd = M // depth if mode == "deep" else 0
+            rest = M - nd * depth
+            return nd + rest // 2, rest % 2
+        step_bytes = sum(s["width"] * s["length"] * (PAIR_BYTES * passes(int(M))[0] + STENCIL_BYTES * passes(int(M))[1])
                          for s, M in zip(systems, Ms))
     else:
         step_bytes = STENCIL_BYTES * site_orders

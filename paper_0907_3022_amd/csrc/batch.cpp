@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -44,6 +45,15 @@ struct BatchState {
     std::vector<int64_t> pair_level_blocks;
     DevBuf pblk_sys, pblk_wave0, tblk_sys, tblk_tile;
     int64_t ntail_blocks = 0;
+    // deep schedule: each system takes M / deep_D passes of deep_D orders
+    // (pass p runs the systems with more than p of them: a prefix of
+    // `order`), then two-order passes while it has two or more orders left
+    // (explicit block lists, concatenated), then the tail if one is left
+    bool deep_ok = false;
+    int deep_D = 5;
+    std::vector<int64_t> deep_pass_blocks, deep_pair_off;
+    DevBuf dblk_sys, dblk_wave0, dpblk_sys, dpblk_wave0, dtblk_sys, dtblk_tile;
+    int64_t ndtail_blocks = 0;
     DevBuf head, done, flag;
     int64_t spin_limit = 0;  // wall-clock ticks a dependency wait may take
     hipGraphExec_t graph = nullptr;
@@ -64,7 +74,8 @@ void batch_destroy(Ctx *c)
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (DevBuf *d : {&b->sys_dev, &b->gamma_dev, &b->work, &b->blk_sys, &b->blk_tile, &b->q_level_off,
                       &b->q_level_active, &b->q_tile_prefix, &b->q_order, &b->pblk_sys, &b->pblk_wave0,
-                      &b->tblk_sys, &b->tblk_tile, &b->head, &b->done, &b->flag})
+                      &b->tblk_sys, &b->tblk_tile, &b->dblk_sys, &b->dblk_wave0, &b->dpblk_sys, &b->dpblk_wave0,
+                      &b->dtblk_sys, &b->dtblk_tile, &b->head, &b->done, &b->flag})
         release(*d);
     delete b;
     c->batch = nullptr;
@@ -142,12 +153,65 @@ static int build_tables(Ctx *c, BatchState *b)
                 }
     }
     b->ntail_blocks = (int64_t)tsys.size();
+    // deep schedule tables
+    std::vector<int32_t> dsys, dw0, dpsys, dpw0, dtsys, dttile;
+    b->deep_pass_blocks.clear();
+    b->deep_pair_off.assign(1, 0);
+    if (b->deep_ok) {
+        const int D = b->deep_D;
+        std::vector<int64_t> dprefix(ns + 1, 0);
+        for (int j = 0; j < ns; ++j) {
+            const SysDev &sd = b->sys[b->order[j]];
+            const int64_t nbk = ((int64_t)sd.dnstrips * sd.dnchunks + 3) / 4;
+            for (int64_t q = 0; q < nbk; ++q) {
+                dsys.push_back(b->order[j]);
+                dw0.push_back((int32_t)(4 * q));
+            }
+            dprefix[j + 1] = dprefix[j] + nbk;
+        }
+        if (dprefix[ns] > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many wavefronts");
+        for (int p = 0; (p + 1) * D <= Mmax; ++p) {
+            int cnt = 0;
+            for (int j = 0; j < ns; ++j)
+                if (b->M[b->order[j]] / D > p) ++cnt;
+            b->deep_pass_blocks.push_back(dprefix[cnt]);
+        }
+        for (int q = 0; 2 * q + 2 < D; ++q) {
+            for (int j = 0; j < ns; ++j) {
+                const int sid = b->order[j];
+                if (b->M[sid] % D < 2 * q + 2) continue;
+                const SysDev &sd = b->sys[sid];
+                const int64_t nbk = ((int64_t)sd.nstrips * sd.nchunks + 3) / 4;
+                for (int64_t w = 0; w < nbk; ++w) {
+                    dpsys.push_back(sid);
+                    dpw0.push_back((int32_t)(4 * w));
+                }
+            }
+            b->deep_pair_off.push_back((int64_t)dpsys.size());
+        }
+        if ((int64_t)dpsys.size() > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many wavefronts");
+        for (int s = 0; s < ns; ++s)
+            if ((b->M[s] % D) & 1)
+                for (int64_t t = 0; t < tiles[s]; ++t) {
+                    dtsys.push_back(s);
+                    dttile.push_back((int32_t)t);
+                }
+    }
+    b->ndtail_blocks = (int64_t)dtsys.size();
     int rc;
     if (b->pairs_ok &&
         ((rc = upload(c, b->pblk_sys, psys.data(), psys.size() * 4, "pair block table")) ||
          (rc = upload(c, b->pblk_wave0, pw0.data(), pw0.size() * 4, "pair wavefront table")) ||
          (rc = upload(c, b->tblk_sys, tsys.data(), tsys.size() * 4, "tail block table")) ||
          (rc = upload(c, b->tblk_tile, ttile.data(), ttile.size() * 4, "tail tile table"))))
+        return rc;
+    if (b->deep_ok &&
+        ((rc = upload(c, b->dblk_sys, dsys.data(), dsys.size() * 4, "deep block table")) ||
+         (rc = upload(c, b->dblk_wave0, dw0.data(), dw0.size() * 4, "deep wavefront table")) ||
+         (rc = upload(c, b->dpblk_sys, dpsys.data(), dpsys.size() * 4, "deep pair block table")) ||
+         (rc = upload(c, b->dpblk_wave0, dpw0.data(), dpw0.size() * 4, "deep pair wavefront table")) ||
+         (rc = upload(c, b->dtblk_sys, dtsys.data(), dtsys.size() * 4, "deep tail block table")) ||
+         (rc = upload(c, b->dtblk_tile, dttile.data(), dttile.size() * 4, "deep tail tile table"))))
         return rc;
     if ((rc = upload(c, b->blk_sys, bsys.data(), bsys.size() * 4, "batch block table")) ||
         (rc = upload(c, b->blk_tile, btile.data(), btile.size() * 4, "batch tile table")) ||
@@ -175,12 +239,33 @@ static hipError_t enqueue_step(Ctx *c, BatchState *b, hipStream_t s, int par)
         const int32_t *ps = static_cast<const int32_t *>(b->pblk_sys.p);
         const int32_t *pw = static_cast<const int32_t *>(b->pblk_wave0.p);
         for (size_t p = 0; p < b->pair_level_blocks.size(); ++p) {
-            hipError_t e = launch_batch_pair(s, sys, gam, ps, pw, b->pair_level_blocks[p], (int)p, par);
+            hipError_t e = launch_batch_pair(s, sys, gam, ps, pw, b->pair_level_blocks[p], (int)p, 0, par);
             if (e != hipSuccess) return e;
         }
         return launch_batch_tail(s, sys, gam, static_cast<const int32_t *>(b->tblk_sys.p),
                                  static_cast<const int32_t *>(b->tblk_tile.p), b->ntail_blocks, b->tile, par,
-                                 b->block);
+                                 b->block, 0);
+    }
+    if (b->mode == CHEBTD_SCHED_DEEP) {
+        const int32_t *dsys = static_cast<const int32_t *>(b->dblk_sys.p);
+        const int32_t *dw = static_cast<const int32_t *>(b->dblk_wave0.p);
+        const int D = b->deep_D;
+        for (size_t p = 0; p < b->deep_pass_blocks.size(); ++p) {
+            hipError_t e = launch_batch_deep(s, D, sys, gam, dsys, dw, b->deep_pass_blocks[p], (int)p, (int)p * D,
+                                             par);
+            if (e != hipSuccess) return e;
+        }
+        const int32_t *ps = static_cast<const int32_t *>(b->dpblk_sys.p);
+        const int32_t *pw = static_cast<const int32_t *>(b->dpblk_wave0.p);
+        for (size_t q = 0; q + 1 < b->deep_pair_off.size(); ++q) {
+            const int64_t o = b->deep_pair_off[q];
+            hipError_t e = launch_batch_pair(s, sys, gam, ps + o, pw + o, b->deep_pair_off[q + 1] - o, (int)q, D,
+                                             par);
+            if (e != hipSuccess) return e;
+        }
+        return launch_batch_tail(s, sys, gam, static_cast<const int32_t *>(b->dtblk_sys.p),
+                                 static_cast<const int32_t *>(b->dtblk_tile.p), b->ndtail_blocks, b->tile, par,
+                                 b->block, 1);
     }
     if (b->mode == CHEBTD_SCHED_LEVELS) {
         for (int k = 0; k < b->nlevels; ++k) {
@@ -367,6 +452,24 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
         sd.nchunks = (sd.W + sd.rows - 1) / sd.rows;
         sd.pad2 = 0;
         if (b->M[s] < 2) b->pairs_ok = false;  // the head of a pair level computes two orders
+        sd.npass_pairs = b->M[s] >> 1;
+    }
+    // deep schedule: deep_D orders per pass (CHEBTD_BATCH_DEPTH, 4 .. 6,
+    // overrides), M / deep_D passes per system, so every system needs M >=
+    // deep_D; chunk heights as for one ribbon below 4M sites (the systems here
+    // are far smaller)
+    if (const char *env = std::getenv("CHEBTD_BATCH_DEPTH")) b->deep_D = std::max(4, std::min(6, std::atoi(env)));
+    b->deep_ok = b->pairs_ok;
+    static const int drows_of[7] = {0, 0, 0, 8, 6, 10, 14};
+    for (int s = 0; s < nsys; ++s) {
+        SysDev &sd = b->sys[s];
+        const int D = b->deep_D;
+        if (b->M[s] < D || !deep_offsets_fit(sd.W, sd.L)) b->deep_ok = false;
+        sd.drows = std::min<int32_t>(sd.W, drows_of[D]);
+        sd.dnstrips = (sd.L + deep_strip_cols(D) - 1) / deep_strip_cols(D);
+        sd.dnchunks = (sd.W + sd.drows - 1) / sd.drows;
+        sd.ndeep = b->M[s] / D;
+        sd.npass_deep = sd.ndeep + (b->M[s] % D) / 2;
     }
     b->order.resize(nsys);
     for (int s = 0; s < nsys; ++s) b->order[s] = s;
@@ -389,7 +492,12 @@ int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int bloc
     if (!b) return fail(c, CHEBTD_E_STATE, "chebtd_batch_set_schedule: no batch");
     if (mode == CHEBTD_SCHED_PAIRS && !b->pairs_ok)
         return fail(c, CHEBTD_E_ARG, "chebtd_batch_set_schedule: the pairs schedule needs M >= 2 for every system");
-    if ((mode != CHEBTD_SCHED_LEVELS && mode != CHEBTD_SCHED_PERSISTENT && mode != CHEBTD_SCHED_PAIRS) ||
+    if (mode == CHEBTD_SCHED_DEEP && !b->deep_ok)
+        return fail(c, CHEBTD_E_ARG,
+                    "chebtd_batch_set_schedule: the deep schedule needs M >= its depth for every system and "
+                    "ribbons whose offsets fit 32 bits");
+    if ((mode != CHEBTD_SCHED_LEVELS && mode != CHEBTD_SCHED_PERSISTENT && mode != CHEBTD_SCHED_PAIRS &&
+         mode != CHEBTD_SCHED_DEEP) ||
         block < 64 || block > 1024 ||
         block % 64 || tile_rows < block || tile_rows % block || wg_per_cu < 1 || wg_per_cu > 8)
         return fail(c, CHEBTD_E_ARG,
@@ -487,6 +595,7 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
         for (int tile : {1024, 2048, 4096, 8192})
             for (int block : {256, 512}) {
                 if (tile % block) continue;
+                if (b->deep_ok) cands.push_back({CHEBTD_SCHED_DEEP, tile, block, 1});
                 if (b->pairs_ok) cands.push_back({CHEBTD_SCHED_PAIRS, tile, block, 1});
                 cands.push_back({CHEBTD_SCHED_LEVELS, tile, block, 1});
             }

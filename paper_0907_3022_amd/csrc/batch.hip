@@ -27,6 +27,7 @@
 
 #include "batch_internal.h"
 #include "device_ops.h"
+#include "deep_walk.h"
 #include "pair_walk.h"
 
 namespace chebtd {
@@ -121,17 +122,22 @@ __global__ void k_batch_level(const SysDev *__restrict__ sys, const double2 *__r
 // pairs schedule
 // ---------------------------------------------------------------------------
 // Buffers of one step (cur = state entering the step, nxt = accumulator):
-// level 0 reads cur and writes v_1 -> A, v_2 -> C; odd levels read (A, C) and
-// write (D, cur); even levels >= 2 read (D, cur) and write (A, C).  cur is
-// free once the head has read it.
+// pass 0 reads cur and writes its last two orders to (A, C); odd passes read
+// (A, C) and write (D, cur); even passes >= 2 read (D, cur) and write (A, C).
+// cur is free once the head has read it.  The deep schedule's passes follow
+// the same rotation.
 template <bool HEAD>
 __global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ sys,
                                                     const double2 *__restrict__ gamma,
                                                     const int32_t *__restrict__ blk_sys,
-                                                    const int32_t *__restrict__ blk_wave0, int level, int par)
+                                                    const int32_t *__restrict__ blk_wave0, int q, int deep_D,
+                                                    int par)
 {
     const int32_t lb = logical_block(1);
     const SysDev sd = sys[blk_sys[lb]];
+    const int32_t base = deep_D > 0 ? sd.ndeep : 0;
+    const int pass = base + q;
+    const int k = base * deep_D + 2 * q;
     const int32_t gw = __builtin_amdgcn_readfirstlane(blk_wave0[lb] + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % sd.nstrips;
     const int32_t chunk = gw / sd.nstrips;
@@ -163,13 +169,13 @@ __global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ s
         g1 = ldg(g, 1);
         g2 = ldg(g, 2);
     } else {
-        const bool odd = level & 1;
+        const bool odd = pass & 1;
         in1 = odd ? sd.A : sd.D;
         in2 = odd ? sd.C : cur;
         o1 = odd ? sd.D : sd.A;
         o2 = odd ? cur : sd.C;
-        g1 = ldg(g, 2 * level + 1);
-        g2 = ldg(g, 2 * level + 2);
+        g1 = ldg(g, k + 1);
+        g2 = ldg(g, k + 2);
     }
     if (sd.edge == CHEBTD_ZIGZAG)
         pair_walk<CHEBTD_ZIGZAG, HEAD>(op, strip, chunk, in1, in2, o1, o2, nxt, g0, g1, g2, nullptr, nrm, en);
@@ -177,17 +183,68 @@ __global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ s
         pair_walk<CHEBTD_ARMCHAIR, HEAD>(op, strip, chunk, in1, in2, o1, o2, nxt, g0, g1, g2, nullptr, nrm, en);
 }
 
-// Order M = 2P+1 of a system with odd M: v_M = 2 H~ v_{M-1} - v_{M-2} over
-// v_{M-2}, acc += g_M v_M.  Level P-1 left (v_{M-2}, v_{M-1}) in (A, C) when
-// P-1 is even, in (D, cur) when odd.
+// D orders per pass over the batch (the deep walk of deep_walk.h, each
+// system with its own operator, grid and weights), buffers as k_batch_pair.
+template <bool HEAD, int D>
+__global__ __launch_bounds__(256) void k_batch_deep(const SysDev *__restrict__ sys,
+                                                    const double2 *__restrict__ gamma,
+                                                    const int32_t *__restrict__ blk_sys,
+                                                    const int32_t *__restrict__ blk_wave0, int pass, int k, int par)
+{
+    const int32_t lb = logical_block(1);
+    const SysDev sd = sys[blk_sys[lb]];
+    const int32_t gw = __builtin_amdgcn_readfirstlane(blk_wave0[lb] + (int32_t)(threadIdx.x >> 6));
+    const int32_t strip = gw % sd.dnstrips;
+    const int32_t chunk = gw / sd.dnstrips;
+    if (chunk >= sd.dnchunks) return;  // uniform per wavefront; the kernel has no barrier
+    OpPair op{};
+    op.onsite = sd.eps;
+    op.dshift = -sd.b;
+    op.s2 = sd.s2;
+    op.off2 = sd.off2;
+    op.W = sd.W;
+    op.L = sd.L;
+    op.rows = sd.drows;
+    op.nstrips = sd.dnstrips;
+    op.nchunks = sd.dnchunks;
+    double2 *cur = par ? sd.B : sd.psi;
+    double2 *nxt = par ? sd.psi : sd.B;
+    const double2 *g = gamma + sd.gamma_off;
+    DeepArgs<D> A{};
+    if (HEAD) {
+        A.vkm1 = nullptr;
+        A.vk = cur;
+        A.out1 = sd.A;
+        A.out2 = sd.C;
+    } else {
+        const bool odd = pass & 1;
+        A.vkm1 = odd ? sd.A : sd.D;
+        A.vk = odd ? sd.C : cur;
+        A.out1 = odd ? sd.D : sd.A;
+        A.out2 = odd ? cur : sd.C;
+    }
+    A.acc = nxt;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) A.w.g[j] = (HEAD || j > 0) ? ldg(g, k + j) : make_double2(0.0, 0.0);
+    double nrm = 0.0, en = 0.0;
+    if (sd.edge == CHEBTD_ZIGZAG)
+        deep_wave<CHEBTD_ZIGZAG, D, HEAD, kDeepProp>(op, strip, chunk, A, nrm, en);
+    else
+        deep_wave<CHEBTD_ARMCHAIR, D, HEAD, kDeepProp>(op, strip, chunk, A, nrm, en);
+}
+
+// The last order M of a system its passes left one short: v_M = 2 H~ v_{M-1}
+// - v_{M-2} over v_{M-2}, acc += g_M v_M.  The system's last pass (index
+// npass-1 of the schedule) left (v_{M-2}, v_{M-1}) in (A, C) when that index
+// is even, in (D, cur) when odd.
 __global__ void k_batch_tail(const SysDev *__restrict__ sys, const double2 *__restrict__ gamma,
                              const int32_t *__restrict__ blk_sys, const int32_t *__restrict__ blk_tile,
-                             int32_t tile, int par)
+                             int32_t tile, int par, int deep)
 {
     const SysDev sd = sys[blk_sys[blockIdx.x]];
     double2 *cur = par ? sd.B : sd.psi;
     double2 *nxt = par ? sd.psi : sd.B;
-    const bool even = (((sd.M >> 1) - 1) & 1) == 0;
+    const bool even = (((deep ? sd.npass_deep : sd.npass_pairs) - 1) & 1) == 0;
     double2 *vprev = even ? sd.A : sd.D;
     const double2 *vk = even ? sd.C : cur;
     const double2 gM = ldg(gamma + sd.gamma_off, sd.M);
@@ -328,24 +385,53 @@ hipError_t launch_batch_persistent(hipStream_t s, const SysDev *sys, const doubl
 }
 
 hipError_t launch_batch_pair(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
-                             const int32_t *blk_wave0, int64_t nblocks, int level, int par)
+                             const int32_t *blk_wave0, int64_t nblocks, int q, int deep_D, int par)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (level == 0)
+    // a head pass only where no deep pass came first (pairs schedule, q = 0)
+    if (q == 0 && deep_D == 0)
         hipLaunchKernelGGL(k_batch_pair<true>, dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma, blk_sys,
-                           blk_wave0, level, par);
+                           blk_wave0, q, deep_D, par);
     else
         hipLaunchKernelGGL(k_batch_pair<false>, dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma, blk_sys,
-                           blk_wave0, level, par);
+                           blk_wave0, q, deep_D, par);
     return hipGetLastError();
 }
 
+namespace {
+template <int D>
+hipError_t launch_batch_deep_d(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
+                               const int32_t *blk_wave0, int64_t nblocks, int pass, int k, int par)
+{
+    if (pass == 0)
+        hipLaunchKernelGGL((k_batch_deep<true, D>), dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma, blk_sys,
+                           blk_wave0, pass, k, par);
+    else
+        hipLaunchKernelGGL((k_batch_deep<false, D>), dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma,
+                           blk_sys, blk_wave0, pass, k, par);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batch_deep(hipStream_t s, int D, const SysDev *sys, const double2 *gamma,
+                             const int32_t *blk_sys, const int32_t *blk_wave0, int64_t nblocks, int pass, int k,
+                             int par)
+{
+    if (nblocks <= 0) return hipSuccess;
+    switch (D) {
+        case 4: return launch_batch_deep_d<4>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, k, par);
+        case 5: return launch_batch_deep_d<5>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, k, par);
+        case 6: return launch_batch_deep_d<6>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, k, par);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_batch_tail(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
-                             const int32_t *blk_tile, int64_t nblocks, int32_t tile, int par, int block)
+                             const int32_t *blk_tile, int64_t nblocks, int32_t tile, int par, int block, int deep)
 {
     if (nblocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_tail, dim3((unsigned)nblocks), dim3(block), 0, s, sys, gamma, blk_sys, blk_tile,
-                       tile, par);
+                       tile, par, deep);
     return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ struct DeepArgs {
     DeepWeights<D> w;        // propagation g_k .. g_{k+D}; adjoint conj(g_{k-j+1}) in w.g[j]
 };
 
-constexpr int deep_strip(int D) { return 66 - 2 * D; }
+constexpr int deep_strip(int D) { return deep_strip_cols(D); }
 constexpr int deep_gcd(int a, int b) { return b == 0 ? a : deep_gcd(b, a % b); }
 constexpr int deep_lcm(int a, int b) { return a / deep_gcd(a, b) * b; }
 // Iterations between issuing a row's loads and using them.  A wavefront
@@ -386,18 +386,15 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     for (base = 0; base < T; base += U) phases<0, U>(step);
 }
 
-// One wavefront per (strip, chunk) of a 256-thread block: wavefronts whose
-// 64 lanes lie on lattice columns and whose every row read (ys - D up to the
-// rows below the chunk that the last unrolled body loads) lies inside the
-// lattice skip the border tests.
+// The walk of one wavefront: wavefronts whose 64 lanes lie on lattice
+// columns and whose every row read (ys - D up to the rows below the chunk
+// that the last unrolled body loads) lies inside the lattice skip the border
+// tests.  deep_dispatch maps the wavefronts of a grid of 256-thread blocks to
+// (strip, chunk).
 template <int EDGE, int D, bool HEAD, int MODE>
-__device__ __forceinline__ void deep_dispatch(const OpPair &op, const DeepArgs<D> &A, double &nrm, double &en)
+__device__ __forceinline__ void deep_wave(const OpPair &op, int32_t strip, int32_t chunk, const DeepArgs<D> &A,
+                                          double &nrm, double &en)
 {
-    const int32_t gwv =
-        __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
-    const int32_t strip = gwv % op.nstrips;
-    const int32_t chunk = gwv / op.nstrips;
-    if (chunk >= op.nchunks) return;  // uniform per wavefront
     const int32_t x0 = strip * deep_strip(D) - (D - 1);
     const int32_t ys = chunk * op.rows, ye = min(ys + op.rows, op.W);
     const int32_t last = ys - (D - 1) + deep_iterations(D, ye - ys) + kDeepAhead;
@@ -405,6 +402,17 @@ __device__ __forceinline__ void deep_dispatch(const OpPair &op, const DeepArgs<D
         deep_walk<EDGE, D, HEAD, false, MODE>(op, strip, chunk, A, nrm, en);
     else
         deep_walk<EDGE, D, HEAD, true, MODE>(op, strip, chunk, A, nrm, en);
+}
+
+template <int EDGE, int D, bool HEAD, int MODE>
+__device__ __forceinline__ void deep_dispatch(const OpPair &op, const DeepArgs<D> &A, double &nrm, double &en)
+{
+    const int32_t gwv =
+        __builtin_amdgcn_readfirstlane(logical_block(op.xcd_remap) * 4 + (int32_t)(threadIdx.x >> 6));
+    const int32_t strip = gwv % op.nstrips;
+    const int32_t chunk = gwv / op.nstrips;
+    if (chunk < op.nchunks)  // uniform per wavefront
+        deep_wave<EDGE, D, HEAD, MODE>(op, strip, chunk, A, nrm, en);
 }
 
 }  // namespace chebtd

@@ -22,6 +22,9 @@ struct OpPair {
 };
 
 constexpr int kPairStripCols = 62;  // columns a wavefront owns
+// columns a wavefront of the D-orders walk owns (each level past the first
+// loses one lane per side)
+constexpr int deep_strip_cols(int D) { return 66 - 2 * D; }
 
 OpPair make_pair_op(const Ctx &c, int rows);
 int64_t pair_grid_blocks(const Ctx &c, int rows);

@@ -59,7 +59,7 @@ def reset(systems, torch):
 
 @pytest.mark.parametrize("mode,tile,block,wg", [(0, 1024, 256, 1), (0, 512, 512, 1), (1, 1024, 256, 2),
                                                 (1, 4096, 512, 4), (1, 256, 256, 8), (2, 1024, 256, 1),
-                                                (2, 512, 512, 1)])
+                                                (2, 512, 512, 1), (3, 1024, 256, 1), (3, 512, 512, 1)])
 @pytest.mark.parametrize("graph", [False, True])
 def test_batch_matches_oracle(torch, cheb, mode, tile, block, wg, graph):
     systems = make_systems(SMALL, torch)
@@ -124,7 +124,7 @@ def test_batch_autotune_restores_state_and_caches(torch, cheb, tmp_path):
     ctx.batch_create(systems, 1.0)
     cache = str(tmp_path / "tune.txt")
     best = ctx.batch_autotune(cache)
-    assert best[0] in (0, 1, 2)
+    assert best[0] in (0, 1, 2, 3)
     for s in systems:
         np.testing.assert_array_equal(s["psi"].cpu().numpy(), s["psi0"])
     assert os.path.exists(cache) and len(open(cache).read().split()) == 5
@@ -145,6 +145,23 @@ def test_batch_rejects_bad_schedule(torch, cheb):
         ctx.batch_set_schedule(1, 1000, 256, 2)  # tile not a multiple of block
     with pytest.raises(cheb.ChebError):
         ctx.batch_set_schedule(5, 1024, 256, 2)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_batch_deep_equals_single_system_path_bitwise(torch, cheb, K):
+    # five orders per pass while every system has five left (M = 20 .. 22 here:
+    # four passes), then a two-order pass or the one-order tail; the single
+    # system restricted to passes of 1, 2 and 5 orders splits M the same way
+    systems = make_systems(SMALL, torch)
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    ctx.batch_set_schedule(cheb.SCHED_DEEP, 1024, 256, 1)
+    ctx.batch_propagate(K, cheb.GRAPH)
+    torch.cuda.synchronize()
+    Ms = ctx.batch_info()
+    assert Ms.min() >= 5 and len(set(int(m) % 5 for m in Ms)) > 1
+    for s in systems:
+        np.testing.assert_array_equal(single_system(torch, cheb, s, K, 5), s["psi"].cpu().numpy())
 
 
 @pytest.mark.parametrize("K", [1, 2, 3])
