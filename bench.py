@@ -429,13 +429,25 @@ def bench_adjoint(torch, P, K):
         gbar2 = (2.0 * m * psi).contiguous()
         dV2 = torch.zeros_like(Vd)
         t_bwd2 = timed(torch, lambda: ctx.adjoint(gbar2, dV2))
+        # forward vectors regenerated downwards from each step's last two
+        ctx.reserve_adjoint(K, P.ADJ_REVERSE)
+        psi.copy_(torch.from_numpy(psi0).cuda())
+        t_fwd3 = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK | P.KEEP_CHECKPOINTS))
+        gbar3 = (2.0 * m * psi).contiguous()
+        dV3 = torch.zeros_like(Vd)
+        t_bwd3 = timed(torch, lambda: ctx.adjoint(gbar3, dV3))
         # the schedules group levels into passes differently: equal to rounding
-        sched_diff = float((dV - dV2).norm() / dV.norm()) if float(dV.norm()) > 0 else 0.0
+        nv = float(dV.norm())
+        sched_diff = float((dV - dV2).norm()) / nv if nv > 0 else 0.0
+        rev_diff = float((dV - dV3).norm()) / nv if nv > 0 else 0.0
+        # backward_s: the default schedule (forward vectors run downwards)
         out[name] = dict(n=int(Vd.numel()), M=M, steps=K, forward_s=t_plain,
-                         forward_with_checkpoints_s=t_fwd, backward_s=t_bwd,
-                         backward_over_forward=t_bwd / t_plain,
+                         forward_with_checkpoints_s=t_fwd3, backward_s=t_bwd3,
+                         backward_over_forward=t_bwd3 / t_plain,
+                         backward_step_s=t_bwd, backward_step_over_forward=t_bwd / t_plain,
+                         forward_with_psi_checkpoints_s=t_fwd,
                          backward_sqrtM_s=t_bwd2, backward_sqrtM_over_forward=t_bwd2 / t_plain,
-                         schedules_rel_diff=sched_diff,
+                         step_sqrtM_rel_diff=sched_diff, step_reverse_rel_diff=rev_diff,
                          transmission=float((m * psi.abs() ** 2).sum().item()))
         ctx.close()
     return out

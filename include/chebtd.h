@@ -204,8 +204,9 @@ int chebtd_plan_passes(const chebtd_ctx *ctx, int *passes_out, int capacity, int
  * synchronises at the end and returns CHEBTD_E_DIVERGED if the final norm
  * is not finite or differs from the initial one by more than the check
  * tolerance (chebtd_set_check_tol, default 1e-6 relative).
- * CHEBTD_KEEP_CHECKPOINTS stores psi_s for the adjoint; it needs
- * chebtd_reserve_adjoint with K <= its max_steps. */
+ * CHEBTD_KEEP_CHECKPOINTS stores psi_s for the adjoint (CHEBTD_ADJ_REVERSE:
+ * also v_{M-1} and v_M of every step); it needs chebtd_reserve_adjoint with
+ * K <= its max_steps. */
 int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_dev,
                      double *energy_dev, unsigned flags);
 
@@ -335,17 +336,28 @@ int chebtd_batch_info(const chebtd_ctx *ctx, int *nsys, int *M_host);
                            /* orders (rounded up to even for chains and    */
                            /* ribbons, which recompute two orders a pass)  */
                            /* and recompute segment by segment              */
+#define CHEBTD_ADJ_REVERSE 2 /* keep each step's last two vectors           */
+                             /* (v_{M-1}, v_M) beside psi_s and regenerate  */
+                             /* v_{M-2} .. v_0 downwards, v_{k-1} =         */
+                             /* 2 H~ v_k - v_{k+1}, inside the passes that  */
+                             /* run the adjoint levels: nothing is          */
+                             /* recomputed forwards.  3 vectors per step;   */
+                             /* chains and ribbons within the deep walk's   */
+                             /* offset limit ((W + 14) L 16 B <= 2^31)      */
 
 /* Allocate the adjoint's storage: psi checkpoints for up to max_steps steps
- * and the recompute buffers of `mode`.  Needs a plan (chain or honeycomb). */
+ * and the recompute buffers of `mode` (CHEBTD_ADJ_REVERSE: also the step-end
+ * pairs, 2 more vectors per step).  Needs a plan (chain or honeycomb);
+ * CHEBTD_E_ARG for CHEBTD_ADJ_REVERSE on a lattice past its offset limit. */
 int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode);
 
 /* After chebtd_propagate(..., K, ..., CHEBTD_KEEP_CHECKPOINTS): gbar_dev
  * (complex128[n]) holds dL/dpsi_K on entry and the adjoint of psi_0 on
  * return; dLdV_dev (float64[n]) is accumulated into (+=).  On ribbons the
  * reverse sweep runs several levels per pass over memory and CHEBTD_ADJ_STEP
- * recomputes several orders per pass, so the two modes group the levels
- * differently and agree to rounding, not bit for bit. */
+ * recomputes several orders per pass; CHEBTD_ADJ_REVERSE regenerates the
+ * forward vectors downwards.  The modes group the levels differently and
+ * agree to rounding, not bit for bit. */
 int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev);
 
 /* ======================================================================= */

@@ -4,7 +4,7 @@ Implements the Chebyshev expansion of the time-evolution operator of Fehske
 et al., arXiv:0907.3022 (Sect. 2.2) as hand-written HIP kernels for gfx950
 behind the C ABI of include/chebtd.h; this package is its Python binding.
 """
-from ._lib import (ADJ_SQRTM, ADJ_STEP, ARMCHAIR, GRAPH, KEEP_CHECKPOINTS, NO_CHECK,
+from ._lib import (ADJ_REVERSE, ADJ_SQRTM, ADJ_STEP, ARMCHAIR, GRAPH, KEEP_CHECKPOINTS, NO_CHECK,
                    NO_PERSISTENT, SCHED_DEEP, SCHED_LEVELS, SCHED_PAIRS, SCHED_PERSISTENT, SINGLE_ORDER, ZIGZAG,
                    ChebError)
 from ._lib import lib as load_library
@@ -13,7 +13,7 @@ from .api import Context, holstein_csr_host, holstein_occupations
 __all__ = [
     "Context", "ChebError", "load_library", "holstein_csr_host", "holstein_occupations",
     "ZIGZAG", "ARMCHAIR", "KEEP_CHECKPOINTS", "NO_CHECK", "GRAPH", "NO_PERSISTENT", "SINGLE_ORDER",
-    "SCHED_LEVELS", "SCHED_PERSISTENT", "SCHED_PAIRS", "SCHED_DEEP", "ADJ_STEP", "ADJ_SQRTM",
+    "SCHED_LEVELS", "SCHED_PERSISTENT", "SCHED_PAIRS", "SCHED_DEEP", "ADJ_STEP", "ADJ_SQRTM", "ADJ_REVERSE",
 ]
 
 

@@ -16,7 +16,7 @@ E_ARG, E_HIP, E_DIVERGED, E_OOM, E_STATE, E_TIMEOUT = -1, -2, -3, -4, -5, -6
 ZIGZAG, ARMCHAIR = 0, 1
 KEEP_CHECKPOINTS, NO_CHECK, GRAPH, NO_PERSISTENT, SINGLE_ORDER = 1, 2, 4, 8, 16
 SCHED_LEVELS, SCHED_PERSISTENT, SCHED_PAIRS, SCHED_DEEP = 0, 1, 2, 3
-ADJ_STEP, ADJ_SQRTM = 0, 1
+ADJ_STEP, ADJ_SQRTM, ADJ_REVERSE = 0, 1, 2
 
 _ERRNAMES = {E_ARG: "CHEBTD_E_ARG", E_HIP: "CHEBTD_E_HIP", E_DIVERGED: "CHEBTD_E_DIVERGED",
              E_OOM: "CHEBTD_E_OOM", E_STATE: "CHEBTD_E_STATE", E_TIMEOUT: "CHEBTD_E_TIMEOUT"}

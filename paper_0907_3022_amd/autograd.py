@@ -22,10 +22,13 @@ class Propagator:
     kind: "chain" (needs dx) or "honeycomb" (needs width, length, edge, t).
     bounds: (emin, emax) enclosing the spectrum of H(V) for every V the
     caller will use (they fix H~ = (H - b)/a).
+    adjoint_mode: L.ADJ_STEP, L.ADJ_SQRTM or L.ADJ_REVERSE; None picks
+    L.ADJ_REVERSE (the fastest, three vectors per step) where the lattice
+    allows it and L.ADJ_STEP elsewhere.
     """
 
     def __init__(self, kind, dt, K, bounds, *, dx=None, width=None, length=None, edge="zigzag",
-                 t=1.0, alpha=0.01, tol=1e-15, adjoint_mode=L.ADJ_STEP, context=None):
+                 t=1.0, alpha=0.01, tol=1e-15, adjoint_mode=None, context=None):
         if kind not in ("chain", "honeycomb"):
             raise ValueError("kind must be 'chain' or 'honeycomb'")
         self.kind, self.dt, self.K = kind, float(dt), int(K)
@@ -45,7 +48,14 @@ class Propagator:
 
     def forward(self, V, psi0, keep=True):
         self._setup(V)
-        if keep:
+        if keep and self.adjoint_mode is None:
+            try:
+                self.ctx.reserve_adjoint(self.K, L.ADJ_REVERSE)
+            except L.ChebError as err:  # past the downward walk's offset limit
+                if err.code != L.E_ARG:
+                    raise
+                self.ctx.reserve_adjoint(self.K, L.ADJ_STEP)
+        elif keep:
             self.ctx.reserve_adjoint(self.K, self.adjoint_mode)
         psi = psi0.detach().clone().contiguous()
         self.ctx.propagate(psi, self.K, flags=L.KEEP_CHECKPOINTS if keep else 0)

@@ -2,8 +2,9 @@
 // time steps.  The forward run keeps psi at the start of every step; the
 // backward run rebuilds that step's Chebyshev vectors from it (all M+1 of
 // them, or in segments of about sqrt(M) orders from (v_{j-1}, v_j) pairs)
-// and runs the reverse recursion, two levels per pass where it can
-// (adjoint.hip).
+// and runs the reverse recursion, several levels per pass where it can
+// (adjoint.hip).  The third schedule also keeps the step's last two vectors
+// and regenerates the others downwards inside the reverse passes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +34,7 @@ struct AdjState {
     DevBuf vbuf;   // recompute buffer
     DevBuf pairs;  // (v_{j-1}, v_j) per segment (sqrt mode)
     DevBuf u;      // two adjoint vectors
+    DevBuf ends;   // (v_{M-1}, v_M) per step (reverse mode)
 };
 
 void adj_destroy(Ctx *c)
@@ -42,6 +44,7 @@ void adj_destroy(Ctx *c)
     release(c->adj->vbuf);
     release(c->adj->pairs);
     release(c->adj->u);
+    release(c->adj->ends);
     delete c->adj;
     c->adj = nullptr;
 }
@@ -57,6 +60,17 @@ double2 *adj_checkpoint(Ctx *c, int64_t step, int64_t K)
         a->ckpt_version = c->plan_version;
     }
     return static_cast<double2 *>(a->ckpt.p) + (size_t)step * (size_t)c->n;
+}
+
+// Slot of (v_{M-1}, v_M) of `step` (2 n values) for the reverse schedule, or
+// null when the adjoint storage does not keep them.
+double2 *adj_step_ends(Ctx *c, int64_t step)
+{
+    AdjState *a = c->adj;
+    if (!a || a->mode != CHEBTD_ADJ_REVERSE || a->plan_version != c->plan_version || step >= a->max_steps ||
+        !a->ends.p)
+        return nullptr;
+    return static_cast<double2 *>(a->ends.p) + (size_t)step * 2 * (size_t)c->n;
 }
 
 }  // namespace chebtd
@@ -179,6 +193,108 @@ hipError_t sweep_levels(Ctx *c, hipStream_t s, int kbeg, int kend, VK vk, double
     return e;
 }
 
+// Levels per pass of the reverse schedule (2 .. kMaxRevDepth, 5 being the
+// most that keeps both recursions in registers without spilling): 5 on
+// ribbons, 3 on chains (measured on MI355X, 256 x 4096 ribbon and 65536-site
+// chain at order 64: 0.50 and 0.23 ms per step; 4 levels 0.56 and 0.30,
+// chains at 5 levels 0.29); CHEBTD_REV_DEPTH overrides.
+int rev_depth(const Ctx &c)
+{
+    int D = c.kind == HKind::Honeycomb ? 5 : 3;
+    if (const char *env = std::getenv("CHEBTD_REV_DEPTH")) D = std::atoi(env);
+    return std::max(2, std::min(kMaxRevDepth, D));
+}
+
+// Rows per wavefront chunk of a reverse pass of depth D, with rows + 2 (D - 1)
+// a multiple of the 6-iteration body.  Up to 4M sites the chunk count decides:
+// at 1M sites 22-row chunks give 5-level passes about one wavefront per SIMD
+// (two fit at 236 VGPRs) and ran 0.50 ms per step against 0.52 for 10 rows and
+// 0.61 for 16 (unevenly 1 or 2 per SIMD); past it the propagation's deep-pass
+// heights.  CHEBTD_REV_ROWS overrides.
+int rev_rows(const Ctx &c, int D)
+{
+    if (const char *env = std::getenv("CHEBTD_REV_ROWS")) return std::max(1, std::atoi(env));
+    static const int small[kMaxRevDepth + 1] = {0, 0, 10, 14, 24, 22};
+    if (c.n >= (int64_t(1) << 22) && D >= 3 && c.deep_rows[D] > 0) return c.deep_rows[D];
+    return small[D];
+}
+
+// The reverse schedule over all steps.  Per step, from the stored
+// (v_{M-1}, v_M), passes of levels k .. k-d+1 regenerate the forward vectors
+// downwards beside the adjoint recursion; the pass holding level 0 writes
+// u_0, the next step's gbar, into the other of two gbar buffers (the pass
+// still reads the current one around its rows).  M = 1 has level 0 alone.
+hipError_t reverse_sweep(Ctx *c, hipStream_t s, double2 *gbar_user, double *grad, URot &u)
+{
+    AdjState *a = c->adj;
+    const int M = c->M;
+    const int64_t n = c->n;
+    double2 *vb = static_cast<double2 *>(a->vbuf.p);
+    double2 *vr[4] = {vb, vb + n, vb + 2 * n, vb + 3 * n};
+    double2 *gcur = gbar_user, *gnext = vb + 4 * n;
+    // pass depths from level M-1 down to level 0: rev_depth each, and no
+    // pass of a single level (the walk needs two)
+    std::vector<int> depths;
+    const int Dm = rev_depth(*c);
+    for (int rem = M; rem > 0;) {
+        int d = std::min(Dm, rem);
+        if (rem - d == 1) d = rem <= kMaxRevDepth ? rem : d - 1;
+        depths.push_back(d);
+        rem -= d;
+    }
+    hipError_t e = hipSuccess;
+    for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {
+        u.start(u.buf[0]);
+        e = launch_adj_init(s, gcur, conj_weight(c, M), u.uk1, n);  // u_M
+        if (e != hipSuccess) break;
+        if (M == 1) {
+            double2 *psi_s = static_cast<double2 *>(a->ckpt.p) + (size_t)st * n;
+            e = sweep_levels(c, s, 0, 1, [&](int) { return psi_s; }, gcur, grad, u);
+            continue;
+        }
+        double2 *ends = adj_step_ends(c, st);
+        if (!ends) return hipErrorInvalidValue;
+        const double2 *v1 = ends + n, *v0 = ends;  // v_{k+1}, v_k for k = M-1
+        int k = M - 1;
+        for (const int d : depths) {
+            RevPass p{};
+            p.last0 = k - d + 1 == 0;
+            double2 *o1, *o2;
+            u.spare(&o1, &o2);
+            p.uk2 = u.has2 ? u.uk2 : nullptr;
+            p.uk1 = u.uk1;
+            p.out1 = p.last0 ? nullptr : o1;
+            p.out2 = p.last0 ? gnext : o2;
+            p.gbar = gcur;
+            p.grad = grad;
+            p.v1 = v1;
+            p.v0 = v0;
+            if (!p.last0) {
+                for (double2 *w : vr) {
+                    if (w == v1 || w == v0) continue;
+                    if (!p.vout1)
+                        p.vout1 = w;
+                    else if (!p.vout2)
+                        p.vout2 = w;
+                }
+            }
+            for (int j = 1; j <= d; ++j) p.cw[j - 1] = conj_weight(c, k - j + 1);
+            e = launch_rev_deep(*c, s, d, rev_rows(*c, d), p);
+            if (e != hipSuccess) break;
+            u.uk2 = o1;  // u_{k-d+2}
+            u.uk1 = o2;  // u_{k-d+1}
+            u.has2 = true;
+            v1 = p.vout1;  // v_{k-d+1}
+            v0 = p.vout2;  // v_{k-d}
+            k -= d;
+        }
+        if (e == hipSuccess && k != -1) e = hipErrorInvalidValue;
+        std::swap(gcur, gnext);
+    }
+    if (e == hipSuccess && gcur != gbar_user) e = launch_copy(s, gcur, gbar_user, n);
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -189,8 +305,11 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
     Ctx *c = static_cast<Ctx *>(ctx);
     if (!c->has_plan || (c->kind != HKind::Chain && c->kind != HKind::Honeycomb))
         return fail(c, CHEBTD_E_STATE, "chebtd_reserve_adjoint: needs a plan for a chain or honeycomb H");
-    if (max_steps < 1 || (mode != CHEBTD_ADJ_STEP && mode != CHEBTD_ADJ_SQRTM))
+    if (max_steps < 1 || (mode != CHEBTD_ADJ_STEP && mode != CHEBTD_ADJ_SQRTM && mode != CHEBTD_ADJ_REVERSE))
         return fail(c, CHEBTD_E_ARG, "chebtd_reserve_adjoint: need max_steps >= 1 and a known mode");
+    if (mode == CHEBTD_ADJ_REVERSE && !rev_deep_fits(*c))
+        return fail(c, CHEBTD_E_ARG,
+                    "chebtd_reserve_adjoint: CHEBTD_ADJ_REVERSE needs (W + 14) L 16 B <= 2^31 (the deep walk's offsets)");
     if (!c->adj) c->adj = new (std::nothrow) AdjState();
     if (!c->adj) return fail(c, CHEBTD_E_OOM, "adjoint state");
     AdjState *a = c->adj;
@@ -208,8 +327,15 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
     if ((rc = ensure(c, a->u, 4 * vb, "adjoint vectors"))) return rc;
     if (mode == CHEBTD_ADJ_STEP) {
         release(a->pairs);
+        release(a->ends);
         if ((rc = ensure(c, a->vbuf, vb * (size_t)(M + 1), "recompute buffer"))) return rc;
+    } else if (mode == CHEBTD_ADJ_REVERSE) {
+        // four vectors for the downward pairs, one for the other gbar
+        release(a->pairs);
+        if ((rc = ensure(c, a->ends, 2 * vb * (size_t)max_steps, "step-end pairs"))) return rc;
+        if ((rc = ensure(c, a->vbuf, 5 * vb, "downward vectors"))) return rc;
     } else {
+        release(a->ends);
         const int nseg = (M + a->seg - 1) / a->seg;
         if ((rc = ensure(c, a->pairs, vb * 2 * (size_t)std::max(nseg, 1), "segment pairs"))) return rc;
         if ((rc = ensure(c, a->vbuf, vb * (size_t)(a->seg + 1), "segment buffer"))) return rc;
@@ -240,6 +366,11 @@ int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
     for (int q = 0; q < 4; ++q) urot.buf[q] = static_cast<double2 *>(a->u.p) + (size_t)q * n;
     const bool pairs_on = pair_supported(*c);
     hipError_t e = hipSuccess;
+    if (a->mode == CHEBTD_ADJ_REVERSE && M >= 1) {
+        e = reverse_sweep(c, s, gbar, dLdV_dev, urot);
+        if (e != hipSuccess) return hip_fail(c, e, "chebtd_adjoint (reverse schedule)");
+        return CHEBTD_OK;
+    }
     for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {
         double2 *psi_s = ck + (size_t)st * n;
         if (M == 0) {

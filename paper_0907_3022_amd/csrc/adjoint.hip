@@ -364,6 +364,16 @@ __global__ __launch_bounds__(256) void k_adj_deep(OpPair op, DeepArgs<D> args)
     deep_dispatch<EDGE, D, false, kDeepAdj>(op, args, nrm, en);
 }
 
+// Reverse levels k .. k-D+1 (>= 0) from (u_{k+2}, u_{k+1}) with the forward
+// vectors run downwards beside them from (v_{k+1}, v_k): writes u_{k-D+2},
+// u_{k-D+1}, v_{k-D+1}, v_{k-D} and adds the levels' shares to dL/dV.
+template <int EDGE, int D>
+__global__ __launch_bounds__(256) void k_rev_deep(OpPair op, DeepArgs<D> args)
+{
+    double nrm = 0.0, en = 0.0;
+    deep_dispatch<EDGE, D, false, kDeepRev>(op, args, nrm, en);
+}
+
 namespace {
 
 template <int D>
@@ -417,7 +427,55 @@ hipError_t launch_adj_deep_d(const Ctx &c, hipStream_t s, int rows, const double
     return hipGetLastError();
 }
 
+template <int D>
+hipError_t launch_rev_deep_d(const Ctx &c, hipStream_t s, int rows, const RevPass &p)
+{
+    const OpPair op = make_deep_op(c, rows, D);
+    const int64_t nb = deep_grid_blocks(c, rows, D);
+    if (nb <= 0 || nb > INT32_MAX || !deep_offsets_fit(op.W, op.L)) return hipErrorInvalidValue;
+    DeepArgs<D> A{};
+    A.vkm1 = p.uk2;
+    A.vk = p.uk1;
+    A.out1 = p.out1;
+    A.out2 = p.out2;
+    A.gbar = p.gbar;
+    A.grad = p.grad;
+    A.gf = 2.0 / c.a;
+    A.gfD = p.last0 ? 1.0 / c.a : 2.0 / c.a;
+    A.hD = p.last0 ? 0.5 : 1.0;
+    A.rv1 = p.v1;
+    A.rv0 = p.v0;
+    A.rout1 = p.vout1;
+    A.rout2 = p.vout2;
+    for (int j = 0; j < D; ++j) A.w.g[j + 1] = p.cw[j];
+    const dim3 grid((unsigned)nb), block(256);
+    const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
+    if (zig)
+        hipLaunchKernelGGL((k_rev_deep<CHEBTD_ZIGZAG, D>), grid, block, 0, s, op, A);
+    else
+        hipLaunchKernelGGL((k_rev_deep<CHEBTD_ARMCHAIR, D>), grid, block, 0, s, op, A);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+bool rev_deep_fits(const Ctx &c)
+{
+    if (!pair_supported(c)) return false;
+    const OpPair op = make_pair_op(c, 1);
+    return deep_offsets_fit(op.W, op.L);
+}
+
+hipError_t launch_rev_deep(const Ctx &c, hipStream_t s, int D, int rows, const RevPass &p)
+{
+    switch (D) {
+        case 2: return launch_rev_deep_d<2>(c, s, rows, p);
+        case 3: return launch_rev_deep_d<3>(c, s, rows, p);
+        case 4: return launch_rev_deep_d<4>(c, s, rows, p);
+        case 5: return launch_rev_deep_d<5>(c, s, rows, p);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_recompute_deep(const Ctx &c, hipStream_t s, int D, int rows, bool head, const double2 *vkm1,
                                  const double2 *vk, double2 *const *all)

@@ -24,13 +24,22 @@
 // unrolled over a common multiple of the ring sizes, so every slot index is
 // a constant and no value is copied between registers.
 //
-// The same walk serves three uses (MODE): the propagation step above; the
+// The same walk serves four uses (MODE): the propagation step above; the
 // recomputation of a step's Chebyshev vectors for the adjoint, each level
-// stored to its own vector and nothing accumulated; and the adjoint's reverse
+// stored to its own vector and nothing accumulated; the adjoint's reverse
 // recursion, level j forming
 //   u_{k-j+1} = conj(g_{k-j+1}) gbar + 2 H~ u_{k-j+2} - u_{k-j+3}
 // from u_{k+1} (level 0) and u_{k+2}, while dL/dV of a row collects
-// (2/a) Re[conj(u_{k-j+2}) v_{k-j+1}] from every level in a ring like acc's.
+// (2/a) Re[conj(u_{k-j+2}) v_{k-j+1}] from every level in a ring like acc's,
+// the forward vectors v read from memory; and that reverse recursion with
+// the forward vectors regenerated beside it, from v_{k+1} and v_k, by the
+// same three-term recursion run downwards,
+//   v_{k-j} = 2 H~ v_{k-j+1} - v_{k-j+2},
+// a second set of D windows in the same walk (exact in exact arithmetic;
+// |T_k| <= 1 on the rescaled spectrum keeps the rounding as small as the
+// forward run's).  The last level of such a pass may be the recursion's
+// level 0, u_0 = conj(g_0) gbar + H~ u_1 - u_2 with dL/dV share
+// (1/a) Re[conj(u_1) v_0]: hD and gfD carry its halved factors.
 //
 // Memory goes through buffer loads and stores whose 32-bit offsets wrap:
 // rows above or below the lattice, columns outside it and lanes that own no
@@ -57,6 +66,7 @@ struct DeepWeights {
 constexpr int kDeepProp = 0;  // propagation: acc += sum_j g_{k+j} v_{k+j}
 constexpr int kDeepAll = 1;   // recomputation: level j stored to all[j-1]
 constexpr int kDeepAdj = 2;   // adjoint levels and dL/dV
+constexpr int kDeepRev = 3;   // adjoint levels, dL/dV and the forward vectors run downwards
 
 // Operands of one pass.  vkm1, vk: the two vectors entering level 1 (the
 // adjoint's u_{k+2}, u_{k+1}; vkm1 may be null for the head, or for the
@@ -72,6 +82,10 @@ struct DeepArgs {
     double *grad;            // adjoint: dL/dV, read and written
     const double2 *fwd;      // adjoint: v_{k-D+1}; level j's v_{k-j+1} lies (D-j) n after it
     double gf;               // adjoint: 2/a
+    const double2 *rv1, *rv0;  // downwards: v_{k+1}, v_k
+    double2 *rout1, *rout2;    // downwards: v_{k-D+1}, v_{k-D} (null: not stored)
+    double hD;               // downwards: 1, or 1/2 when level D is the recursion's level 0
+    double gfD;              // downwards: level D's dL/dV factor, 2/a or 1/a
     DeepWeights<D> w;        // propagation g_k .. g_{k+D}; adjoint conj(g_{k-j+1}) in w.g[j]
 };
 
@@ -130,9 +144,11 @@ __device__ __forceinline__ void bstore1(Rsrc r, uint32_t voff, uint32_t soff, do
 
 // Operands of row rn loaded ahead: v_k of row rn+1 (the next level-0 row),
 // and v_{k-1}, the on-site term, the outside value and acc (adjoint: gbar
-// and dL/dV) of row rn.
+// and dL/dV) of row rn; run downwards, the same three for the forward
+// vectors (va, vkm1, vext).
 struct DeepPrefetch {
     double2 a, km1, ext, acc;
+    double2 va, vkm1, vext;
     double e, gr;
 };
 
@@ -161,7 +177,8 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
 {
     static_assert(D >= 2 && D <= 6, "depth");
     static_assert(MODE == kDeepProp || !HEAD || MODE == kDeepAll, "the adjoint has no head pass");
-    constexpr bool PROP = MODE == kDeepProp, ALL = MODE == kDeepAll, ADJ = MODE == kDeepAdj;
+    constexpr bool PROP = MODE == kDeepProp, ALL = MODE == kDeepAll, REV = MODE == kDeepRev;
+    constexpr bool ADJ = MODE == kDeepAdj || REV;  // the adjoint recursion, either way
     const DeepWeights<D> &gw = A.w;
     using namespace pairdev;
     using namespace deepdev;
@@ -188,7 +205,10 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     const Rsrc rgr = rsrc_or_0(ADJ ? A.grad : nullptr, nb16 / 2);
     // the adjoint's D forward vectors, n apart (D n 16 B <= 2^30, so the
     // out-of-range bias never wraps into them)
-    const Rsrc rfw = rsrc_or_0(ADJ ? A.fwd : nullptr, (uint32_t)D * nb16);
+    const Rsrc rfw = rsrc_or_0(ADJ && !REV ? A.fwd : nullptr, ADJ && !REV ? (uint32_t)D * nb16 : 0u);
+    // run downwards: the two forward vectors entering the pass and the two it leaves
+    const Rsrc rv1 = rsrc_or_0(REV ? A.rv1 : nullptr, nb16), rv0 = rsrc_or_0(REV ? A.rv0 : nullptr, nb16);
+    const Rsrc rvo1 = rsrc_or_0(REV ? A.rout1 : nullptr, nb16), rvo2 = rsrc_or_0(REV ? A.rout2 : nullptr, nb16);
     // column part of each offset: loads (lattice columns), stores (own
     // columns), the outside value (lanes 0 and 63); kOut elsewhere
     const uint32_t c16 = colok ? (uint32_t)x * 16u : kOut;
@@ -241,11 +261,14 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     // diagonal terms 2 (eps - b)/a of the last RS rows
     constexpr int RS = deep_ring(D);
     double2 lv[D][3];
+    double2 vl[REV ? D : 1][3];  // downwards: the forward vectors' windows
     double2 P[RS];   // propagation: partial acc; adjoint: gbar of the row
     double G[RS];    // adjoint: partial dL/dV
     double dd[RS];
 #pragma unroll
     for (int j = 0; j < D; ++j) lv[j][0] = lv[j][1] = lv[j][2] = zero;
+#pragma unroll
+    for (int j = 0; j < (REV ? D : 1); ++j) vl[j][0] = vl[j][1] = vl[j][2] = zero;
 #pragma unroll
     for (int j = 0; j < RS; ++j) {
         P[j] = zero;
@@ -255,6 +278,10 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     // iteration 0 reads level-0 rows r0-1 (slot 1) and r0 (slot 2)
     lv[0][1] = ld2(rk, c16, r0 - 1);
     lv[0][2] = ld2(rk, c16, r0);
+    if (REV) {
+        vl[0][1] = ld2(rv0, c16, r0 - 1);
+        vl[0][2] = ld2(rv0, c16, r0);
+    }
     // operands of iteration n (pair_walk.h's set: v_k of the row below, and
     // v_{k-1}, on-site term, outside value and acc of row r0 + n)
     constexpr int K = kDeepAhead + 1;
@@ -274,10 +301,15 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
             nx.acc = ld2(racc, c16, rn);
             nx.gr = ld1(rgr, ok ? s8 : kOut, rn);
         }
+        if (REV) {
+            nx.va = ld2(rv0, c16, rn + 1);
+            nx.vkm1 = ld2(rv1, c16, rn);
+            nx.vext = ld2(rv0, ext_off(rn), rn);
+        }
     };
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        pf[k].km1 = pf[k].acc = zero;
+        pf[k].km1 = pf[k].acc = pf[k].va = pf[k].vkm1 = pf[k].vext = zero;
         pf[k].gr = 0.0;
         if (k < K - 1) issue(pf[k], k);
     }
@@ -302,8 +334,8 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
         __builtin_amdgcn_sched_barrier(0);
         // adjoint: the forward vectors of this iteration's rows, used after
         // the levels (own columns of chunk rows only)
-        double2 fv[ADJ ? D : 1];
-        if constexpr (ADJ) {
+        double2 fv[ADJ && !REV ? D : 1];
+        if constexpr (ADJ && !REV) {
 #pragma unroll
             for (int j = 1; j <= D; ++j) {
                 const int32_t rel = i - (D - 1) - (j - 1);
@@ -313,6 +345,7 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
             }
         }
         lv[0][sl0] = cur.a;  // level 0, row rr+1
+        if (REV) vl[0][sl0] = cur.va;
         dd[ph % RS] = op.s2 * (cur.e + op.dshift);
         if (ADJ) P[ph % RS] = cur.acc;  // gbar of row rr
 #pragma unroll
@@ -333,8 +366,10 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
                     val = make_double2(0.5 * fma(d, c.x, op.off2 * s.x), 0.5 * fma(d, c.y, op.off2 * s.y));
                 } else {
                     const double2 prev = j == 1 ? cur.km1 : lv[j >= 2 ? j - 2 : 0][sl2];
-                    val = make_double2(fma(d, c.x, fma(op.off2, s.x, -prev.x)),
-                                       fma(d, c.y, fma(op.off2, s.y, -prev.y)));
+                    // level D of a downward pass may be level 0 (H~ u_1 in place of 2 H~)
+                    const bool half = REV && j == D;
+                    const double dj = half ? d * A.hD : d, oj = half ? op.off2 * A.hD : op.off2;
+                    val = make_double2(fma(dj, c.x, fma(oj, s.x, -prev.x)), fma(dj, c.y, fma(oj, s.y, -prev.y)));
                 }
                 if (ADJ) val = cfma(gw.g[j], P[ps], val);
                 if (BORDER) val = csel(colok && active, val, zero);
@@ -362,6 +397,21 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
                 }
             }
             if (j < D) lv[j][sl0] = val;
+            if constexpr (REV) {
+                // the forward vector v_{k-j} of row q, from v_{k-j+1} and v_{k-j+2}
+                const double2 c = vl[j - 1][sl1], m = vl[j - 1][sl2], p = vl[j - 1][sl0];
+                double2 s = stencil_sum(m, p, from_left0(c), from_right0(c), q);
+                if (j == 1) s = cadd(s, cur.vext);
+                const double2 prev = j == 1 ? cur.vkm1 : vl[j >= 2 ? j - 2 : 0][sl2];
+                const double d = dd[ps];
+                double2 vv = make_double2(fma(d, c.x, fma(op.off2, s.x, -prev.x)),
+                                          fma(d, c.y, fma(op.off2, s.y, -prev.y)));
+                if (BORDER) vv = csel(colok && active, vv, zero);
+                const bool mine = rel >= 0 && rel < nrows;
+                if (j == D - 1) st2(rvo1, q, vv, mine);
+                if (j == D) st2(rvo2, q, vv, mine);
+                if (j < D) vl[j][sl0] = vv;
+            }
         }
         if constexpr (ADJ) {
             // dL/dV of row rr - (j-1): level j's share, from the centre of
@@ -372,8 +422,9 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
                 const int32_t rel = i - (D - 1) - (j - 1);
                 const int ps = ((ph - (j - 1)) % RS + RS) % RS;
                 const double2 c = lv[j - 1][sl1];
-                const double t = c.x * fv[j - 1].x + c.y * fv[j - 1].y;
-                G[ps] = (j == 1 ? cur.gr : G[ps]) + A.gf * t;
+                const double2 f = REV ? vl[REV ? j - 1 : 0][sl1] : fv[REV ? 0 : j - 1];
+                const double t = c.x * f.x + c.y * f.y;
+                G[ps] = (j == 1 ? cur.gr : G[ps]) + (REV && j == D ? A.gfD : A.gf) * t;
                 if (j == D) st1(rgr, rr - (D - 1), G[ps], rel >= 0 && rel < nrows);
             }
         }

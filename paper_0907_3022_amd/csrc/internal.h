@@ -232,6 +232,23 @@ bool adj_deep_fits(const Ctx &c, int D);
 hipError_t launch_adj_deep(const Ctx &c, hipStream_t s, int D, int rows, const double2 *uk2, const double2 *uk1,
                            double2 *out1, double2 *out2, const double2 *gbar, double *grad, const double2 *fwd,
                            const double2 *cw);
+// D = 2 .. kMaxRevDepth adjoint levels k .. k-D+1 >= 0 per pass with the
+// forward vectors regenerated downwards (v_{k-j} = 2 H~ v_{k-j+1} - v_{k-j+2})
+// beside them: no stored forward vectors are read.  last0: level k-D+1 is
+// level 0 (out2 = u_0; out1 and the forward outputs may then be null).
+constexpr int kMaxRevDepth = 5;
+struct RevPass {
+    const double2 *uk2, *uk1;  // u_{k+2} (null: zero), u_{k+1}
+    double2 *out1, *out2;      // u_{k-D+2}, u_{k-D+1}
+    const double2 *gbar;
+    double *grad;
+    const double2 *v1, *v0;    // v_{k+1}, v_k
+    double2 *vout1, *vout2;    // v_{k-D+1}, v_{k-D}
+    double2 cw[kMaxRevDepth];  // conj(g_{k-j+1}), j = 1 .. D
+    bool last0;
+};
+bool rev_deep_fits(const Ctx &c);
+hipError_t launch_rev_deep(const Ctx &c, hipStream_t s, int D, int rows, const RevPass &p);
 hipError_t launch_adj_level(const Ctx &c, hipStream_t s, const double2 *u1, double2 *u2_in,
                             const double2 *gbar_in, double2 *out, const double2 *vk, double2 gk,
                             double gscale, int has_u2, double *grad);

@@ -18,6 +18,7 @@ int ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what);
 void release(DevBuf &b);
 void drop_graphs(Ctx *c);
 double2 *adj_checkpoint(Ctx *c, int64_t step, int64_t K);  // adjoint.cpp
+double2 *adj_step_ends(Ctx *c, int64_t step);              // adjoint.cpp
 }  // namespace chebtd
 
 using namespace chebtd;
@@ -54,7 +55,8 @@ int dominant_pass(const Ctx &c)
 // pair kernel, 3 .. kMaxDepth: the deep kernel); a single-order pass, if
 // any, comes last.  Pass outputs alternate between (vA, vC) and (vD, cur):
 // cur is free once the head pass has read it.
-hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt,
+// ends (or null): 2 n values that receive v_{M-1}, v_M of the step
+hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt, double2 *ends,
                               double *norm_out, double *energy_out)
 {
     double2 *A = static_cast<double2 *>(c->vA.p), *C = static_cast<double2 *>(c->vC.p),
@@ -65,12 +67,15 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
     double2 g[kMaxDepth + 1];
     hipError_t e;
     int64_t head_blocks;
+    // the last multi-order pass writes its two orders, v_{M-1} and v_M, into ends
+    const bool head_last = P.size() == 1;
+    double2 *h1 = ends && head_last ? ends : A, *h2 = ends && head_last ? ends + c->n : C;
     if (h > 2) {
         for (int j = 0; j <= h; ++j) g[j] = weight(c, j);
-        e = launch_deep(*c, s, h, c->deep_rows[h], true, nullptr, cur, A, C, nxt, g, ckpt, partials, nullptr);
+        e = launch_deep(*c, s, h, c->deep_rows[h], true, nullptr, cur, h1, h2, nxt, g, ckpt, partials, nullptr);
         head_blocks = deep_grid_blocks(*c, c->deep_rows[h], h);
     } else {
-        e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, A, C, nxt, weight(c, 0), weight(c, 1),
+        e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, h1, h2, nxt, weight(c, 0), weight(c, 1),
                         weight(c, 2), ckpt, partials);
         head_blocks = pair_grid_blocks(*c, c->pair_rows);
     }
@@ -90,8 +95,14 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
     for (size_t i = 1; i < P.size(); ++i) {
         const int d = P[i];
         const NeFinal *f = (want_ne && i == 1) ? &fin : nullptr;
+        if (ends && i + 1 == P.size() && d >= 2) {
+            F1 = ends;
+            F2 = ends + c->n;
+        }
         if (d == 1) {  // the last order: v_M = 2 H~ v_{M-1} - v_{M-2} over v_{M-2}
             e = launch_iter(*c, s, Y, X, nxt, weight(c, k + 1));
+            if (e == hipSuccess && ends) e = launch_copy(s, Y, ends, c->n);
+            if (e == hipSuccess && ends) e = launch_copy(s, X, ends + c->n, c->n);
         } else if (d == 2) {
             e = launch_pair(*c, s, c->pair_rows, false, X, Y, F1, F2, nxt, make_double2(0.0, 0.0),
                             weight(c, k + 1), weight(c, k + 2), nullptr, nullptr, f);
@@ -112,11 +123,11 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
 }
 
 // Enqueue one time step: cur -> nxt.  cur is overwritten with v_2, v_4, ...
-hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt,
+hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, double2 *ckpt, double2 *ends,
                         double *norm_out, double *energy_out, unsigned flags)
 {
     if (c->use_pairs && !(flags & CHEBTD_SINGLE_ORDER))
-        return enqueue_step_pairs(c, s, cur, nxt, ckpt, norm_out, energy_out);
+        return enqueue_step_pairs(c, s, cur, nxt, ckpt, ends, norm_out, energy_out);
     double2 *A = static_cast<double2 *>(c->vA.p);
     double *partials = static_cast<double *>(c->partials.p);
     hipError_t e = launch_head(*c, s, cur, A, nxt, weight(c, 0), weight(c, 1), ckpt, partials);
@@ -132,7 +143,13 @@ hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, doubl
         e = launch_iter(*c, s, vk, vprev, nxt, weight(c, k + 1));
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    if (ends && c->M >= 1) {
+        // v_M was written over v_{M-2}: A holds the odd orders, cur the even ones
+        double2 *vM = (c->M & 1) ? A : cur, *vM1 = (c->M & 1) ? cur : A;
+        e = launch_copy(s, vM1, ends, c->n);
+        if (e == hipSuccess) e = launch_copy(s, vM, ends + c->n, c->n);
+    }
+    return e;
 }
 
 // norm of psi into results[slot]
@@ -164,8 +181,8 @@ int get_pair_graph(Ctx *c, double2 *psi, double *norm_out, double *energy_out, u
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
-    hipError_t e1 = enqueue_step(c, c->cap_stream, psi, B, nullptr, norm_out, energy_out, flags);
-    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, c->cap_stream, B, psi, nullptr, norm_out, energy_out, flags)
+    hipError_t e1 = enqueue_step(c, c->cap_stream, psi, B, nullptr, nullptr, norm_out, energy_out, flags);
+    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, c->cap_stream, B, psi, nullptr, nullptr, norm_out, energy_out, flags)
                                      : e1;
     e = hipStreamEndCapture(c->cap_stream, &g);
     if (e2 != hipSuccess) {
@@ -215,8 +232,9 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
         if (e != hipSuccess) return hip_fail(c, e, "counter reset");
     }
 
+    // the one-workgroup chain kernel keeps psi_s but not the step-end pairs
     const bool small = c->kind == HKind::Chain && chain_small_fits(c->n) &&
-                       !(flags & CHEBTD_NO_PERSISTENT);
+                       !(flags & CHEBTD_NO_PERSISTENT) && !(keep && adj_step_ends(c, 0));
     if (small) {
         e = launch_chain_small(*c, s, P, P, static_cast<const double2 *>(c->gamma_dev.p), K, norm_dev,
                                energy_dev, keep ? adj_checkpoint(c, 0, K) : nullptr);
@@ -230,7 +248,7 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
             if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
         }
         if (K & 1) {
-            e = enqueue_step(c, s, P, B, nullptr, norm_dev, energy_dev, flags);
+            e = enqueue_step(c, s, P, B, nullptr, nullptr, norm_dev, energy_dev, flags);
             if (e == hipSuccess) e = launch_copy(s, B, P, c->n);
             if (e != hipSuccess) return hip_fail(c, e, "last step");
         }
@@ -238,8 +256,8 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
         for (int64_t st = 0; st < K; ++st) {
             double2 *cur = (st & 1) ? B : P;
             double2 *nxt = (st & 1) ? P : B;
-            e = enqueue_step(c, s, cur, nxt, keep ? adj_checkpoint(c, st, K) : nullptr, norm_dev,
-                             energy_dev, flags);
+            e = enqueue_step(c, s, cur, nxt, keep ? adj_checkpoint(c, st, K) : nullptr,
+                             keep ? adj_step_ends(c, st) : nullptr, norm_dev, energy_dev, flags);
             if (e != hipSuccess) return hip_fail(c, e, "step launch");
         }
         if (K & 1) {
@@ -299,7 +317,7 @@ int chebtd_propagate_td(chebtd_ctx *ctx, double *psi_dev, int64_t K, const doubl
             c->hol_delta = on;
         double2 *cur = (st & 1) ? B : P;
         double2 *nxt = (st & 1) ? P : B;
-        e = enqueue_step(c, s, cur, nxt, nullptr, norm_dev, energy_dev, step_flags);
+        e = enqueue_step(c, s, cur, nxt, nullptr, nullptr, norm_dev, energy_dev, step_flags);
     }
     if (c->kind == HKind::Chain)
         c->V = saved;

@@ -57,7 +57,7 @@ def gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, mode):
     return float(L.item()), Vt.grad.cpu().numpy(), p0.grad.cpu().numpy(), prop
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("case", ["chain", "zigzag", "armchair", "chain_large"])
 def test_adjoint_matches_oracle(torch, cheb, case, mode):
     if case.startswith("chain"):
@@ -88,8 +88,9 @@ def test_adjoint_matches_oracle(torch, cheb, case, mode):
 
 # z = a dt from 1e-9 to 0.3 gives M = 1, 2, 3, 4, 5, 6, 10: the reverse sweep
 # pairs levels two by two where it can and leaves single levels (odd counts,
-# level 0, the level next to u_M) to the one-level kernel
-@pytest.mark.parametrize("mode", [0, 1])
+# level 0, the level next to u_M) to the one-level kernel; the downward
+# schedule (mode 2) splits the M levels into passes of 2 .. 5 ending at level 0
+@pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("case", ["chain", "zigzag", "armchair"])
 @pytest.mark.parametrize("z", [1e-9, 1e-7, 3e-4, 1e-3, 0.01, 0.02, 0.3])
 def test_adjoint_low_orders(torch, cheb, case, mode, z):
@@ -127,6 +128,88 @@ def test_adjoint_modes_agree(torch, cheb):
     _, g1, u1, _ = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask, b, 9.4, 3, 1)
     assert rel_l2(g0, g1) <= 1e-12
     assert rel_l2(u0, u1) <= 1e-13
+    # the downward schedule regenerates the forward vectors by the recursion
+    # run backwards: equal to rounding as well
+    _, g2, u2, _ = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask, b, 9.4, 3, 2)
+    assert rel_l2(g2, g0) <= 1e-12
+    assert rel_l2(u2, u0) <= 1e-13
+
+
+# the downward schedule at every pass depth and at chunk heights that put
+# chunk boundaries at every offset of the 6-iteration body; 37 x 130 has
+# chunks and strips clear of the border
+@pytest.mark.parametrize("rows", [None, 1, 5, 16])
+@pytest.mark.parametrize("case", ["chain", "zigzag", "armchair"])
+@pytest.mark.parametrize("rev_depth", [2, 3, 4, 5])
+def test_adjoint_reverse_depths_match_oracle(torch, cheb, monkeypatch, rev_depth, case, rows):
+    if case == "chain" and rows is not None:
+        pytest.skip("a chain is one row")
+    monkeypatch.setenv("CHEBTD_REV_DEPTH", str(rev_depth))
+    if rows is not None:
+        monkeypatch.setenv("CHEBTD_REV_ROWS", str(rows))
+    if case == "chain":
+        dx, V, psi0, mask = chain_inputs(5003)
+        H = O.chain1d(V, dx)
+        geom, kind = dict(dx=dx), "chain"
+        lo, hi = H.gershgorin()
+        dt = 12.0 / (0.5 * 1.01 * (hi - lo))
+    else:
+        w, l = 37, 130
+        V, psi0, mask = ribbon_inputs(w, l)
+        H = O.honeycomb(w, l, V, edge=case)
+        geom, kind = dict(width=w, length=l, edge=case), "honeycomb"
+        lo, hi = H.gershgorin()
+        dt = 1.37
+    K = 2
+    Lg, g, u0, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, (lo, hi), dt, K, 2)
+    plan = O.Plan(lo, hi, dt)
+    assert prop.M == plan.M and plan.M >= 14
+    Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
+    assert Lg == pytest.approx(Lr, rel=1e-10)
+    assert rel_l2(g, gr) <= 1e-8
+    assert rel_l2(u0, ur) <= 1e-10
+
+
+# the forward run keeps each step's (v_{M-1}, v_M) for the downward schedule:
+# written by the step's last multi-order pass, or copied after a last single
+# order or the one-order-per-pass path
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("case", ["chain", "zigzag"])
+@pytest.mark.parametrize("z", [0.02, 1.0, 7.0])
+def test_adjoint_reverse_step_ends(torch, cheb, case, single, z):
+    if case == "chain":
+        dx, V, psi0, mask = chain_inputs(257)
+        H = O.chain1d(V, dx)
+    else:
+        V, psi0, mask = ribbon_inputs(9, 70)
+        H = O.honeycomb(9, 70, V)
+    lo, hi = H.gershgorin()
+    dt = z / (0.5 * 1.01 * (hi - lo))
+    K = 3
+    ctx = cheb.Context()
+    Vd = torch.from_numpy(V.copy()).cuda()
+    if case == "chain":
+        ctx.chain1d(Vd, dx)
+    else:
+        ctx.honeycomb(9, 70, Vd)
+    ctx.set_bounds(lo, hi)
+    M = ctx.plan(dt)
+    ctx.reserve_adjoint(K, cheb.ADJ_REVERSE)
+    say(f"[gpu] reverse step ends {case} M={M} passes={ctx.plan_passes()} single={single}")
+    psi = torch.from_numpy(psi0.copy()).cuda()
+    flags = cheb.NO_CHECK | cheb.KEEP_CHECKPOINTS | (cheb.SINGLE_ORDER if single else 0)
+    ctx.propagate(psi, K, None, None, flags)
+    m = torch.from_numpy(mask).cuda()
+    gbar = (2.0 * m * psi).contiguous()
+    dV = torch.zeros_like(Vd)
+    ctx.adjoint(gbar, dV)
+    torch.cuda.synchronize()
+    plan = O.Plan(lo, hi, dt)
+    assert M == plan.M
+    Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
+    assert np.linalg.norm(dV.cpu().numpy() - gr) <= 1e-8 * np.linalg.norm(gr) + 1e-12
+    assert rel_l2(gbar.cpu().numpy(), ur) <= 1e-10
+    ctx.close()
 
 
 # D adjoint levels per pass (2 .. 6) with the forward vectors recomputed two
@@ -162,7 +245,7 @@ def test_adjoint_depths_match_oracle(torch, cheb, monkeypatch, adj_depth, rec_de
 
 
 def _fd_check(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, sites, h, rtol_floor):
-    Lg, g, _, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, 0)
+    Lg, g, _, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, None)
     Vd = torch.from_numpy(V.copy()).cuda()
     m = torch.from_numpy(mask).cuda()
     p0 = torch.from_numpy(psi0).cuda()
@@ -215,7 +298,8 @@ def test_adjoint_config_chain_65536_fd(torch, cheb):
     _fd_check(torch, cheb, "chain", dict(dx=dx), V, psi0, mask, (lo, hi), dt, p["K"], sites, p["h"], 1e-4)
 
 
-def test_adjoint_full_size_vs_oracle_short(torch, cheb):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_adjoint_full_size_vs_oracle_short(torch, cheb, mode):
     # full 256 x 4096 ribbon, order ~64, 2 steps: GPU reverse sweep vs the oracle's
     p = W.ADJOINT.params
     w, l = p["width"], p["length"]
@@ -226,7 +310,7 @@ def test_adjoint_full_size_vs_oracle_short(torch, cheb):
     lo, hi = H.gershgorin()
     dt = 30.5 / (0.5 * 1.01 * (hi - lo))
     Lg, g, u0, prop = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask,
-                                  (lo, hi), dt, 2, 0)
+                                  (lo, hi), dt, 2, mode)
     plan = O.Plan(lo, hi, dt)
     assert prop.M == plan.M and 60 <= plan.M <= 70
     Lr, gr, ur = O.adjoint(H, plan, psi0, 2, mask)
