@@ -453,6 +453,26 @@ def bench_adjoint(torch, P, K):
     return out
 
 
+def bench_triad(torch, total_bytes, reps):
+    """A STREAM-style triad a = b + s c in float64 (torch's elementwise kernel)
+    over three arrays of total_bytes together: 2 reads and 1 write per
+    element.  Returns GB/s from HIP events around `reps` launches."""
+    n = max(1, int(total_bytes) // 24)
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.full_like(b, 0.5)
+    a = torch.empty_like(b)
+    for _ in range(3):
+        torch.add(b, c, alpha=2.0, out=a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(b, c, alpha=2.0, out=a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    return 24 * n / sec / 1e9
+
+
 def bench_copy(torch, nbytes=1 << 30, reps=5):
     """A plain device copy of known size: the reference that scales the
     hardware byte counters (FETCH_SIZE, WRITE_SIZE) of the other kernels."""
@@ -552,6 +572,16 @@ def main():
         "norm_drift": r["norm_drift"],
     }
     r["ctx"].close()
+    # measured ceilings: a plain streaming kernel over 3 GiB (HBM) and over the
+    # footprint of one pass of the dominant kernel (resident in the 256 MB MALL
+    # like the pass itself)
+    footprint = unit_bytes * r["n"]
+    tri_hbm = bench_triad(torch, 3 << 30, 20)
+    tri_fp = bench_triad(torch, footprint, 400)
+    line["roofline"]["measured_ceiling"] = {
+        "kernel": "triad a = b + s*c, float64, torch elementwise",
+        "GBs_3GiB": tri_hbm, "GBs_same_footprint": tri_fp, "footprint_bytes": footprint,
+        "frac_of_same_footprint": achieved / tri_fp if tri_fp > 0 else None}
     extra = {}
     if "double_well" in sections:
         log("[bench] double well N=4096, 200 steps")
