@@ -453,6 +453,47 @@ def bench_adjoint(torch, P, K):
     return out
 
 
+def bench_table2(torch, P):
+    """Table 2 shape: the armchair ribbon of 10 x 1000 atoms with one occupied
+    site at its centre, propagated to t = 1e4 at dt = 1, 10 and 100.  Reports
+    each run's time beside the paper's single-core times (context only), the
+    order the 1e-15 cutoff gives (the paper's M are the empirical orders for
+    agreement with exact results, not comparable), the three final states
+    against each other (each step is exact to the cutoff, so they differ by
+    rounding accumulated over the steps), the norm and how far the state
+    spread (rms distance from the start column, participation fraction)."""
+    p = W.TABLE2.params
+    w, l = p["width"], p["length"]
+    eps, psi0 = W.table2_inputs(w, l, p["W"], p["seed"])
+    ctx = P.Context()
+    eps_d = torch.from_numpy(eps).cuda()
+    ctx.honeycomb(w, l, eps_d, edge=p["edge"], t=p["t"])
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi)
+    x = np.tile(np.arange(l), w).astype(np.float64)
+    x0 = l // 2
+    runs, finals = [], []
+    for dt, paper_s, paper_M in zip(p["dts"], (378.0, 97.0, 45.0), (104, 264, 1210)):
+        M = ctx.plan(dt)
+        K = int(round(p["t_end"] / dt))
+        psi = torch.from_numpy(psi0).cuda()
+        ctx.propagate(psi, 2, None, None, P.NO_CHECK | P.GRAPH)  # warm-up (captures the graph)
+        psi = torch.from_numpy(psi0).cuda()
+        t = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK | P.GRAPH))
+        f = psi.cpu().numpy()
+        finals.append(f)
+        rho = np.abs(f) ** 2
+        runs.append(dict(dt=dt, M=M, steps=K, seconds=t, passes=ctx.plan_passes(), paper_seconds=paper_s,
+                         paper_M=paper_M, norm_deviation=abs(float(rho.sum()) - 1.0),
+                         rms_distance_columns=float(np.sqrt((rho * (x - x0) ** 2).sum() / rho.sum())),
+                         participation_fraction=float(rho.sum() ** 2 / (rho ** 2).sum() / rho.size)))
+    ref = finals[0]
+    for r, f in zip(runs[1:], finals[1:]):
+        r["rel_l2_vs_dt1"] = float(np.linalg.norm(f - ref) / np.linalg.norm(ref))
+    ctx.close()
+    return dict(workload=W.TABLE2.name, W=p["W"], seed=p["seed"], runs=runs)
+
+
 def bench_triad(torch, total_bytes, reps):
     """A STREAM-style triad a = b + s c in float64 (torch's elementwise kernel)
     over three arrays of total_bytes together: 2 reads and 1 write per
@@ -518,7 +559,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections",
-                    default="main,double_well,table1,holstein,batched,adjoint,polaron,sweep,cpu")
+                    default="main,double_well,table1,table2,holstein,batched,adjoint,polaron,sweep,cpu")
     ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -589,6 +630,9 @@ def main():
     if "table1" in sections:
         log("[bench] double well to t = 40: Chebyshev vs Crank-Nicolson")
         extra["table1"] = bench_table1(torch, P)
+    if "table2" in sections:
+        log("[bench] armchair ribbon 10x1000 to t = 1e4 at dt = 1, 10, 100 (Table 2 shape)")
+        extra["table2"] = bench_table2(torch, P)
     if "holstein" in sections:
         log("[bench] Holstein ring L=10, N_ph<=10, 500 steps")
         extra["holstein"] = bench_holstein(torch, P, W.HOLSTEIN.params["K"])

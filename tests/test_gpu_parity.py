@@ -171,6 +171,23 @@ def test_honeycomb_parity(torch, cheb, edge, width, length):
     np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11)
 
 
+# Table 2 shape (Sect. 3.2): the 10 x 1000 armchair ribbon from one occupied
+# site at its centre, at dt = 1, 10 and 100 (M = 20, 67, 399) to t = 100 (the
+# paper runs to t = 1e4), replayed as a graph
+@pytest.mark.parametrize("dt", [1.0, 10.0, 100.0])
+def test_table2_ribbon_single_site(torch, cheb, dt):
+    p = W.TABLE2.params
+    w, l = p["width"], p["length"]
+    eps, psi0 = W.table2_inputs(w, l, p["W"], p["seed"])
+    case = dict(kind="honey", width=w, length=l, edge=p["edge"], eps=eps, psi0=psi0,
+                H=O.honeycomb(w, l, eps, edge=p["edge"]))
+    K = int(round(100.0 / dt))
+    _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, dt, K, flags=cheb.GRAPH)
+    assert rel_l2(psi, ref) <= TOL
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11)
+
+
 @pytest.mark.parametrize("L,nph,g2,periodic", [(4, 3, 0.5, True), (6, 4, 2.0, True), (5, 5, 0.5, False)])
 def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic):
     case = holstein_case(L, nph, g2, periodic, Delta=np.linspace(0, 0.5, L))

@@ -181,6 +181,11 @@ POLARON_PAPER = Workload("polaron_L18_nph11", dict(L=18, nph=11, t=1.0, w0=2.0, 
                                                    eps_p_barrier=1.0, barrier_site=11,
                                                    barrier=2.0, packet_site=3, k=math.pi / 9,
                                                    width=2.0, dt=0.5, snapshots=(6.0, 10.0, 14.0)))
+# Sect. 3.2 / Table 2: armchair ribbon of 10 x 1000 atoms, one occupied site
+# at the centre, propagated to t = 1e4 with dt = 1, 10, 100.  Not printed for
+# the timings, chosen here: disorder W = 0.5 (the weakest of Fig. 2), seed 2.
+TABLE2 = Workload("armchair_ribbon_10x1000_t1e4", dict(width=10, length=1000, edge="armchair", t=1.0,
+                                                       W=0.5, seed=2, t_end=1e4, dts=(1.0, 10.0, 100.0)))
 ADJOINT = Workload("adjoint_transmission", dict(n1d=65536, width=256, length=4096, W=0.5, K=100,
                                                 order=64, fd_sites=32, h=1e-6))
 
@@ -192,6 +197,13 @@ def ribbon_inputs(width: int, length: int, W: float, seed: int, sigma: float = 2
     sig = min(sigma, width / 4.0)
     psi = ribbon_packet(width, length, sig, k0)
     return eps, psi
+
+
+def table2_inputs(width: int, length: int, W: float, seed: int):
+    """(eps, psi0) for the Table 2 ribbon: disorder and the single site at the
+    centre (row width // 2, column length // 2)."""
+    eps = anderson_disorder(width, length, W, seed)
+    return eps, single_site(width * length, (width // 2) * length + length // 2)
 
 
 def double_well_inputs(n: int = 4096, xmin: float = -20.0, xmax: float = 20.0, a: float = 0.05,
