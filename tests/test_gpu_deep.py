@@ -197,3 +197,23 @@ def test_long_chain_beyond_deep_offsets_uses_pairs(torch, cheb, depth_env):
         torch.cuda.synchronize()
         assert abs(host(nrm)[1] / host(nrm)[0] - 1.0) < 1e-12
         ctx.close()
+
+
+def test_deep_tall_chunks_from_16M_sites(torch, cheb, depth_env):
+    # from 16M sites five- and six-order passes walk 52- and 56-row chunks:
+    # one step of a 512 x 32768 ribbon against the oracle
+    case = honey_case(512, 32768, "zigzag", 0.5, 4)
+    ref = None
+    for depth in (None, 6):
+        depth_env(depth)
+        ctx, psi, nrm, _, plan = run(torch, cheb, case, 1.0, 1)
+        passes = ctx.plan_passes()
+        assert plan.M == 20 and sum(passes) == 20
+        if depth is None:
+            assert passes == [5, 5, 5, 5]
+            ref = O.propagate(case["H"], plan, case["psi0"], 1)
+        else:
+            assert 6 in passes
+        ctx.close()
+        assert rel_l2(psi, ref) <= 1e-10
+        assert abs(nrm[0] - 1.0) < 1e-12
