@@ -457,15 +457,19 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
     // deep schedule: deep_D orders per pass (CHEBTD_BATCH_DEPTH, 4 .. 6,
     // overrides), M / deep_D passes per system, so every system needs M >=
     // deep_D; chunk heights as for one ribbon below 4M sites (the systems here
-    // are far smaller)
+    // are far smaller; on the 256-ribbon workload over 200 steps 10 rows ran
+    // 211 G site-orders/s, 16 rows 209 G, 22 rows 205 G); CHEBTD_BATCH_DEEP_ROWS
+    // overrides
     if (const char *env = std::getenv("CHEBTD_BATCH_DEPTH")) b->deep_D = std::max(4, std::min(6, std::atoi(env)));
     b->deep_ok = b->pairs_ok;
     static const int drows_of[7] = {0, 0, 0, 8, 6, 10, 14};
+    int drows_env = 0;
+    if (const char *env = std::getenv("CHEBTD_BATCH_DEEP_ROWS")) drows_env = std::max(1, std::atoi(env));
     for (int s = 0; s < nsys; ++s) {
         SysDev &sd = b->sys[s];
         const int D = b->deep_D;
         if (b->M[s] < D || !deep_offsets_fit(sd.W, sd.L)) b->deep_ok = false;
-        sd.drows = std::min<int32_t>(sd.W, drows_of[D]);
+        sd.drows = std::min<int32_t>(sd.W, drows_env ? drows_env : drows_of[D]);
         sd.dnstrips = (sd.L + deep_strip_cols(D) - 1) / deep_strip_cols(D);
         sd.dnchunks = (sd.W + sd.drows - 1) / sd.drows;
         sd.ndeep = b->M[s] / D;

@@ -147,11 +147,16 @@ def test_batch_rejects_bad_schedule(torch, cheb):
         ctx.batch_set_schedule(5, 1024, 256, 2)
 
 
+@pytest.mark.parametrize("rows", [None, "3", "22", "40"])
 @pytest.mark.parametrize("K", [1, 2, 3])
-def test_batch_deep_equals_single_system_path_bitwise(torch, cheb, K):
+def test_batch_deep_equals_single_system_path_bitwise(torch, cheb, monkeypatch, K, rows):
     # five orders per pass while every system has five left (M = 20 .. 22 here:
     # four passes), then a two-order pass or the one-order tail; the single
-    # system restricted to passes of 1, 2 and 5 orders splits M the same way
+    # system restricted to passes of 1, 2 and 5 orders splits M the same way.
+    # A site's arithmetic does not depend on the chunk heights (the batch's
+    # default, overrides, the single system's own)
+    if rows is not None:
+        monkeypatch.setenv("CHEBTD_BATCH_DEEP_ROWS", rows)
     systems = make_systems(SMALL, torch)
     ctx = cheb.Context()
     ctx.batch_create(systems, 1.0)
