@@ -121,8 +121,12 @@ static bool large_lattice(const Ctx &c) { return c.n >= (int64_t(4) << 20); }
 // sites five- and six-order passes take 52 and 56 rows (measured at
 // 512x32768: 4.49 against 4.65 ps per site and order for 28 rows, 4.14
 // against 4.40 for 32; at 4M sites the taller chunks were 7% slower, too few
-// wavefronts).  Each height makes the walk's rows + 2 (D - 1) iterations a
-// whole number of unrolled 6-iteration bodies.  CHEBTD_DEEP_ROWS overrides.
+// wavefronts).  Below 2^17 sites a pass has only tens of wavefronts, each
+// walking its chunk row after row: 4-row chunks at five orders cut a step of
+// the 10x1000 and 32x2048 ribbons from 45.7 and 48.7 us to 36.6 and 40.4
+// (no change at 64x4096).  Each height makes the walk's rows + 2 (D - 1)
+// iterations a whole number of unrolled 6-iteration bodies.
+// CHEBTD_DEEP_ROWS overrides.
 int choose_deep_rows(const Ctx &c, int D)
 {
     if (c.kind != HKind::Honeycomb) return 1;
@@ -133,8 +137,9 @@ int choose_deep_rows(const Ctx &c, int D)
     static const int small_rows[kMaxDepth + 1] = {0, 0, 0, 8, 6, 10, 14};
     static const int large_rows[kMaxDepth + 1] = {0, 0, 0, 32, 30, 28, 32};
     static const int huge_rows[kMaxDepth + 1] = {0, 0, 0, 32, 30, 52, 56};
-    const bool huge = c.n >= (int64_t(16) << 20);
-    const int r = (huge ? huge_rows : large_lattice(c) ? large_rows : small_rows)[D];
+    static const int tiny_rows[kMaxDepth + 1] = {0, 0, 0, 2, 6, 4, 2};
+    const bool huge = c.n >= (int64_t(16) << 20), tiny = c.n < (int64_t(1) << 17);
+    const int r = (huge ? huge_rows : large_lattice(c) ? large_rows : tiny ? tiny_rows : small_rows)[D];
     return (int)std::min<int64_t>(c.W, r);
 }
 
