@@ -494,6 +494,36 @@ def bench_table2(torch, P):
     return dict(workload=W.TABLE2.name, W=p["W"], seed=p["seed"], runs=runs)
 
 
+def bench_shard(torch, P, gpus=(1, 2, 4, 8), shapes=((128, 8192), (1024, 65536)), D=5):
+    """One GPU's share of a ribbon cut into N slabs along its length (the
+    sharding the design describes; this build runs on one GPU): the dominant
+    pass timed on a slab of L/N columns plus D halo columns on each side that
+    the pass recomputes (D = its orders, 5 for these M = 20 ribbons), and the
+    halo a pass would exchange per side: D columns of v_{k-1} and v_k,
+    2 D W 16 bytes.  No exchange is run or timed here."""
+    out = []
+    for (w, l) in shapes:
+        for n in gpus:
+            halo = D if n > 1 else 0
+            cols = l // n + 2 * halo
+            eps_d = torch.from_numpy(W.anderson_disorder(w, cols, 0.5, 11)).cuda()
+            ctx = P.Context()
+            ctx.honeycomb(w, cols, eps_d)
+            lo, hi = ctx.gershgorin()
+            ctx.set_bounds(lo, hi)
+            M = ctx.plan(1.0)
+            passes = ctx.plan_passes()
+            assert max(passes) == D, passes
+            ms, name, orders = ctx.time_recursion_kernel(100 if w * cols <= (1 << 22) else 20)
+            ctx.close()
+            del eps_d
+            out.append(dict(ribbon=f"{w}x{l}", gpus=n, slab=f"{w}x{cols}", M=M, passes=passes, kernel=name,
+                            us_per_pass=ms * 1e3, step_us_compute=ms * 1e3 * len(passes),
+                            halo_bytes_per_pass_per_side=2 * halo * w * 16))
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_triad(torch, total_bytes, reps):
     """A STREAM-style triad a = b + s c in float64 (torch's elementwise kernel)
     over three arrays of total_bytes together: 2 reads and 1 write per
@@ -559,7 +589,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--sections",
-                    default="main,double_well,table1,table2,holstein,batched,adjoint,polaron,sweep,cpu")
+                    default="main,double_well,table1,table2,holstein,batched,adjoint,polaron,sweep,shard,cpu")
     ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -648,6 +678,9 @@ def main():
     if "sweep" in sections:
         log("[bench] ribbon size sweep")
         extra["sweep"] = bench_sweep(torch, P, [(128, 8192), (256, 16384), (512, 32768), (1024, 65536)])
+    if "shard" in sections:
+        log("[bench] one GPU's share of a ribbon cut into 2, 4, 8 slabs")
+        extra["shard"] = bench_shard(torch, P)
     if "copy" in sections:
         log("[bench] reference copy")
         extra["copy"] = bench_copy(torch)
