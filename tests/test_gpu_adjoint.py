@@ -316,3 +316,31 @@ def test_adjoint_full_size_vs_oracle_short(torch, cheb, mode):
     Lr, gr, ur = O.adjoint(H, plan, psi0, 2, mask)
     assert rel_l2(g, gr) <= 1e-8
     assert rel_l2(u0, ur) <= 1e-10
+
+
+def test_reverse_schedule_past_offset_limit(torch, cheb):
+    # (1 + 14) n 16 B > 2^31 for a 9M-site chain: the downward schedule is
+    # refused with CHEBTD_E_ARG, and the autograd wrapper's default falls back
+    # to the recompute schedule
+    n = 9_000_000
+    x, dx = W.chain_grid(n, -0.01 * n, 0.01 * n)
+    V = torch.from_numpy(W.harmonic(x, 1e-3)).cuda()
+    ctx = cheb.Context()
+    ctx.chain1d(V, dx)
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi, 0.01)
+    ctx.plan(0.002)
+    with pytest.raises(cheb.ChebError) as err:
+        ctx.reserve_adjoint(2, cheb.ADJ_REVERSE)
+    assert err.value.code == -1  # CHEBTD_E_ARG
+    ctx.reserve_adjoint(2, cheb.ADJ_STEP)
+    ctx.close()
+    prop = cheb.Propagator("chain", 0.002, 2, (lo, hi), dx=dx)
+    Vt = V.clone().requires_grad_(True)
+    p0 = torch.from_numpy(W.gaussian_1d(x, 0.0, 50.0, 0.5)).cuda()
+    psi = cheb.ChebPropagate.apply(Vt, p0, prop)
+    L = (psi.abs() ** 2 * (torch.from_numpy(x).cuda() > 0)).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    g = Vt.grad.cpu().numpy()
+    assert np.all(np.isfinite(g)) and np.abs(g).max() > 0
