@@ -36,8 +36,9 @@
 // same three-term recursion run downwards,
 //   v_{k-j} = 2 H~ v_{k-j+1} - v_{k-j+2},
 // a second set of D windows in the same walk (exact in exact arithmetic;
-// |T_k| <= 1 on the rescaled spectrum keeps the rounding as small as the
-// forward run's).  The last level of such a pass may be the recursion's
+// with the rescaled spectrum inside [-1, 1] a rounding error grows no faster
+// run downwards than upwards, bounded by the Chebyshev polynomials of the
+// second kind).  The last level of such a pass may be the recursion's
 // level 0, u_0 = conj(g_0) gbar + H~ u_1 - u_2 with dL/dV share
 // (1/a) Re[conj(u_1) v_0]: hD and gfD carry its halved factors.
 //
