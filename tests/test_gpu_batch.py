@@ -201,8 +201,8 @@ def test_batch_pairs_needs_two_orders(torch, cheb):
 
 def test_full_batched_config_sampled(torch, cheb):
     # 256 ribbons, widths 32-128, lengths 512-4096, W in [0.1, 2]: the levels
-    # and persistent schedules agree bit for bit everywhere, the pairs schedule
-    # to rounding; three systems are checked against the oracle
+    # and persistent schedules agree bit for bit everywhere, the pairs and deep
+    # schedules to rounding; three systems are checked against the oracle
     p = W.BATCHED.params
     descs = W.batched_ribbons(p["nsys"], p["seed_base"])
     total = sum(d.n for d in descs)
@@ -237,6 +237,15 @@ def test_full_batched_config_sampled(torch, cheb):
         s["psi"].copy_(torch.from_numpy(psi0).cuda())
     say("[gpu] full batch: pairs schedule")
     ctx.batch_set_schedule(2, 2048, 256, 1)
+    ctx.batch_propagate(2, cheb.GRAPH)
+    torch.cuda.synchronize()
+    for s, ref in zip(systems, lev):
+        assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-13
+    for s, d in zip(systems, descs):
+        _, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        s["psi"].copy_(torch.from_numpy(psi0).cuda())
+    say("[gpu] full batch: deep schedule")
+    ctx.batch_set_schedule(cheb.SCHED_DEEP, 1024, 512, 1)
     ctx.batch_propagate(2, cheb.GRAPH)
     torch.cuda.synchronize()
     for s, ref in zip(systems, lev):
