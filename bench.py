@@ -27,6 +27,7 @@ import json
 import os
 import platform
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -352,8 +353,7 @@ def bench_batched(torch, P, K, seq_steps=10):
     ctx.batch_create(systems, p["dt"])
     Ms = ctx.batch_info()
     t0 = time.perf_counter()
-    best = ctx.batch_autotune(os.path.join(ROOT, "gpurun_out", "batch_tune.txt")
-                              if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    best = ctx.batch_autotune(os.path.join(tempfile.gettempdir(), "chebtd_batch_tune.txt"))
     tune_s = time.perf_counter() - t0
     site_orders = float(sum(s["width"] * s["length"] * int(M) for s, M in zip(systems, Ms)))
     ctx.batch_propagate(2, P.GRAPH | P.NO_CHECK)  # warm-up
@@ -502,7 +502,7 @@ def bench_table2(torch, P):
 
 def bench_shard(torch, P, gpus=(1, 2, 4, 8), shapes=((128, 8192), (1024, 65536)), D=5):
     """One GPU's share of a ribbon cut into N slabs along its length (the
-    sharding the design describes; this build runs on one GPU): the dominant
+    sharding the design describes; the library runs on one GPU): the dominant
     pass timed on a slab of L/N columns plus D halo columns on each side that
     the pass recomputes (D = its orders, 5 for these M = 20 ribbons), and the
     halo a pass would exchange per side: D columns of v_{k-1} and v_k,
@@ -599,7 +599,7 @@ def main():
     ap.add_argument("--mode", default="auto", choices=["auto", "direct", "graph"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(see the design notes for how the propagation would shard)", file=sys.stderr)
         sys.exit(2)
     import torch
