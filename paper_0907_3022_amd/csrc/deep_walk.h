@@ -142,10 +142,13 @@ __device__ __forceinline__ double bload1(Rsrc r, uint32_t voff, uint32_t soff)
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// CPOL: the store's cache policy bits, 0 or kStreamStore
+constexpr int kStreamStore = 2;  // non-temporal (streaming) on gfx950
+template <int CPOL = 0>
 __device__ __forceinline__ void bstore2(Rsrc r, uint32_t voff, uint32_t soff, double2 v)
 {
     using V4 = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, v), r, (int)voff, (int)soff, CPOL);
 }
 __device__ __forceinline__ void bstore1(Rsrc r, uint32_t voff, uint32_t soff, double v)
 {
@@ -182,7 +185,11 @@ __device__ __forceinline__ void phases(F &f)
 // is limited to its rows and masked to the lattice's columns.  Elsewhere a
 // level also computes the rows before its first needed one; those only feed
 // other such rows and are never stored.
-template <int EDGE, int D, bool HEAD, bool BORDER, int MODE, bool UP = false>
+// NT: the pass's vector stores stream past the caches (lattices far larger
+// than the last-level cache: measured on MI355X, five-order passes at
+// 512x32768 ran 366 -> 354 us; at 128x8192, whose vectors the next pass reads
+// from that cache, 20.3 -> 29.2 us, so smaller lattices store normally)
+template <int EDGE, int D, bool HEAD, bool BORDER, int MODE, bool UP = false, bool NT = false>
 __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32_t chunk, const DeepArgs<D> &A,
                                           double &nrm, double &en)
 {
@@ -261,7 +268,7 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
     // the store intermittently reached memory in place of the stored values.
     auto st2 = [&](Rsrc rs, int32_t row, double2 v, bool ok) {
         const uint32_t ro = (uint32_t)row * row16;
-        bstore2(rs, ro + (ok ? s16 : kOut), 0, v);
+        bstore2<NT ? kStreamStore : 0>(rs, ro + (ok ? s16 : kOut), 0, v);
     };
     const uint32_t s8 = own ? (uint32_t)x * 8u : kOut;
     auto st1 = [&](Rsrc rs, int32_t row, double v, bool ok) {
@@ -460,7 +467,7 @@ __device__ __forceinline__ void deep_walk(const OpPair &op, int32_t strip, int32
 // the rows above the chunk that the last body loads) lies inside the lattice
 // skip the border tests.  deep_dispatch maps the wavefronts of a grid of
 // 256-thread blocks to (strip, chunk).
-template <int EDGE, int D, bool HEAD, int MODE>
+template <int EDGE, int D, bool HEAD, int MODE, bool NT = false>
 __device__ __forceinline__ void deep_wave(const OpPair &op, int32_t strip, int32_t chunk, const DeepArgs<D> &A,
                                           double &nrm, double &en)
 {
@@ -472,20 +479,20 @@ __device__ __forceinline__ void deep_wave(const OpPair &op, int32_t strip, int32
         if (chunk & 1) {
             const int32_t hi = ye - 1 + D, lo = ye - 1 + (D - 1) - it - kDeepAhead;
             if (cols && lo >= 0 && hi < op.W)
-                deep_walk<EDGE, D, HEAD, false, MODE, true>(op, strip, chunk, A, nrm, en);
+                deep_walk<EDGE, D, HEAD, false, MODE, true, NT>(op, strip, chunk, A, nrm, en);
             else
-                deep_walk<EDGE, D, HEAD, true, MODE, true>(op, strip, chunk, A, nrm, en);
+                deep_walk<EDGE, D, HEAD, true, MODE, true, NT>(op, strip, chunk, A, nrm, en);
             return;
         }
     }
     const int32_t last = ys - (D - 1) + it + kDeepAhead;
     if (cols && ys - D >= 0 && last < op.W)
-        deep_walk<EDGE, D, HEAD, false, MODE>(op, strip, chunk, A, nrm, en);
+        deep_walk<EDGE, D, HEAD, false, MODE, false, NT>(op, strip, chunk, A, nrm, en);
     else
-        deep_walk<EDGE, D, HEAD, true, MODE>(op, strip, chunk, A, nrm, en);
+        deep_walk<EDGE, D, HEAD, true, MODE, false, NT>(op, strip, chunk, A, nrm, en);
 }
 
-template <int EDGE, int D, bool HEAD, int MODE>
+template <int EDGE, int D, bool HEAD, int MODE, bool NT = false>
 __device__ __forceinline__ void deep_dispatch(const OpPair &op, const DeepArgs<D> &A, double &nrm, double &en)
 {
     const int32_t gwv =
@@ -494,7 +501,7 @@ __device__ __forceinline__ void deep_dispatch(const OpPair &op, const DeepArgs<D
     const int32_t strip = cf ? gwv / op.nchunks : gwv % op.nstrips;
     const int32_t chunk = cf ? gwv % op.nchunks : gwv / op.nstrips;
     if (chunk < op.nchunks && strip < op.nstrips)  // uniform per wavefront
-        deep_wave<EDGE, D, HEAD, MODE>(op, strip, chunk, A, nrm, en);
+        deep_wave<EDGE, D, HEAD, MODE, NT>(op, strip, chunk, A, nrm, en);
 }
 
 }  // namespace chebtd

@@ -37,6 +37,9 @@ bool pair_supported(const Ctx &c);
 // launch_pair, with the weights g_k .. g_{k+D} in g (g[0] used by the head)
 OpPair make_deep_op(const Ctx &c, int rows, int D);
 int64_t deep_grid_blocks(const Ctx &c, int rows, int D);
+// whether the propagation's deep passes stream their stores past the caches:
+// from 16M sites, where the working set is far past the last-level cache
+inline bool deep_stream_stores(const Ctx &c) { return c.n >= (int64_t(16) << 20); }
 
 // The deep kernel's 32-bit buffer offsets stay unambiguous for a W x L
 // lattice: rows from -(D+1) to W+D+1 at 16 B per site, plus the 2^31 bias of

@@ -43,13 +43,13 @@ __global__ __launch_bounds__(256) void k_pair(OpPair op, const double2 *__restri
     }
 }
 
-template <int EDGE, int D, bool HEAD>
+template <int EDGE, int D, bool HEAD, bool NT>
 __global__ __launch_bounds__(256) void k_deep(OpPair op, DeepArgs<D> args, double *partials, NeFinal fin)
 {
     __shared__ double red[2 * 4];
     if (!HEAD && fin.partials && blockIdx.x == 0) finalize_ne_block(fin, nullptr, red);
     double nrm = 0.0, en = 0.0;
-    deep_dispatch<EDGE, D, HEAD, kDeepProp>(op, args, nrm, en);
+    deep_dispatch<EDGE, D, HEAD, kDeepProp, NT>(op, args, nrm, en);
     if (HEAD) {
         block_sum2(nrm, en, red);
         if (threadIdx.x == 0) {
@@ -165,14 +165,25 @@ hipError_t launch_deep_d(const Ctx &c, hipStream_t s, int rows, bool head, const
     if (fin_in && !head) fin = *fin_in;
     const dim3 grid((unsigned)nb), block(256);
     const bool zig = c.kind == HKind::Chain || c.edge == CHEBTD_ZIGZAG;
-    if (head && zig)
-        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, true>), grid, block, 0, s, op, A, partials, fin);
-    else if (head)
-        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, true>), grid, block, 0, s, op, A, partials, fin);
-    else if (zig)
-        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, false>), grid, block, 0, s, op, A, partials, fin);
-    else
-        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, false>), grid, block, 0, s, op, A, partials, fin);
+    const bool nt = deep_stream_stores(c);
+    if (nt) {
+        if (head && zig)
+            hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, true, true>), grid, block, 0, s, op, A, partials, fin);
+        else if (head)
+            hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, true, true>), grid, block, 0, s, op, A, partials, fin);
+        else if (zig)
+            hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, false, true>), grid, block, 0, s, op, A, partials, fin);
+        else
+            hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, false, true>), grid, block, 0, s, op, A, partials, fin);
+    } else if (head && zig) {
+        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, true, false>), grid, block, 0, s, op, A, partials, fin);
+    } else if (head) {
+        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, true, false>), grid, block, 0, s, op, A, partials, fin);
+    } else if (zig) {
+        hipLaunchKernelGGL((k_deep<CHEBTD_ZIGZAG, D, false, false>), grid, block, 0, s, op, A, partials, fin);
+    } else {
+        hipLaunchKernelGGL((k_deep<CHEBTD_ARMCHAIR, D, false, false>), grid, block, 0, s, op, A, partials, fin);
+    }
     return hipGetLastError();
 }
 

@@ -409,11 +409,18 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
     const int dp = pairs ? dominant_pass(*c) : 2;
     static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr",
                                   "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol"};
-    static const char *deep_names[2][kMaxDepth + 1] = {
-        {"", "", "", "k_deep<0,3,false>", "k_deep<0,4,false>", "k_deep<0,5,false>", "k_deep<0,6,false>"},
-        {"", "", "", "k_deep<1,3,false>", "k_deep<1,4,false>", "k_deep<1,5,false>", "k_deep<1,6,false>"}};
+    // [edge][streaming stores][orders per pass]
+    static const char *deep_names[2][2][kMaxDepth + 1] = {
+        {{"", "", "", "k_deep<0,3,false,false>", "k_deep<0,4,false,false>", "k_deep<0,5,false,false>",
+          "k_deep<0,6,false,false>"},
+         {"", "", "", "k_deep<0,3,false,true>", "k_deep<0,4,false,true>", "k_deep<0,5,false,true>",
+          "k_deep<0,6,false,true>"}},
+        {{"", "", "", "k_deep<1,3,false,false>", "k_deep<1,4,false,false>", "k_deep<1,5,false,false>",
+          "k_deep<1,6,false,false>"},
+         {"", "", "", "k_deep<1,3,false,true>", "k_deep<1,4,false,true>", "k_deep<1,5,false,true>",
+          "k_deep<1,6,false,true>"}}};
     const bool arm = c->kind == HKind::Honeycomb && c->edge == CHEBTD_ARMCHAIR;
-    const char *nm = (pairs && dp > 2) ? deep_names[arm ? 1 : 0][dp]
+    const char *nm = (pairs && dp > 2) ? deep_names[arm ? 1 : 0][deep_stream_stores(*c) ? 1 : 0][dp]
                      : pairs ? (arm ? names[5] : names[4])
                      : c->kind == HKind::Chain    ? names[0]
                      : c->kind == HKind::Csr      ? names[3]
