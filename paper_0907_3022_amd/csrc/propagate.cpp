@@ -67,9 +67,12 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
     double2 g[kMaxDepth + 1];
     hipError_t e;
     int64_t head_blocks;
-    // the last multi-order pass writes its two orders, v_{M-1} and v_M, into ends
+    // the last multi-order pass writes its two orders, v_{M-1} and v_M, into
+    // ends; without ends nothing reads them (the next step starts from acc),
+    // so a deep last pass writes acc alone (32 of its 104 B per site fewer)
     const bool head_last = P.size() == 1;
     double2 *h1 = ends && head_last ? ends : A, *h2 = ends && head_last ? ends + c->n : C;
+    if (head_last && !ends && h > 2) h1 = h2 = nullptr;
     if (h > 2) {
         for (int j = 0; j <= h; ++j) g[j] = weight(c, j);
         e = launch_deep(*c, s, h, c->deep_rows[h], true, nullptr, cur, h1, h2, nxt, g, ckpt, partials, nullptr);
@@ -109,7 +112,9 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
         } else {
             g[0] = make_double2(0.0, 0.0);
             for (int j = 1; j <= d; ++j) g[j] = weight(c, k + j);
-            e = launch_deep(*c, s, d, c->deep_rows[d], false, X, Y, F1, F2, nxt, g, nullptr, nullptr, f);
+            const bool last = i + 1 == P.size() && !ends;
+            e = launch_deep(*c, s, d, c->deep_rows[d], false, X, Y, last ? nullptr : F1, last ? nullptr : F2, nxt,
+                            g, nullptr, nullptr, f);
         }
         if (e != hipSuccess) return e;
         k += d;
