@@ -224,6 +224,9 @@ __global__ __launch_bounds__(256) void k_batch_deep(const SysDev *__restrict__ s
         A.out2 = odd ? cur : sd.C;
     }
     A.acc = nxt;
+    // the system's final pass (no pairs or tail after it): nothing reads its
+    // two orders, so only acc is written
+    if (pass == sd.ndeep - 1 && sd.M == sd.ndeep * D) A.out1 = A.out2 = nullptr;
 #pragma unroll
     for (int j = 0; j <= D; ++j) A.w.g[j] = (HEAD || j > 0) ? ldg(g, k + j) : make_double2(0.0, 0.0);
     double nrm = 0.0, en = 0.0;
