@@ -302,16 +302,23 @@ int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int bloc
                               int wg_per_cu);
 
 /* Time candidate schedules on the real batch (a few steps each, the
- * systems' psi are saved and restored) and keep the fastest.  If
+ * systems' psi are saved and restored, also when the search fails; a
+ * candidate that is refused or times out is skipped) and keep the fastest.  If
  * cache_path is non-NULL the choice is read from / appended to that text
  * file, keyed by the batch's shape.  Synchronises.  best_out (int[4], may be
  * NULL) receives mode, tile_rows, block, wg_per_cu. */
 int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out);
 
-/* Advance every system of the batch by K steps.  flags: CHEBTD_GRAPH
- * replays a captured hipGraph per pair of steps; CHEBTD_NO_CHECK skips the
- * final synchronisation that reports CHEBTD_E_TIMEOUT. */
-int chebtd_batch_propagate(chebtd_ctx *ctx, int64_t K, unsigned flags);
+/* Advance every system of the batch by K steps.  psi_dev: NULL to propagate
+ * the states bound before (at chebtd_batch_create or by an earlier call), or
+ * a host array of nsys device pointers (complex128[width*length] each, in
+ * place): system s then propagates psi_dev[s], in this call and later ones,
+ * without re-planning (the kernels and a captured graph read the states from
+ * the batch's device table, which is re-uploaded on the stream when the
+ * pointers change).  K = 0 only re-binds.  flags: CHEBTD_GRAPH replays a
+ * captured hipGraph per pair of steps; CHEBTD_NO_CHECK skips the final
+ * synchronisation that reports CHEBTD_E_TIMEOUT. */
+int chebtd_batch_propagate(chebtd_ctx *ctx, double *const *psi_dev, int64_t K, unsigned flags);
 
 /* Number of systems and, per system, its order M (int[nsys], may be NULL). */
 int chebtd_batch_info(const chebtd_ctx *ctx, int *nsys, int *M_host);
@@ -359,6 +366,18 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode);
  * forward vectors downwards.  The modes group the levels differently and
  * agree to rounding, not bit for bit. */
 int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev);
+
+/* Every chebtd_propagate call with CHEBTD_KEEP_CHECKPOINTS overwrites the
+ * stored trajectory and numbers the run (1, 2, ... per context).
+ * chebtd_checkpoint_run sets *run_id to the number of the run whose
+ * checkpoints are stored and valid for the current plan, or 0 if none (no
+ * such run since chebtd_reserve_adjoint, or a new Hamiltonian or plan since).
+ * chebtd_adjoint_run is chebtd_adjoint for that run only: it returns
+ * CHEBTD_E_STATE, touching neither gbar_dev nor dLdV_dev, if run_id is not
+ * the stored run (its checkpoints were overwritten by a later run).
+ * run_id = 0 accepts the stored run, as chebtd_adjoint does. */
+int chebtd_checkpoint_run(const chebtd_ctx *ctx, int64_t *run_id);
+int chebtd_adjoint_run(chebtd_ctx *ctx, int64_t run_id, double *gbar_dev, double *dLdV_dev);
 
 /* ======================================================================= */
 /* Measurement helpers                                                      */

@@ -79,10 +79,12 @@ _SIGS = {
                                       C.c_double, C.c_double]),
     "chebtd_batch_set_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
     "chebtd_batch_autotune": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int)]),
-    "chebtd_batch_propagate": (C.c_int, [C.c_void_p, C.c_int64, C.c_uint]),
+    "chebtd_batch_propagate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint]),
     "chebtd_batch_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.c_void_p]),
     "chebtd_reserve_adjoint": (C.c_int, [C.c_void_p, C.c_int64, C.c_int]),
     "chebtd_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chebtd_checkpoint_run": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "chebtd_adjoint_run": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "chebtd_time_recursion_kernel": (C.c_int, [C.c_void_p, C.c_int, C.c_uint, C.POINTER(C.c_double),
                                                C.POINTER(C.c_char_p), C.POINTER(C.c_int)]),
 }

@@ -282,6 +282,7 @@ class Context:
         self._check(self._lib.chebtd_batch_create(self.h, len(systems), arr, float(dt),
                                                   float(alpha), float(tol)))
         self._bkeep = keep
+        self._bsizes = [s["width"] * s["length"] for s in systems]
         return self
 
     def batch_set_schedule(self, mode: int, tile_rows: int, block: int, wg_per_cu: int = 2):
@@ -294,8 +295,19 @@ class Context:
         self._check(self._lib.chebtd_batch_autotune(self.h, path, best))
         return tuple(best)
 
-    def batch_propagate(self, K: int, flags: int = 0):
-        self._check(self._lib.chebtd_batch_propagate(self.h, int(K), int(flags)))
+    def batch_propagate(self, K: int, flags: int = 0, psi=None):
+        """psi: None (the bound states) or one complex128 CUDA tensor per
+        system, propagated in place and bound for later calls."""
+        arr = None
+        if psi is not None:
+            torch = _torch()
+            if len(psi) != len(self._bsizes):
+                raise ValueError("need one state per system")
+            arr = (C.c_void_p * len(psi))()
+            for i, (p, n) in enumerate(zip(psi, self._bsizes)):
+                arr[i] = _need(p, torch.complex128, n, f"psi[{i}]").value
+            self._bkeep = [t for t in self._bkeep[0::2]] + list(psi)
+        self._check(self._lib.chebtd_batch_propagate(self.h, arr, int(K), int(flags)))
 
     def batch_info(self):
         ns = C.c_int()
@@ -308,11 +320,22 @@ class Context:
     def reserve_adjoint(self, max_steps: int, mode: int = L.ADJ_STEP):
         self._check(self._lib.chebtd_reserve_adjoint(self.h, int(max_steps), int(mode)))
 
-    def adjoint(self, gbar, dLdV):
+    def checkpoint_run(self) -> int:
+        """Number of the checkpointing run whose trajectory is stored (0: none)."""
+        rid = C.c_int64()
+        self._check(self._lib.chebtd_checkpoint_run(self.h, C.byref(rid)))
+        return rid.value
+
+    def adjoint(self, gbar, dLdV, run: int | None = None):
+        """run: the checkpointing run the gradient is for (checked); None
+        takes the stored one."""
         torch = _torch()
         pg = _need(gbar, torch.complex128, self.n, "gbar")
         pd = _need(dLdV, torch.float64, self.n, "dLdV")
-        self._check(self._lib.chebtd_adjoint(self.h, pg, pd))
+        if run is None:
+            self._check(self._lib.chebtd_adjoint(self.h, pg, pd))
+        else:
+            self._check(self._lib.chebtd_adjoint_run(self.h, int(run), pg, pd))
 
     # -- measurement ---------------------------------------------------------------------
     def time_recursion_kernel(self, launches: int = 100, flags: int = 0):

@@ -37,6 +37,7 @@ class Propagator:
         self.alpha, self.tol, self.adjoint_mode = alpha, tol, adjoint_mode
         self.ctx = context or Context()
         self.M = None
+        self.run = 0
 
     def _setup(self, V):
         if self.kind == "chain":
@@ -47,6 +48,8 @@ class Propagator:
         self.M = self.ctx.plan(self.dt, self.tol)
 
     def forward(self, V, psi0, keep=True):
+        """psi after K steps; with keep, the trajectory is stored for one
+        backward and self.run numbers that run."""
         self._setup(V)
         if keep and self.adjoint_mode is None:
             try:
@@ -59,13 +62,23 @@ class Propagator:
             self.ctx.reserve_adjoint(self.K, self.adjoint_mode)
         psi = psi0.detach().clone().contiguous()
         self.ctx.propagate(psi, self.K, flags=L.KEEP_CHECKPOINTS if keep else 0)
+        self.run = self.ctx.checkpoint_run() if keep else 0
         return psi
 
-    def backward(self, gbar, V):
-        """gbar: dL/dpsi_K (torch convention); returns (dL/dV, dL/dpsi_0)."""
+    def backward(self, gbar, V, psi0=None, run=None):
+        """gbar: dL/dpsi_K (torch convention); returns (dL/dV, dL/dpsi_0).
+        run: the checkpointing run of the forward pass this gradient belongs
+        to.  If the context has stored another trajectory since (the same
+        propagator applied again before this backward), the forward pass is
+        run again from V and psi0 so the adjoint sees its own trajectory."""
+        if run is not None and self.ctx.checkpoint_run() != run:
+            if psi0 is None:
+                raise RuntimeError("the stored trajectory belongs to another run and psi0 is unknown")
+            self.forward(V, psi0, keep=True)
+            run = self.run
         g = gbar.detach().clone().contiguous().to(torch.complex128)
         dV = torch.zeros_like(V, dtype=torch.float64)
-        self.ctx.adjoint(g, dV)
+        self.ctx.adjoint(g, dV, run=run)
         return dV, g
 
 
@@ -75,11 +88,12 @@ class ChebPropagate(torch.autograd.Function):
         keep = V.requires_grad or psi0.requires_grad
         out = prop.forward(V.detach(), psi0, keep=keep)
         fctx.prop = prop
-        fctx.save_for_backward(V)
+        fctx.run = prop.run
+        fctx.save_for_backward(V, psi0)
         return out
 
     @staticmethod
     def backward(fctx, grad_out):
-        (V,) = fctx.saved_tensors
-        dV, dpsi0 = fctx.prop.backward(grad_out, V.detach())
+        V, psi0 = fctx.saved_tensors
+        dV, dpsi0 = fctx.prop.backward(grad_out, V.detach(), psi0.detach(), fctx.run)
         return dV, dpsi0, None

@@ -30,6 +30,7 @@ struct AdjState {
     int64_t plan_version = -1;
     int64_t last_K = 0;   // steps stored by the last checkpointing run
     int64_t ckpt_version = -1;
+    int64_t ckpt_run = 0;  // number of that run (Ctx::run_seq), 0: none
     DevBuf ckpt;   // psi_s, s < max_steps
     DevBuf vbuf;   // recompute buffer
     DevBuf pairs;  // (v_{j-1}, v_j) per segment (sqrt mode)
@@ -49,17 +50,37 @@ void adj_destroy(Ctx *c)
     c->adj = nullptr;
 }
 
+// Start a checkpointing run of K steps: false if the storage is missing, too
+// small or sized for another plan.  The run gets the next number; the
+// adjoint refuses to run for any other.
+bool adj_begin_run(Ctx *c, int64_t K)
+{
+    AdjState *a = c->adj;
+    if (!a || K > a->max_steps || a->plan_version != c->plan_version) return false;
+    a->last_K = K;
+    a->ckpt_version = c->plan_version;
+    a->ckpt_run = ++c->run_seq;
+    return true;
+}
+
 // Checkpoint slot of `step` for a run of K steps, or null if the storage is
-// missing or too small.  Calling it for step 0 marks a checkpointing run.
+// missing or too small.
 double2 *adj_checkpoint(Ctx *c, int64_t step, int64_t K)
 {
     AdjState *a = c->adj;
     if (!a || K > a->max_steps || a->plan_version != c->plan_version) return nullptr;
-    if (step == 0) {
-        a->last_K = K;
-        a->ckpt_version = c->plan_version;
-    }
     return static_cast<double2 *>(a->ckpt.p) + (size_t)step * (size_t)c->n;
+}
+
+// Number of the checkpointing run the adjoint would use now, 0 if none (no
+// run since the storage was reserved, or the plan changed since).
+int64_t adj_current_run(const Ctx *c)
+{
+    const AdjState *a = c->adj;
+    if (!a || !c->has_plan || a->plan_version != c->plan_version || a->ckpt_version != c->plan_version ||
+        a->last_K < 1)
+        return 0;
+    return a->ckpt_run;
 }
 
 // Slot of (v_{M-1}, v_M) of `step` (2 n values) for the reverse schedule, or
@@ -343,19 +364,36 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
     a->plan_version = c->plan_version;
     a->last_K = 0;
     a->ckpt_version = -1;
+    a->ckpt_run = 0;
+    return CHEBTD_OK;
+}
+
+int chebtd_checkpoint_run(const chebtd_ctx *ctx, int64_t *run_id)
+{
+    if (!ctx || !run_id) return fail(nullptr, CHEBTD_E_ARG, "chebtd_checkpoint_run: null pointer");
+    *run_id = adj_current_run(static_cast<const Ctx *>(ctx));
     return CHEBTD_OK;
 }
 
 int chebtd_adjoint(chebtd_ctx *ctx, double *gbar_dev, double *dLdV_dev)
 {
+    return chebtd_adjoint_run(ctx, 0, gbar_dev, dLdV_dev);
+}
+
+int chebtd_adjoint_run(chebtd_ctx *ctx, int64_t run_id, double *gbar_dev, double *dLdV_dev)
+{
     if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
     Ctx *c = static_cast<Ctx *>(ctx);
     AdjState *a = c->adj;
     if (!gbar_dev || !dLdV_dev) return fail(c, CHEBTD_E_ARG, "chebtd_adjoint: null pointer");
-    if (!a || !c->has_plan || a->plan_version != c->plan_version || a->ckpt_version != c->plan_version ||
-        a->last_K < 1)
+    const int64_t cur = adj_current_run(c);
+    if (cur == 0)
         return fail(c, CHEBTD_E_STATE,
                     "chebtd_adjoint: run chebtd_propagate with CHEBTD_KEEP_CHECKPOINTS on the current plan first");
+    if (run_id != 0 && run_id != cur)
+        return fail(c, CHEBTD_E_STATE,
+                    "chebtd_adjoint: the checkpoints of run " + std::to_string(run_id) +
+                        " were overwritten (the stored run is " + std::to_string(cur) + ")");
     hipStream_t s = c->stream;
     const int M = c->M;
     const int64_t n = c->n;

@@ -428,6 +428,10 @@ int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0, cons
     c->hol_t = t;
     c->hol_w0 = w0;
     c->hol_periodic = periodic ? 1 : 0;
+    // tuning and test override: electron sites per thread of the order walk
+    // (the size-based choice groups sites only past 2^20 configurations)
+    c->hol_spt = 0;
+    if (const char *env = std::getenv("CHEBTD_HOL_SPT")) c->hol_spt = std::max(0, std::atoi(env));
     return ensure_partials(c);
 }
 

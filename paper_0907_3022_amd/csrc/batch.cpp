@@ -58,6 +58,11 @@ struct BatchState {
     int64_t spin_limit = 0;  // wall-clock ticks a dependency wait may take
     hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;
+    // re-binding the systems' states: a pinned mirror of the system table,
+    // and an event on the last upload from it
+    SysDev *sys_pinned = nullptr;
+    hipEvent_t sys_ev = nullptr;
+    bool sys_ev_pending = false;
 };
 
 static void drop_graph(BatchState *b)
@@ -72,6 +77,11 @@ void batch_destroy(Ctx *c)
     if (!b) return;
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->sys_ev) {
+        (void)hipEventSynchronize(b->sys_ev);
+        (void)hipEventDestroy(b->sys_ev);
+    }
+    if (b->sys_pinned) (void)hipHostFree(b->sys_pinned);
     for (DevBuf *d : {&b->sys_dev, &b->gamma_dev, &b->work, &b->blk_sys, &b->blk_tile, &b->q_level_off,
                       &b->q_level_active, &b->q_tile_prefix, &b->q_order, &b->pblk_sys, &b->pblk_wave0,
                       &b->tblk_sys, &b->tblk_tile, &b->dblk_sys, &b->dblk_wave0, &b->dpblk_sys, &b->dpblk_wave0,
@@ -516,13 +526,55 @@ int chebtd_batch_set_schedule(chebtd_ctx *ctx, int mode, int tile_rows, int bloc
     return retile ? build_tables(c, b) : CHEBTD_OK;
 }
 
-int chebtd_batch_propagate(chebtd_ctx *ctx, int64_t K, unsigned flags)
+// Point the systems at new states: the kernels (and a captured graph) read
+// psi from the device system table, so an upload of the table on the stream
+// re-binds them for every later launch.
+static int rebind_states(Ctx *c, BatchState *b, double *const *psi_dev)
+{
+    bool same = true;
+    for (int s = 0; s < b->nsys; ++s) {
+        if (!psi_dev[s]) return fail(c, CHEBTD_E_ARG, "chebtd_batch_propagate: null state of system " +
+                                                          std::to_string(s));
+        same = same && reinterpret_cast<double2 *>(psi_dev[s]) == b->sys[s].psi;
+    }
+    if (same) return CHEBTD_OK;
+    const size_t bytes = b->sys.size() * sizeof(SysDev);
+    hipError_t e = hipSuccess;
+    if (!b->sys_pinned) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&b->sys_pinned), bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            b->sys_pinned = nullptr;
+            return fail(c, CHEBTD_E_OOM, "chebtd_batch_propagate: pinned system table");
+        }
+        e = hipEventCreateWithFlags(&b->sys_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            b->sys_ev = nullptr;
+            return hip_fail(c, e, "chebtd_batch_propagate: event");
+        }
+    }
+    // the previous upload may still be reading the mirror
+    if (b->sys_ev_pending && (e = hipEventSynchronize(b->sys_ev)) != hipSuccess)
+        return hip_fail(c, e, "chebtd_batch_propagate: previous table upload");
+    for (int s = 0; s < b->nsys; ++s) b->sys[s].psi = reinterpret_cast<double2 *>(psi_dev[s]);
+    std::memcpy(b->sys_pinned, b->sys.data(), bytes);
+    e = hipMemcpyAsync(b->sys_dev.p, b->sys_pinned, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->sys_ev, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "chebtd_batch_propagate: table upload");
+    b->sys_ev_pending = true;
+    return CHEBTD_OK;
+}
+
+int chebtd_batch_propagate(chebtd_ctx *ctx, double *const *psi_dev, int64_t K, unsigned flags)
 {
     if (!ctx) return fail(nullptr, CHEBTD_E_ARG, "null context");
     Ctx *c = static_cast<Ctx *>(ctx);
     BatchState *b = c->batch;
     if (!b) return fail(c, CHEBTD_E_STATE, "chebtd_batch_propagate: no batch");
     if (K < 0) return fail(c, CHEBTD_E_ARG, "chebtd_batch_propagate: K < 0");
+    if (psi_dev) {
+        const int rc = rebind_states(c, b, psi_dev);
+        if (rc) return rc;
+    }
     if (K == 0) return CHEBTD_OK;
     int rc = run_steps(c, b, K, (flags & CHEBTD_GRAPH) != 0);
     if (rc) return rc;
@@ -609,22 +661,31 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
                     for (int wg : {2, 4}) cands.push_back({CHEBTD_SCHED_PERSISTENT, tile, block, wg});
         double best_ms = 1e300;
         for (const Cand &cd : cands) {
+            // a candidate that fails its own way (refused, or a persistent
+            // schedule whose dependency wait ran out) is skipped; a HIP
+            // failure ends the search.  The states are restored either way.
             rc = chebtd_batch_set_schedule(ctx, cd.mode, cd.tile, cd.block, cd.wg);
-            if (rc) break;
-            rc = run_steps(c, b, 1, false);  // warm-up
+            if (!rc) rc = run_steps(c, b, 1, false);  // warm-up
             if (!rc) rc = check_timeout(c, b);
-            if (rc) break;
-            e = hipEventRecord(c->ev_a, s);
-            if (e == hipSuccess) rc = run_steps(c, b, 2, false);
-            if (e == hipSuccess && !rc) e = hipEventRecord(c->ev_b, s);
-            if (e == hipSuccess && !rc) e = hipEventSynchronize(c->ev_b);
             float ms = 0.f;
-            if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, c->ev_a, c->ev_b);
-            if (e != hipSuccess) {
-                rc = hip_fail(c, e, "autotune timing");
+            if (!rc) {
+                e = hipEventRecord(c->ev_a, s);
+                if (e == hipSuccess) rc = run_steps(c, b, 2, false);
+                if (e == hipSuccess && !rc) e = hipEventRecord(c->ev_b, s);
+                if (e == hipSuccess && !rc) e = hipEventSynchronize(c->ev_b);
+                if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, c->ev_a, c->ev_b);
+                if (e != hipSuccess) rc = hip_fail(c, e, "autotune timing");
+                if (!rc) rc = check_timeout(c, b);
+            }
+            const hipError_t er = copy_all(false);
+            if (er != hipSuccess) {
+                rc = hip_fail(c, er, "autotune restore");
                 break;
             }
-            if (!rc) rc = check_timeout(c, b);
+            if (rc == CHEBTD_E_ARG || rc == CHEBTD_E_TIMEOUT) {
+                rc = CHEBTD_OK;
+                continue;
+            }
             if (rc) break;
             const bool slow_persistent = cd.mode == CHEBTD_SCHED_PERSISTENT && ms > 2.0 * best_ms;
             if (ms < best_ms) {
@@ -634,20 +695,17 @@ int chebtd_batch_autotune(chebtd_ctx *ctx, const char *cache_path, int *best_out
                 best[2] = cd.block;
                 best[3] = cd.wg;
             }
-            e = copy_all(false);
-            if (e != hipSuccess) {
-                rc = hip_fail(c, e, "autotune restore");
-                break;
-            }
             if (slow_persistent) break;
         }
-        if (!rc) {
+        {
+            // every exit restores the caller's states before the backup goes
             e = copy_all(false);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) rc = hip_fail(c, e, "autotune restore");
+            if (e != hipSuccess && !rc) rc = hip_fail(c, e, "autotune restore");
         }
         release(save);
         if (rc) return rc;
+        if (best[0] < 0) return fail(c, CHEBTD_E_ARG, "chebtd_batch_autotune: no schedule ran on this batch");
         if (cache_path) {
             std::ofstream out(cache_path, std::ios::app);
             out << keystr << ' ' << best[0] << ' ' << best[1] << ' ' << best[2] << ' ' << best[3] << '\n';

@@ -200,7 +200,7 @@ struct CsrRow {
     }
 };
 
-// Matrix-free Holstein rows (eq. (ghm)); state i = r*L + site.
+// Matrix-free Holstein rows (eq. (ghm)); state i = site * nconf + r.
 struct HolRow {
     __device__ static __forceinline__ int64_t row(const OpHol &op)
     {

@@ -109,6 +109,7 @@ struct Ctx {
     int hol_periodic = 0;
     double hol_t = 0.0, hol_w0 = 0.0;
     const double *hol_delta = nullptr;  // per-step Delta_i during a time-dependent run
+    int hol_spt = 0;  // electron sites per thread of the walk; 0: chosen by size
 
     // bounds and plan
     bool has_bounds = false;
@@ -136,6 +137,7 @@ struct Ctx {
     double *pinned = nullptr;  // host pinned double[16]
     double check_tol = 1e-6;
     int64_t plan_version = 0;  // bumped by every plan
+    int64_t run_seq = 0;       // numbers the checkpointing propagation runs
 
     // graph cache for CHEBTD_GRAPH
     hipStream_t cap_stream = nullptr;

@@ -598,7 +598,8 @@ hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *
         // configurations: 12.0 ms against 14.7 ms for all 18)
         const int64_t C = c.hol_nconf, L = c.hol_L;
         const int64_t groups = C <= ((int64_t)1 << 20) ? 1 : (L + 8) / 9;
-        const int spt = (int)((L + groups - 1) / groups);
+        const int spt = c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, L)
+                                      : (int)((L + groups - 1) / groups);
         const int64_t ngrp = (L + spt - 1) / spt;
         const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), block, 0, s, make_hol(c), spt, vk, vprev, acc, g);

@@ -17,6 +17,7 @@ int hip_fail(Ctx *c, hipError_t e, const char *what);
 int ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what);
 void release(DevBuf &b);
 void drop_graphs(Ctx *c);
+bool adj_begin_run(Ctx *c, int64_t K);                         // adjoint.cpp
 double2 *adj_checkpoint(Ctx *c, int64_t step, int64_t K);  // adjoint.cpp
 double2 *adj_step_ends(Ctx *c, int64_t step);              // adjoint.cpp
 }  // namespace chebtd
@@ -219,7 +220,7 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
     if (!psi_dev || K < 0) return fail(c, CHEBTD_E_ARG, "chebtd_propagate: need psi and K >= 0");
     if (K == 0) return CHEBTD_OK;
     const bool keep = (flags & CHEBTD_KEEP_CHECKPOINTS) != 0;
-    if (keep && !adj_checkpoint(c, 0, K))
+    if (keep && !adj_begin_run(c, K))
         return fail(c, CHEBTD_E_STATE,
                     "chebtd_propagate: checkpoints need chebtd_reserve_adjoint with max_steps >= K");
     const bool check = (flags & CHEBTD_NO_CHECK) == 0;

@@ -49,6 +49,10 @@ def test_null_context_is_rejected_without_gpu():
     assert lib.chebtd_set_bounds(None, 0.0, 1.0, 0.01) == L.E_ARG
     assert lib.chebtd_propagate(None, dummy, 1, None, None, 0) == L.E_ARG
     assert lib.chebtd_adjoint(None, dummy, dummy) == L.E_ARG
+    assert lib.chebtd_adjoint_run(None, 1, dummy, dummy) == L.E_ARG
+    rid = C.c_int64(7)
+    assert lib.chebtd_checkpoint_run(None, C.byref(rid)) == L.E_ARG
+    assert lib.chebtd_batch_propagate(None, None, 1, 0) == L.E_ARG
     assert lib.chebtd_create(None, None) == L.E_ARG
     assert "null" in L.last_error(None)
     assert lib.chebtd_destroy(None) == L.OK

@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from test_gpu_parity import assert_state_close
 
 pytestmark = pytest.mark.gpu
 
@@ -33,15 +34,29 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def chain_inputs(n, a=0.05, b=5.0):
+def chain_inputs(n, a=0.05, b=5.0, dense=False):
+    """dense: a random state and random weights w_i in L = sum w_i |psi_i|^2,
+    so that gbar, every adjoint vector and dL/dV are nonzero on every site."""
     x, dx, V, psi0 = W.double_well_inputs(n, -20.0, 20.0, a, b, -5.0, 1.0, 1.0)
     mask = (x > 0).astype(np.float64)
+    if dense:
+        psi0, mask = W.random_state(n, 500 + n), W.random_weights(n, 600 + n)
     return dx, V, psi0, mask
 
 
-def ribbon_inputs(width, length, Wd=0.5, seed=0):
+def ribbon_inputs(width, length, Wd=0.5, seed=0, dense=False):
     eps, psi0 = W.ribbon_inputs(width, length, Wd, seed)
-    return eps, psi0, W.right_half_mask_ribbon(width, length)
+    mask = W.right_half_mask_ribbon(width, length)
+    if dense:
+        n = width * length
+        psi0, mask = W.random_state(n, 700 + seed), W.random_weights(n, 800 + seed)
+    return eps, psi0, mask
+
+
+def assert_grad_close(g, gr, tol=1e-8):
+    """rel-L2 <= tol and every site within tol * max|gr|."""
+    assert rel_l2(g, gr) <= tol
+    assert np.abs(g - gr).max() <= tol * np.abs(gr).max()
 
 
 def gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, mode):
@@ -59,10 +74,11 @@ def gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, mode):
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
 @pytest.mark.parametrize("case", ["chain", "zigzag", "armchair", "chain_large"])
-def test_adjoint_matches_oracle(torch, cheb, case, mode):
+@pytest.mark.parametrize("dense", [False, True])
+def test_adjoint_matches_oracle(torch, cheb, case, mode, dense):
     if case.startswith("chain"):
         n = 300 if case == "chain" else 9001
-        dx, V, psi0, mask = chain_inputs(n)
+        dx, V, psi0, mask = chain_inputs(n, dense=dense)
         H = O.chain1d(V, dx)
         geom = dict(dx=dx)
         kind = "chain"
@@ -70,7 +86,7 @@ def test_adjoint_matches_oracle(torch, cheb, case, mode):
         dt = 30.0 / (0.5 * 1.01 * (hi - lo))   # order ~ 64
     else:
         w, l = 8, 60
-        V, psi0, mask = ribbon_inputs(w, l)
+        V, psi0, mask = ribbon_inputs(w, l, dense=dense)
         H = O.honeycomb(w, l, V, edge=case)
         geom = dict(width=w, length=l, edge=case)
         kind = "honeycomb"
@@ -82,8 +98,8 @@ def test_adjoint_matches_oracle(torch, cheb, case, mode):
     assert prop.M == plan.M
     Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
     assert Lg == pytest.approx(Lr, rel=1e-10)
-    assert rel_l2(g, gr) <= 1e-8
-    assert rel_l2(u0, ur) <= 1e-10
+    assert_grad_close(g, gr)
+    assert_state_close(u0, ur)
 
 
 # z = a dt from 1e-9 to 0.3 gives M = 1, 2, 3, 4, 5, 6, 10: the reverse sweep
@@ -148,14 +164,14 @@ def test_adjoint_reverse_depths_match_oracle(torch, cheb, monkeypatch, rev_depth
     if rows is not None:
         monkeypatch.setenv("CHEBTD_REV_ROWS", str(rows))
     if case == "chain":
-        dx, V, psi0, mask = chain_inputs(5003)
+        dx, V, psi0, mask = chain_inputs(5003, dense=True)
         H = O.chain1d(V, dx)
         geom, kind = dict(dx=dx), "chain"
         lo, hi = H.gershgorin()
         dt = 12.0 / (0.5 * 1.01 * (hi - lo))
     else:
         w, l = 37, 130
-        V, psi0, mask = ribbon_inputs(w, l)
+        V, psi0, mask = ribbon_inputs(w, l, dense=True)
         H = O.honeycomb(w, l, V, edge=case)
         geom, kind = dict(width=w, length=l, edge=case), "honeycomb"
         lo, hi = H.gershgorin()
@@ -166,8 +182,8 @@ def test_adjoint_reverse_depths_match_oracle(torch, cheb, monkeypatch, rev_depth
     assert prop.M == plan.M and plan.M >= 14
     Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
     assert Lg == pytest.approx(Lr, rel=1e-10)
-    assert rel_l2(g, gr) <= 1e-8
-    assert rel_l2(u0, ur) <= 1e-10
+    assert_grad_close(g, gr)
+    assert_state_close(u0, ur)
 
 
 # the forward run keeps each step's (v_{M-1}, v_M) for the downward schedule:
@@ -222,14 +238,14 @@ def test_adjoint_depths_match_oracle(torch, cheb, monkeypatch, adj_depth, rec_de
     monkeypatch.setenv("CHEBTD_ADJ_DEPTH", str(adj_depth))
     monkeypatch.setenv("CHEBTD_REC_DEPTH", str(rec_depth))
     if case == "chain":
-        dx, V, psi0, mask = chain_inputs(5003)
+        dx, V, psi0, mask = chain_inputs(5003, dense=True)
         H = O.chain1d(V, dx)
         geom, kind = dict(dx=dx), "chain"
         lo, hi = H.gershgorin()
         dt = 12.0 / (0.5 * 1.01 * (hi - lo))
     else:
         w, l = 37, 130
-        V, psi0, mask = ribbon_inputs(w, l)
+        V, psi0, mask = ribbon_inputs(w, l, dense=True)
         H = O.honeycomb(w, l, V, edge=case)
         geom, kind = dict(width=w, length=l, edge=case), "honeycomb"
         lo, hi = H.gershgorin()
@@ -240,8 +256,8 @@ def test_adjoint_depths_match_oracle(torch, cheb, monkeypatch, adj_depth, rec_de
     assert prop.M == plan.M and plan.M >= 14
     Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
     assert Lg == pytest.approx(Lr, rel=1e-10)
-    assert rel_l2(g, gr) <= 1e-8
-    assert rel_l2(u0, ur) <= 1e-10
+    assert_grad_close(g, gr)
+    assert_state_close(u0, ur)
 
 
 def _fd_check(torch, cheb, kind, geom, V, psi0, mask, bounds, dt, K, sites, h, rtol_floor):
@@ -298,14 +314,17 @@ def test_adjoint_config_chain_65536_fd(torch, cheb):
     _fd_check(torch, cheb, "chain", dict(dx=dx), V, psi0, mask, (lo, hi), dt, p["K"], sites, p["h"], 1e-4)
 
 
-@pytest.mark.parametrize("mode", [0, 2])
-def test_adjoint_full_size_vs_oracle_short(torch, cheb, mode):
+@pytest.mark.parametrize("mode,state", [(0, "packet"), (2, "packet"), (2, "dense"), (1, "dense")])
+def test_adjoint_full_size_vs_oracle_short(torch, cheb, mode, state):
     # full 256 x 4096 ribbon, order ~64, 2 steps: GPU reverse sweep vs the oracle's
     p = W.ADJOINT.params
     w, l = p["width"], p["length"]
-    V, psi0, _ = ribbon_inputs(w, l, p["W"], 0)
-    # two steps barely move the packet: weigh the half of it ahead of x0 = l/4
-    mask = (np.tile(np.arange(l), w) > l / 4).astype(np.float64)
+    if state == "dense":
+        V, psi0, mask = ribbon_inputs(w, l, p["W"], 0, dense=True)
+    else:
+        V, psi0, _ = ribbon_inputs(w, l, p["W"], 0)
+        # two steps barely move the packet: weigh the half of it ahead of x0 = l/4
+        mask = (np.tile(np.arange(l), w) > l / 4).astype(np.float64)
     H = O.honeycomb(w, l, V)
     lo, hi = H.gershgorin()
     dt = 30.5 / (0.5 * 1.01 * (hi - lo))
@@ -314,8 +333,8 @@ def test_adjoint_full_size_vs_oracle_short(torch, cheb, mode):
     plan = O.Plan(lo, hi, dt)
     assert prop.M == plan.M and 60 <= plan.M <= 70
     Lr, gr, ur = O.adjoint(H, plan, psi0, 2, mask)
-    assert rel_l2(g, gr) <= 1e-8
-    assert rel_l2(u0, ur) <= 1e-10
+    assert_grad_close(g, gr)
+    assert_state_close(u0, ur)
 
 
 def test_reverse_schedule_past_offset_limit(torch, cheb):
@@ -344,3 +363,71 @@ def test_reverse_schedule_past_offset_limit(torch, cheb):
     torch.cuda.synchronize()
     g = Vt.grad.cpu().numpy()
     assert np.all(np.isfinite(g)) and np.abs(g).max() > 0
+
+
+def test_adjoint_refuses_overwritten_run(torch, cheb):
+    # each checkpointing run is numbered; the adjoint of an overwritten run is
+    # refused (CHEBTD_E_STATE) and the stored run's adjoint is the oracle's
+    w, l = 9, 70
+    V, psi0, mask = ribbon_inputs(w, l, dense=True)
+    H = O.honeycomb(w, l, V)
+    lo, hi = H.gershgorin()
+    ctx = cheb.Context()
+    Vd = torch.from_numpy(V.copy()).cuda()
+    ctx.honeycomb(w, l, Vd)
+    ctx.set_bounds(lo, hi)
+    ctx.plan(1.3)
+    ctx.reserve_adjoint(3, cheb.ADJ_REVERSE)
+    assert ctx.checkpoint_run() == 0
+    psi_b0 = W.random_state(w * l, 1234)
+    runs = []
+    for p0 in (psi_b0, psi0):
+        psi = torch.from_numpy(p0.copy()).cuda()
+        ctx.propagate(psi, 3, flags=cheb.KEEP_CHECKPOINTS)
+        runs.append(ctx.checkpoint_run())
+    assert 0 < runs[0] < runs[1]
+    m = torch.from_numpy(mask).cuda()
+    gbar = (2.0 * m * psi).contiguous()
+    dV = torch.zeros_like(Vd)
+    with pytest.raises(cheb.ChebError) as err:
+        ctx.adjoint(gbar.clone(), dV, run=runs[0])
+    assert err.value.code == -5  # CHEBTD_E_STATE
+    assert float(dV.abs().max()) == 0.0
+    ctx.adjoint(gbar, dV, run=runs[1])
+    torch.cuda.synchronize()
+    _, gr, ur = O.adjoint(H, O.Plan(lo, hi, 1.3), psi0, 3, mask)
+    assert_grad_close(dV.cpu().numpy(), gr)
+    assert_state_close(gbar.cpu().numpy(), ur)
+    # a new plan drops the stored run
+    ctx.plan(1.3)
+    assert ctx.checkpoint_run() == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", [None, 0, 1])
+def test_autograd_two_applies_before_backward(torch, cheb, mode):
+    # one Propagator applied to two disorder realisations before one backward
+    # through their summed loss: each graph node gets the gradient of its own
+    # trajectory (the second forward overwrote the first's checkpoints, so the
+    # first node's backward runs its forward again)
+    w, l = 8, 60
+    V1, psi1, mask = ribbon_inputs(w, l, 0.5, 0, dense=True)
+    V2 = W.anderson_disorder(w, l, 0.9, 5)
+    psi2 = W.random_state(w * l, 55)
+    lo = min(V1.min(), V2.min()) - 3.0
+    hi = max(V1.max(), V2.max()) + 3.0
+    dt, K = 1.7, 3
+    prop = cheb.Propagator("honeycomb", dt, K, (lo, hi), width=w, length=l, adjoint_mode=mode)
+    m = torch.from_numpy(mask).cuda()
+    Vt1 = torch.from_numpy(V1.copy()).cuda().requires_grad_(True)
+    Vt2 = torch.from_numpy(V2.copy()).cuda().requires_grad_(True)
+    out1 = cheb.ChebPropagate.apply(Vt1, torch.from_numpy(psi1.copy()).cuda(), prop)
+    out2 = cheb.ChebPropagate.apply(Vt2, torch.from_numpy(psi2.copy()).cuda(), prop)
+    loss = (m * out1.abs() ** 2).sum() + 0.5 * (m * out2.abs() ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    plan = O.Plan(lo, hi, dt)
+    _, g1, _ = O.adjoint(O.honeycomb(w, l, V1), plan, psi1, K, mask)
+    _, g2, _ = O.adjoint(O.honeycomb(w, l, V2), plan, psi2, K, mask)
+    assert_grad_close(Vt1.grad.cpu().numpy(), g1)
+    assert_grad_close(Vt2.grad.cpu().numpy(), 0.5 * g2)

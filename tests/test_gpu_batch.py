@@ -8,6 +8,8 @@ import pytest
 
 import oracle as O
 import workloads as W
+from test_gpu_parity import assert_state_close
+from windows import ribbon_sites
 
 pytestmark = pytest.mark.gpu
 
@@ -34,11 +36,15 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def make_systems(specs, torch):
-    """specs: (width, length, W, seed, edge); bounds from the oracle's discs."""
+def make_systems(specs, torch, state="dense"):
+    """specs: (width, length, W, seed, edge); bounds from the oracle's discs.
+    state "dense": a seeded random state on every site of each ribbon;
+    "packet": the injected Gaussian."""
     out = []
     for (w, l, Wd, seed, edge) in specs:
         eps, psi0 = W.ribbon_inputs(w, l, Wd, seed)
+        if state == "dense":
+            psi0 = W.random_state(w * l, 7000 + seed)
         H = O.honeycomb(w, l, eps, edge=edge)
         lo, hi = H.gershgorin()
         out.append(dict(width=w, length=l, edge=edge, eps_np=eps, psi0=psi0, H=H, emin=lo, emax=hi,
@@ -75,7 +81,21 @@ def test_batch_matches_oracle(torch, cheb, mode, tile, block, wg, graph):
         plan = O.Plan(s["emin"], s["emax"], dt)
         assert M == plan.M
         ref = O.propagate(s["H"], plan, s["psi0"], K)
-        assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-10
+        assert_state_close(s["psi"].cpu().numpy(), ref)
+
+
+def test_batch_packets_match_oracle(torch, cheb):
+    # the injected packets of the batched workload through the default deep
+    # schedule
+    systems = make_systems(SMALL, torch, state="packet")
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    ctx.batch_set_schedule(cheb.SCHED_DEEP, 1024, 256, 1)
+    ctx.batch_propagate(3, cheb.GRAPH)
+    torch.cuda.synchronize()
+    for s in systems:
+        ref = O.propagate(s["H"], O.Plan(s["emin"], s["emax"], 1.0), s["psi0"], 3)
+        assert_state_close(s["psi"].cpu().numpy(), ref)
 
 
 def single_system(torch, cheb, s, K, depth):
@@ -134,7 +154,7 @@ def test_batch_autotune_restores_state_and_caches(torch, cheb, tmp_path):
     torch.cuda.synchronize()
     s = systems[3]
     ref = O.propagate(s["H"], O.Plan(s["emin"], s["emax"], 1.0), s["psi0"], 3)
-    assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-10
+    assert_state_close(s["psi"].cpu().numpy(), ref)
 
 
 def test_batch_rejects_bad_schedule(torch, cheb):
@@ -200,20 +220,30 @@ def test_batch_pairs_needs_two_orders(torch, cheb):
 
 
 def test_full_batched_config_sampled(torch, cheb):
-    # 256 ribbons, widths 32-128, lengths 512-4096, W in [0.1, 2]: the levels
-    # and persistent schedules agree bit for bit everywhere, the pairs and deep
-    # schedules to rounding; three systems are checked against the oracle
+    # 256 ribbons, widths 32-128, lengths 512-4096, W in [0.1, 2], each from a
+    # dense random state: the levels and persistent schedules agree bit for
+    # bit everywhere, the pairs and deep schedules to rounding site by site;
+    # every system is checked against the oracle at sampled sites (corners,
+    # far borders, seeded interior) from windows around them, and three whole
+    # systems against the oracle
     p = W.BATCHED.params
     descs = W.batched_ribbons(p["nsys"], p["seed_base"])
     total = sum(d.n for d in descs)
     assert 3e7 < total < 7e7
-    systems = []
+    systems, inputs = [], []
     for d in descs:
-        eps, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        eps = W.anderson_disorder(d.width, d.length, d.W, d.seed)
+        psi0 = W.random_state(d.n, 9000 + d.seed)
+        inputs.append((eps, psi0))
         # Gershgorin discs of a zigzag brick wall (interior sites have 3 bonds)
         systems.append(dict(width=d.width, length=d.length, eps=torch.from_numpy(eps).cuda(),
                             psi=torch.from_numpy(psi0).cuda(), emin=float(eps.min()) - 3.0,
                             emax=float(eps.max()) + 3.0))
+
+    def reset():
+        for s, (_, psi0) in zip(systems, inputs):
+            s["psi"].copy_(torch.from_numpy(psi0).cuda())
+
     ctx = cheb.Context()
     ctx.batch_create(systems, p["dt"])
     Ms = ctx.batch_info()
@@ -223,39 +253,70 @@ def test_full_batched_config_sampled(torch, cheb):
     ctx.batch_propagate(2)
     torch.cuda.synchronize()
     lev = [s["psi"].cpu().numpy() for s in systems]
-    for s, d in zip(systems, descs):
-        _, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
-        s["psi"].copy_(torch.from_numpy(psi0).cuda())
+    reset()
     say("[gpu] full batch: persistent schedule")
     ctx.batch_set_schedule(1, 4096, 256, 2)
     ctx.batch_propagate(2, cheb.GRAPH)
     torch.cuda.synchronize()
     for s, ref in zip(systems, lev):
         np.testing.assert_array_equal(s["psi"].cpu().numpy(), ref)
-    for s, d in zip(systems, descs):
-        _, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
-        s["psi"].copy_(torch.from_numpy(psi0).cuda())
-    say("[gpu] full batch: pairs schedule")
-    ctx.batch_set_schedule(2, 2048, 256, 1)
-    ctx.batch_propagate(2, cheb.GRAPH)
-    torch.cuda.synchronize()
-    for s, ref in zip(systems, lev):
-        assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-13
-    for s, d in zip(systems, descs):
-        _, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
-        s["psi"].copy_(torch.from_numpy(psi0).cuda())
-    say("[gpu] full batch: deep schedule")
-    ctx.batch_set_schedule(cheb.SCHED_DEEP, 1024, 512, 1)
-    ctx.batch_propagate(2, cheb.GRAPH)
-    torch.cuda.synchronize()
-    for s, ref in zip(systems, lev):
-        assert rel_l2(s["psi"].cpu().numpy(), ref) <= 1e-13
+    for mode, tile, block, name in ((2, 2048, 256, "pairs"), (cheb.SCHED_DEEP, 1024, 512, "deep")):
+        reset()
+        say(f"[gpu] full batch: {name} schedule")
+        ctx.batch_set_schedule(mode, tile, block, 1)
+        ctx.batch_propagate(2, cheb.GRAPH)
+        torch.cuda.synchronize()
+        for s, ref in zip(systems, lev):
+            assert_state_close(s["psi"].cpu().numpy(), ref, 1e-13)
+    say("[gpu] full batch: oracle windows on every system")
+    u = W.uniform01(321, 2 * len(descs))
+    for j, d in enumerate(descs):
+        eps, psi0 = inputs[j]
+        plan = O.Plan(systems[j]["emin"], systems[j]["emax"], p["dt"])
+        assert plan.M == Ms[j]
+        sites = [(0, 0), (d.width - 1, d.length - 1), (d.width - 1, 0), (0, d.length - 1),
+                 (int(u[2 * j] * d.width), int(u[2 * j + 1] * d.length))]
+        ref = ribbon_sites(d.width, d.length, "zigzag", eps, psi0, plan, 2, sites)
+        got = np.array([lev[j][y * d.length + x] for y, x in sites])
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max(), j
     sizes = np.array([d.n for d in descs])
     for j in (int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), 17):
         d = descs[j]
-        eps, psi0 = W.ribbon_inputs(d.width, d.length, d.W, d.seed)
+        eps, psi0 = inputs[j]
         H = O.honeycomb(d.width, d.length, eps)
         plan = O.Plan(systems[j]["emin"], systems[j]["emax"], p["dt"])
-        assert plan.M == Ms[j]
         ref = O.propagate(H, plan, psi0, 2)
-        assert rel_l2(lev[j], ref) <= 1e-10
+        assert_state_close(lev[j], ref)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batch_rebinds_states_without_replanning(torch, cheb, mode):
+    # the batch is built on one set of states; new states are passed per call
+    # (the signature chebtd_batch_propagate(ctx, psi[], K, flags)), replayed
+    # through the graph captured before the re-bind, and stay bound for the
+    # next call
+    systems = make_systems(SMALL, torch)
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    ctx.batch_set_schedule(mode, 1024, 256, 2)
+    ctx.batch_propagate(2, cheb.GRAPH)  # captures the graph on the first states
+    torch.cuda.synchronize()
+    first = [s["psi"].cpu().numpy() for s in systems]
+    new0 = [W.random_state(s["width"] * s["length"], 31337 + j) for j, s in enumerate(systems)]
+    new = [torch.from_numpy(p.copy()).cuda() for p in new0]
+    say(f"[gpu] batch re-bind mode={mode}")
+    ctx.batch_propagate(2, cheb.GRAPH, psi=new)
+    ctx.batch_propagate(1, cheb.GRAPH)  # still bound to the new states
+    torch.cuda.synchronize()
+    for j, s in enumerate(systems):
+        # the first states were left where the first call put them
+        np.testing.assert_array_equal(s["psi"].cpu().numpy(), first[j])
+        ref = O.propagate(s["H"], O.Plan(s["emin"], s["emax"], 1.0), new0[j], 3)
+        assert_state_close(new[j].cpu().numpy(), ref)
+    # and back to the first states
+    ctx.batch_propagate(0, 0, psi=[s["psi"] for s in systems])
+    ctx.batch_propagate(1)
+    torch.cuda.synchronize()
+    for j, s in enumerate(systems):
+        ref = O.propagate(s["H"], O.Plan(s["emin"], s["emax"], 1.0), s["psi0"], 3)
+        assert_state_close(s["psi"].cpu().numpy(), ref)

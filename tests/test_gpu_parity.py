@@ -42,6 +42,18 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def assert_state_close(got, ref, tol=TOL):
+    """rel-L2 <= tol, and every site within tol * max|ref| (an error where
+    the state is small cannot hide in the norm of the whole vector)."""
+    got, ref = np.asarray(got), np.asarray(ref)
+    err = rel_l2(got, ref)
+    assert err <= tol, f"rel-L2 {err:.3e}"
+    d = np.abs(got - ref)
+    worst = int(np.argmax(d))
+    assert d[worst] <= tol * np.abs(ref).max(), \
+        f"site {worst}: |diff| {d[worst]:.3e} vs max|ref| {np.abs(ref).max():.3e}"
+
+
 def dev(torch, x, dtype=None):
     t = torch.from_numpy(np.ascontiguousarray(x))
     if dtype is not None:
@@ -56,26 +68,43 @@ def host(t):
 # ---------------------------------------------------------------------------
 # helpers building the same problem on both sides
 # ---------------------------------------------------------------------------
-def chain_case(n, xmin=-20.0, xmax=20.0, a=0.05, b=5.0, x0=-5.0, sigma=1.0, k0=1.0):
+def chain_case(n, xmin=-20.0, xmax=20.0, a=0.05, b=5.0, x0=-5.0, sigma=1.0, k0=1.0,
+               state="packet", seed=11):
+    """state "packet": the Sect. 3.1 Gaussian; "dense": a seeded random state
+    with amplitude on every site."""
     if n == 1:  # single point: H = 1/dx^2 + V
         V, dx, psi0 = np.array([0.3]), 1.0, np.array([1.0 + 0.0j])
         return dict(kind="chain", n=1, dx=dx, V=V, psi0=psi0, H=O.chain1d(V, dx))
     x, dx, V, psi0 = W.double_well_inputs(n, xmin, xmax, a, b, x0, sigma, k0)
+    if state == "dense":
+        psi0 = W.random_state(n, seed)
     return dict(kind="chain", n=n, dx=dx, V=V, psi0=psi0, H=O.chain1d(V, dx))
 
 
-def honey_case(width, length, edge="zigzag", Wd=0.5, seed=0, sigma=None, k0=1.0):
+def honey_case(width, length, edge="zigzag", Wd=0.5, seed=0, sigma=None, k0=1.0,
+               state="packet"):
+    """state "packet": the injected Gaussian of the ribbon workload; "dense": a
+    seeded random state with amplitude on every site (borders, far strips and
+    chunks included)."""
     eps = W.anderson_disorder(width, length, Wd, seed)
-    sig = sigma if sigma is not None else min(20.0, width / 4.0)
-    psi0 = W.ribbon_packet(width, length, sig, k0)
+    if state == "dense":
+        psi0 = W.random_state(width * length, seed + 101)
+    else:
+        sig = sigma if sigma is not None else min(20.0, width / 4.0)
+        psi0 = W.ribbon_packet(width, length, sig, k0)
     return dict(kind="honey", width=width, length=length, edge=edge, eps=eps, psi0=psi0,
                 H=O.honeycomb(width, length, eps, edge=edge))
 
 
-def holstein_case(L, nph, g2, periodic=True, Delta=0.0):
+def holstein_case(L, nph, g2, periodic=True, Delta=0.0, state="vacuum"):
+    """state "vacuum": the electron on site 0 with no phonons; "dense": a
+    seeded random state over the whole basis."""
     g = math.sqrt(g2)
     nconf = O.holstein_nconf(L, nph)
-    psi0 = W.holstein_vacuum_site(L, 0, nconf)
+    if state == "dense":
+        psi0 = W.random_state(L * nconf, 31 + L + nph)
+    else:
+        psi0 = W.holstein_vacuum_site(L, 0, nconf)
     return dict(kind="holstein", L=L, nph=nph, g=g, Delta=Delta, periodic=periodic, psi0=psi0,
                 H=O.holstein(L, nph, 1.0, 1.0, g, Delta, periodic))
 
@@ -149,13 +178,14 @@ def test_gershgorin_matches_oracle(torch, cheb, which):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,flags", [(1, 0), (17, 0), (700, 0), (1024, 0), (1500, 0), (4096, 0),
                                      (4096, 8), (5003, 0), (70001, 0)])
-def test_chain_parity(torch, cheb, n, flags):
-    case = chain_case(n) if n > 64 else chain_case(n, -2.0, 2.0)
+@pytest.mark.parametrize("state", ["packet", "dense"])
+def test_chain_parity(torch, cheb, n, flags, state):
+    case = chain_case(n, state=state) if n > 64 else chain_case(n, -2.0, 2.0, state=state)
     dt, K = (0.02, 4) if n >= 4096 else (0.05, 5)
     if n == 1:
         dt = 0.3
     _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, dt, K, flags)
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
     np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11 * plan.a)
 
@@ -163,10 +193,11 @@ def test_chain_parity(torch, cheb, n, flags):
 @pytest.mark.parametrize("edge,width,length", [("zigzag", 6, 300), ("zigzag", 1, 513),
                                                ("zigzag", 31, 257), ("armchair", 6, 300),
                                                ("armchair", 10, 1000), ("zigzag", 128, 200)])
-def test_honeycomb_parity(torch, cheb, edge, width, length):
-    case = honey_case(width, length, edge)
+@pytest.mark.parametrize("state", ["packet", "dense"])
+def test_honeycomb_parity(torch, cheb, edge, width, length, state):
+    case = honey_case(width, length, edge, state=state)
     _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, 1.0, 6)
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
     np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11)
 
@@ -183,16 +214,18 @@ def test_table2_ribbon_single_site(torch, cheb, dt):
                 H=O.honeycomb(w, l, eps, edge=p["edge"]))
     K = int(round(100.0 / dt))
     _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, dt, K, flags=cheb.GRAPH)
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
     np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11)
 
 
-@pytest.mark.parametrize("L,nph,g2,periodic", [(4, 3, 0.5, True), (6, 4, 2.0, True), (5, 5, 0.5, False)])
-def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic):
-    case = holstein_case(L, nph, g2, periodic, Delta=np.linspace(0, 0.5, L))
+@pytest.mark.parametrize("L,nph,g2,periodic", [(4, 3, 0.5, True), (6, 4, 2.0, True), (5, 5, 0.5, False),
+                                               (3, 6, 2.0, True), (1, 7, 0.5, False), (2, 5, 0.5, False)])
+@pytest.mark.parametrize("state", ["vacuum", "dense"])
+def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic, state):
+    case = holstein_case(L, nph, g2, periodic, Delta=np.linspace(0, 0.5, L), state=state)
     ctx, psi, ref, nrm, rn, en, re, _ = run_both(torch, cheb, case, 0.1, 8)
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
     n_i, nph_i, chi = (host(t) for t in ctx.holstein_obs(dev(torch, ref)))
     rn_i, rnph_i, rchi = O.holstein_obs(L, nph, ref)
@@ -218,7 +251,88 @@ def test_polaron_figure3_parameters_reduced(torch, cheb):
     ctx.propagate(psi, 12)
     torch.cuda.synchronize()
     ref = O.propagate(H, O.Plan(emin, emax, p["dt"]), psi0, 12)
-    assert rel_l2(host(psi), ref) <= TOL
+    assert_state_close(host(psi), ref)
+    for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
+        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+
+
+@pytest.fixture
+def hol_spt_env():
+    import os
+    saved = os.environ.get("CHEBTD_HOL_SPT")
+
+    def setter(spt):
+        if spt is None:
+            os.environ.pop("CHEBTD_HOL_SPT", None)
+        else:
+            os.environ["CHEBTD_HOL_SPT"] = str(spt)
+    yield setter
+    setter(saved)
+
+
+def _polaron_fig3(L, nph, barrier_site, periodic, state):
+    p = W.POLARON_PAPER.params
+    g, Delta = W.polaron_couplings(L, p["w0"], p["eps_p"], p["eps_p_barrier"], barrier_site,
+                                   p["barrier"])
+    H = O.holstein(L, nph, p["t"], p["w0"], g, Delta, periodic)
+    nconf = O.holstein_nconf(L, nph)
+    if state == "dense":
+        psi0 = W.random_state(L * nconf, 400 + L)
+    else:
+        psi0 = W.holstein_packet(L, nconf, p["packet_site"], p["width"], p["k"])
+    return p, g, Delta, H, psi0
+
+
+# the walk groups at most 9 electron sites per thread past 2^20 phonon
+# configurations (the Sect. 3.3 / Fig. 3 polaron takes that branch); forcing
+# the grouping here runs that code at oracle size: group boundaries inside
+# the chain (left neighbour from the previous group), groups that do not
+# divide L, the ring's wrap from the last group to the first
+@pytest.mark.parametrize("spt", [1, 2, 3, 5, 7, 9, 12])
+@pytest.mark.parametrize("periodic,state", [(False, "packet"), (False, "dense"), (True, "dense")])
+def test_holstein_grouped_walk_matches_oracle(torch, cheb, hol_spt_env, spt, periodic, state):
+    L, nph = 12, 5
+    p, g, Delta, H, psi0 = _polaron_fig3(L, nph, 8, periodic, state)
+    hol_spt_env(spt)
+    ctx = cheb.Context()
+    ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, periodic)
+    hol_spt_env(None)
+    emin, emax = H.gershgorin()
+    ctx.set_bounds(emin, emax)
+    plan = O.Plan(emin, emax, p["dt"])
+    assert ctx.plan(p["dt"]) == plan.M
+    psi = dev(torch, psi0)
+    nrm = torch.zeros(6, dtype=torch.float64, device="cuda")
+    say(f"[gpu] Holstein grouped walk spt={spt} periodic={periodic} {state}")
+    ctx.propagate(psi, 6, nrm)
+    torch.cuda.synchronize()
+    ref, rn, _ = O.propagate(H, plan, psi0, 6, want_obs=True)
+    assert_state_close(host(psi), ref)
+    np.testing.assert_allclose(host(nrm), rn, rtol=1e-12)
+    for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
+        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+
+
+def test_holstein_grouped_walk_by_size_matches_oracle(torch, cheb, hol_spt_env):
+    # 12 open sites with up to 11 phonons: 1,352,078 configurations (16.2M
+    # states), past 2^20, so the walk groups sites by its own choice (two
+    # groups of six) exactly as the Fig. 3 polaron run does
+    L, nph = 12, 11
+    hol_spt_env(None)
+    p, g, Delta, H, psi0 = _polaron_fig3(L, nph, 8, False, "packet")
+    assert O.holstein_nconf(L, nph) == 1_352_078
+    ctx = cheb.Context()
+    ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, False)
+    emin, emax = H.gershgorin()
+    ctx.set_bounds(emin, emax)
+    plan = O.Plan(emin, emax, p["dt"])
+    assert ctx.plan(p["dt"]) == plan.M
+    psi = dev(torch, psi0)
+    say(f"[gpu] Holstein L=12 nph=11 (16.2M states), grouped by size, M={plan.M}")
+    ctx.propagate(psi, 2)
+    torch.cuda.synchronize()
+    ref = O.propagate(H, plan, psi0, 2)
+    assert_state_close(host(psi), ref)
     for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
         np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
 
@@ -283,15 +397,16 @@ def test_generic_csr_parity(torch, cheb):
     assert ctx.plan(0.7) == plan.M
     psi = dev(torch, psi0)
     ctx.propagate(psi, 5)
-    assert rel_l2(host(psi), O.propagate(H, plan, psi0, 5)) <= TOL
+    assert_state_close(host(psi), O.propagate(H, plan, psi0, 5))
 
 
 @pytest.mark.parametrize("M", [0, 1, 2, 3])
 def test_low_orders(torch, cheb, M):
-    for case in (chain_case(300), chain_case(9000), honey_case(5, 100)):
+    for case in (chain_case(300, state="dense"), chain_case(9000, state="dense"),
+                 honey_case(5, 100, state="dense")):
         # a forced low order is not unitary: skip the norm check
         _, psi, ref, *_ = run_both(torch, cheb, case, 1e-4, 3, flags=cheb.NO_CHECK, M=M)
-        assert rel_l2(psi, ref) <= TOL
+        assert_state_close(psi, ref)
 
 
 # ---------------------------------------------------------------------------
@@ -300,8 +415,10 @@ def test_low_orders(torch, cheb, M):
 @pytest.mark.parametrize("rows", ["1", "3", "8", "16", "200"])
 def test_two_orders_per_pass_matches_single_order_and_oracle(torch, cheb, rows, monkeypatch):
     monkeypatch.setenv("CHEBTD_PAIR_ROWS", rows)
-    cases = [(honey_case(19, 211), 1.0), (honey_case(12, 130, "armchair"), 1.0),
-             (honey_case(1, 300), 1.0), (chain_case(9001), 0.002), (honey_case(64, 640), 1.4)]
+    cases = [(honey_case(19, 211, state="dense"), 1.0),
+             (honey_case(12, 130, "armchair", state="dense"), 1.0),
+             (honey_case(1, 300, state="dense"), 1.0), (chain_case(9001, state="dense"), 0.002),
+             (honey_case(64, 640, state="dense"), 1.4), (honey_case(64, 640), 1.4)]
     for case, dt in cases:
         H = case["H"]
         emin, emax = H.gershgorin()
@@ -317,16 +434,17 @@ def test_two_orders_per_pass_matches_single_order_and_oracle(torch, cheb, rows, 
         ctx.propagate(b, 3, nb, flags=cheb.SINGLE_ORDER)
         torch.cuda.synchronize()
         ref = O.propagate(H, O.Plan(emin, emax, dt), case["psi0"], 3)
-        assert rel_l2(host(a), ref) <= TOL
+        assert_state_close(host(a), ref)
+        assert_state_close(host(b), ref)
         assert rel_l2(host(a), host(b)) <= 1e-13
         np.testing.assert_allclose(host(na), host(nb), rtol=1e-13)
 
 
 @pytest.mark.parametrize("M", [2, 3, 4, 5, 8, 9])
 def test_two_orders_per_pass_at_small_orders(torch, cheb, M):
-    for case in (honey_case(10, 300), chain_case(7000)):
+    for case in (honey_case(10, 300, state="dense"), chain_case(7000, state="dense")):
         _, psi, ref, nrm, rn, *_ = run_both(torch, cheb, case, 0.01, 3, flags=cheb.NO_CHECK, M=M)
-        assert rel_l2(psi, ref) <= TOL
+        assert_state_close(psi, ref)
         np.testing.assert_allclose(nrm, rn, rtol=1e-12)
 
 
@@ -445,24 +563,26 @@ def test_full_double_well_4096(torch, cheb):
     case = chain_case(p["n"], p["xmin"], p["xmax"], p["a"], p["b"], p["x0"], p["sigma"], p["k0"])
     _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, p["dt"], 2)
     assert plan.M > 7000
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)
     np.testing.assert_allclose(en, re, rtol=1e-11)
 
 
-def test_full_zigzag_ribbon_128x8192(torch, cheb):
+@pytest.mark.parametrize("state", ["packet", "dense"])
+def test_full_zigzag_ribbon_128x8192(torch, cheb, state):
     p = W.GRAPHENE.params
-    case = honey_case(p["width"], p["length"], p["edge"], p["W"], p["seed"], p["sigma"], p["k0"])
+    case = honey_case(p["width"], p["length"], p["edge"], p["W"], p["seed"], p["sigma"], p["k0"],
+                      state=state)
     _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, p["dt"], 3)
     assert plan.M == 20
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
 
 
-@pytest.mark.parametrize("g2", [0.5, 2.0])
-def test_full_holstein_ring(torch, cheb, g2):
+@pytest.mark.parametrize("g2,state", [(0.5, "vacuum"), (2.0, "vacuum"), (2.0, "dense")])
+def test_full_holstein_ring(torch, cheb, g2, state):
     p = W.HOLSTEIN.params
-    case = holstein_case(p["L"], p["nph"], g2, p["periodic"])
+    case = holstein_case(p["L"], p["nph"], g2, p["periodic"], state=state)
     ctx, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, p["dt"], 2)
     assert ctx.n == 1_847_560
     assert plan.M == (13 if g2 == 0.5 else 14)
-    assert rel_l2(psi, ref) <= TOL
+    assert_state_close(psi, ref)

@@ -102,6 +102,21 @@ def single_site(n: int, i: int) -> np.ndarray:
     return psi
 
 
+def random_state(n: int, seed: int) -> np.ndarray:
+    """Dense complex vector with unit 2-norm: real and imaginary parts uniform
+    in [-1/2, 1/2) from one SplitMix64 stream (re, im of site i from outputs
+    2i and 2i+1).  Every site carries an amplitude of order 1/sqrt(n)."""
+    u = uniform01(seed, 2 * n) - 0.5
+    psi = u[0::2] + 1j * u[1::2]
+    return (psi / np.linalg.norm(psi)).astype(np.complex128)
+
+
+def random_weights(n: int, seed: int) -> np.ndarray:
+    """Dense real weights in [0, 1) from SplitMix64 (a loss sum_i w_i |psi_i|^2
+    then has a nonzero adjoint on every site)."""
+    return uniform01(seed, n)
+
+
 def right_half_mask_ribbon(width: int, length: int) -> np.ndarray:
     """1 where the column lies right of the ribbon centre (x > (length-1)/2)."""
     x = np.tile(np.arange(length), width)
