@@ -339,10 +339,14 @@ int chebtd_batch_info(const chebtd_ctx *ctx, int *nsys, int *M_host);
 /* Adjoint memory schedules. */
 #define CHEBTD_ADJ_STEP 0  /* recompute each step's M+1 vectors into a     */
                            /* buffer, then sweep back                       */
-#define CHEBTD_ADJ_SQRTM 1 /* keep (v_{j-1}, v_j) every ceil(sqrt(M))      */
-                           /* orders (rounded up to even for chains and    */
-                           /* ribbons, which recompute two orders a pass)  */
-                           /* and recompute segment by segment              */
+#define CHEBTD_ADJ_SQRTM 1 /* keep psi_s only; the backward pass rebuilds */
+                           /* each step's (v_{j-1}, v_j) pairs about every */
+                           /* ceil(sqrt(M)) orders in one forward pass and */
+                           /* regenerates the vectors between them         */
+                           /* downwards, restarting from each stored pair  */
+                           /* (chains and ribbons within the deep walk's   */
+                           /* offset limit); elsewhere it recomputes       */
+                           /* segment by segment from the pairs             */
 #define CHEBTD_ADJ_REVERSE 2 /* keep each step's last two vectors           */
                              /* (v_{M-1}, v_M) beside psi_s and regenerate  */
                              /* v_{M-2} .. v_0 downwards, v_{k-1} =         */

@@ -36,6 +36,13 @@ struct AdjState {
     DevBuf pairs;  // (v_{j-1}, v_j) per segment (sqrt mode)
     DevBuf u;      // two adjoint vectors
     DevBuf ends;   // (v_{M-1}, v_M) per step (reverse mode)
+    // downward sweeps (reverse mode, and the sqrt mode where the deep walk
+    // fits): levels per pass from level M-1 down, and in the sqrt mode the
+    // pair slot each pass restarts from (-1: it continues from the pairs the
+    // pass above regenerated)
+    bool down = false;
+    std::vector<int> rdepths, cpslot;
+    DevBuf hpart;  // norm partials of the recomputation's head pass (unused)
 };
 
 void adj_destroy(Ctx *c)
@@ -46,6 +53,7 @@ void adj_destroy(Ctx *c)
     release(c->adj->pairs);
     release(c->adj->u);
     release(c->adj->ends);
+    release(c->adj->hpart);
     delete c->adj;
     c->adj = nullptr;
 }
@@ -240,44 +248,118 @@ int rev_rows(const Ctx &c, int D)
     return small[D];
 }
 
-// The reverse schedule over all steps.  Per step, from the stored
-// (v_{M-1}, v_M), passes of levels k .. k-d+1 regenerate the forward vectors
-// downwards beside the adjoint recursion; the pass holding level 0 writes
-// u_0, the next step's gbar, into the other of two gbar buffers (the pass
-// still reads the current one around its rows).  M = 1 has level 0 alone.
-hipError_t reverse_sweep(Ctx *c, hipStream_t s, double2 *gbar_user, double *grad, URot &u)
+// Levels per pass of a downward sweep from level M-1 to level 0: rev_depth
+// each, and no pass of a single level (the walk needs two).
+std::vector<int> rev_pass_depths(const Ctx &c)
 {
-    AdjState *a = c->adj;
-    const int M = c->M;
-    const int64_t n = c->n;
-    double2 *vb = static_cast<double2 *>(a->vbuf.p);
-    double2 *vr[4] = {vb, vb + n, vb + 2 * n, vb + 3 * n};
-    double2 *gcur = gbar_user, *gnext = vb + 4 * n;
-    // pass depths from level M-1 down to level 0: rev_depth each, and no
-    // pass of a single level (the walk needs two)
     std::vector<int> depths;
-    const int Dm = rev_depth(*c);
-    for (int rem = M; rem > 0;) {
+    const int Dm = rev_depth(c);
+    for (int rem = c.M; rem > 0;) {
         int d = std::min(Dm, rem);
         if (rem - d == 1) d = rem <= kMaxRevDepth ? rem : d - 1;
         depths.push_back(d);
         rem -= d;
     }
+    return depths;
+}
+
+// The sqrt mode's forward pass of one step on the downward path: from psi_s,
+// the passes of the downward sweep in reverse order (so every pass ends on
+// an order where a downward pass starts), each advancing its orders without
+// the accumulator (the deep walk with no acc buffer reads and writes none of
+// it: 72 B per site and pass).  A pass whose end starts a restarting
+// downward pass writes its (v_{e-1}, v_e) into that pair slot; the others
+// rotate through four scratch vectors.  The last pass ends on (v_{M-1}, v_M)
+// in slot 0.
+hipError_t recompute_pairs(Ctx *c, hipStream_t s, const double2 *psi_s, double2 *const vr[4])
+{
+    AdjState *a = c->adj;
+    const int64_t n = c->n;
+    const int P = (int)a->rdepths.size();
+    double2 *pairs = static_cast<double2 *>(a->pairs.p);
+    const double2 *gam = reinterpret_cast<const double2 *>(c->gamma.data());
+    const double2 *in1 = nullptr, *in2 = psi_s;  // (v_{k-1}, v_k)
+    int k = 0;
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < P && e == hipSuccess; ++f) {
+        const int p = P - 1 - f, d = a->rdepths[p];
+        double2 *o1 = nullptr, *o2 = nullptr;
+        if (a->cpslot[p] >= 0) {
+            o1 = pairs + (size_t)(2 * a->cpslot[p]) * n;
+            o2 = o1 + n;
+        } else {
+            for (int j = 0; j < 4; ++j) {
+                if (vr[j] == in1 || vr[j] == in2) continue;
+                if (!o1)
+                    o1 = vr[j];
+                else if (!o2)
+                    o2 = vr[j];
+            }
+        }
+        if (d == 2)
+            e = launch_recompute_pair(*c, s, k == 0, in1, in2, o1, o2);
+        else
+            e = launch_deep(*c, s, d, c->deep_rows[d], k == 0, in1, in2, o1, o2, nullptr, gam + k, nullptr,
+                            static_cast<double *>(a->hpart.p), nullptr);
+        in1 = o1;
+        in2 = o2;
+        k += d;
+    }
+    if (e == hipSuccess && k != c->M) e = hipErrorInvalidValue;
+    return e;
+}
+
+// The downward schedules over all steps.  Per step, from (v_{M-1}, v_M) --
+// stored by the forward run (reverse mode) or rebuilt from psi_s by
+// recompute_pairs (sqrt mode) -- passes of levels k .. k-d+1 regenerate the
+// forward vectors downwards beside the adjoint recursion; in the sqrt mode
+// every pass with a pair slot starts from the stored pair instead of the
+// regenerated one (the pass above then stores no forward vectors).  The pass
+// holding level 0 writes u_0, the next step's gbar, into the other of two
+// gbar buffers (the pass still reads the current one around its rows).
+// M = 1 has level 0 alone.
+hipError_t reverse_sweep(Ctx *c, hipStream_t s, double2 *gbar_user, double *grad, URot &u)
+{
+    AdjState *a = c->adj;
+    const bool seg = a->mode == CHEBTD_ADJ_SQRTM;
+    const int M = c->M;
+    const int64_t n = c->n;
+    double2 *vb = static_cast<double2 *>(a->vbuf.p);
+    double2 *const vr[4] = {vb, vb + n, vb + 2 * n, vb + 3 * n};
+    double2 *pairs = static_cast<double2 *>(a->pairs.p);
+    double2 *gcur = gbar_user, *gnext = vb + 4 * n;
+    const std::vector<int> &depths = a->rdepths;
+    const int P = (int)depths.size();
     hipError_t e = hipSuccess;
     for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {
+        double2 *psi_s = static_cast<double2 *>(a->ckpt.p) + (size_t)st * n;
         u.start(u.buf[0]);
         e = launch_adj_init(s, gcur, conj_weight(c, M), u.uk1, n);  // u_M
         if (e != hipSuccess) break;
         if (M == 1) {
-            double2 *psi_s = static_cast<double2 *>(a->ckpt.p) + (size_t)st * n;
             e = sweep_levels(c, s, 0, 1, [&](int) { return psi_s; }, gcur, grad, u);
             continue;
         }
-        double2 *ends = adj_step_ends(c, st);
-        if (!ends) return hipErrorInvalidValue;
-        const double2 *v1 = ends + n, *v0 = ends;  // v_{k+1}, v_k for k = M-1
+        const double2 *v1, *v0;  // v_{k+1}, v_k for k = M-1
+        if (seg) {
+            e = recompute_pairs(c, s, psi_s, vr);
+            if (e != hipSuccess) break;
+            v1 = pairs + n;
+            v0 = pairs;
+        } else {
+            double2 *ends = adj_step_ends(c, st);
+            if (!ends) return hipErrorInvalidValue;
+            v1 = ends + n;
+            v0 = ends;
+        }
         int k = M - 1;
-        for (const int d : depths) {
+        for (int i = 0; i < P; ++i) {
+            const int d = depths[i];
+            if (seg && a->cpslot[i] >= 0) {
+                const double2 *slot = pairs + (size_t)(2 * a->cpslot[i]) * n;
+                v1 = slot + n;
+                v0 = slot;
+            }
             RevPass p{};
             p.last0 = k - d + 1 == 0;
             double2 *o1, *o2;
@@ -290,7 +372,8 @@ hipError_t reverse_sweep(Ctx *c, hipStream_t s, double2 *gbar_user, double *grad
             p.grad = grad;
             p.v1 = v1;
             p.v0 = v0;
-            if (!p.last0) {
+            const bool restart_next = seg && i + 1 < P && a->cpslot[i + 1] >= 0;
+            if (!p.last0 && !restart_next) {
                 for (double2 *w : vr) {
                     if (w == v1 || w == v0) continue;
                     if (!p.vout1)
@@ -343,6 +426,11 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
     // two-orders-per-pass recomputation ends exactly on segment boundaries
     a->seg = std::max(1, (int)std::ceil(std::sqrt((double)std::max(M, 1))));
     if (pair_supported(*c)) a->seg += a->seg & 1;
+    // the reverse mode, and the sqrt mode where the deep walk fits, sweep
+    // downwards (M >= 2; M = 1 is level 0 alone)
+    a->down = mode == CHEBTD_ADJ_REVERSE || (mode == CHEBTD_ADJ_SQRTM && rev_deep_fits(*c) && M >= 2);
+    a->rdepths = a->down ? rev_pass_depths(*c) : std::vector<int>();
+    a->cpslot.assign(a->rdepths.size(), -1);
     int rc;
     if ((rc = ensure(c, a->ckpt, vb * (size_t)max_steps, "adjoint checkpoints"))) return rc;
     if ((rc = ensure(c, a->u, 4 * vb, "adjoint vectors"))) return rc;
@@ -355,6 +443,26 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode)
         release(a->pairs);
         if ((rc = ensure(c, a->ends, 2 * vb * (size_t)max_steps, "step-end pairs"))) return rc;
         if ((rc = ensure(c, a->vbuf, 5 * vb, "downward vectors"))) return rc;
+    } else if (a->down) {
+        // a pair slot for the top pass and then one each time at least
+        // ceil(sqrt(M)) levels have passed since the last slot; four vectors
+        // for the forward pass's and the downward pairs, one for the other gbar
+        release(a->ends);
+        const int S = std::max(1, (int)std::ceil(std::sqrt((double)M)));
+        int nslot = 0, since = 0;
+        for (size_t i = 0; i < a->rdepths.size(); ++i) {
+            if (i == 0 || since >= S) {
+                a->cpslot[i] = nslot++;
+                since = 0;
+            }
+            since += a->rdepths[i];
+        }
+        if ((rc = ensure(c, a->pairs, vb * 2 * (size_t)std::max(nslot, 1), "checkpoint pairs"))) return rc;
+        if ((rc = ensure(c, a->vbuf, 5 * vb, "downward vectors"))) return rc;
+        const int dh = a->rdepths.empty() ? 2 : a->rdepths.back();  // the forward pass's head
+        const int64_t hb = dh >= 3 ? deep_grid_blocks(*c, c->deep_rows[dh], dh) : 1;
+        if ((rc = ensure(c, a->hpart, (size_t)std::max<int64_t>(hb, 1) * 2 * sizeof(double), "head partials")))
+            return rc;
     } else {
         release(a->ends);
         const int nseg = (M + a->seg - 1) / a->seg;
@@ -404,9 +512,9 @@ int chebtd_adjoint_run(chebtd_ctx *ctx, int64_t run_id, double *gbar_dev, double
     for (int q = 0; q < 4; ++q) urot.buf[q] = static_cast<double2 *>(a->u.p) + (size_t)q * n;
     const bool pairs_on = pair_supported(*c);
     hipError_t e = hipSuccess;
-    if (a->mode == CHEBTD_ADJ_REVERSE && M >= 1) {
+    if (a->down && M >= 1) {
         e = reverse_sweep(c, s, gbar, dLdV_dev, urot);
-        if (e != hipSuccess) return hip_fail(c, e, "chebtd_adjoint (reverse schedule)");
+        if (e != hipSuccess) return hip_fail(c, e, "chebtd_adjoint (downward schedule)");
         return CHEBTD_OK;
     }
     for (int64_t st = a->last_K - 1; st >= 0 && e == hipSuccess; --st) {

@@ -109,7 +109,8 @@ struct Ctx {
     int hol_periodic = 0;
     double hol_t = 0.0, hol_w0 = 0.0;
     const double *hol_delta = nullptr;  // per-step Delta_i during a time-dependent run
-    int hol_spt = 0;  // electron sites per thread of the walk; 0: chosen by size
+    int hol_spt = 0;    // electron sites per thread of the walk; 0: chosen by size
+    int hol_remap = 0;  // 1: XCD-contiguous configuration ranges in the walk
 
     // bounds and plan
     bool has_bounds = false;

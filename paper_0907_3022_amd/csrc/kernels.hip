@@ -149,15 +149,18 @@ __global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2
 // load and store of a site is contiguous across the wavefront except the
 // phonon partners v(s, up_s(r)) and v(s, dn_s(r)).
 // Thread t = grp * nconf + r covers sites [grp*spt, min(grp*spt + spt, L)).
-__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, const double2 *__restrict__ vk,
+__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int remap, const double2 *__restrict__ vk,
                                                      double2 *vprev, double2 *__restrict__ acc, double2 g)
 {
     const uint32_t C = op.nconf, L = (uint32_t)op.L;
     const uint32_t ngrp = (L + (uint32_t)spt - 1) / (uint32_t)spt;
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // remap: each XCD takes one contiguous range of configurations, so the
+    // phonon partners that neighbouring wavefronts share meet in one L2
+    const uint32_t lb = (uint32_t)logical_block(remap);
+    const uint64_t t = (uint64_t)lb * blockDim.x + threadIdx.x;
     if (t >= (uint64_t)C * ngrp) return;
     // (grp, r) from t: one division per wavefront, then at most a few steps
-    const uint32_t b0 = (uint32_t)(blockIdx.x * blockDim.x);
+    const uint32_t b0 = lb * blockDim.x;
     uint32_t grp = __builtin_amdgcn_readfirstlane(b0 / C);
     uint32_t r = (uint32_t)t - grp * C;
     while (r >= C) {
@@ -602,7 +605,8 @@ hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *
                                       : (int)((L + groups - 1) / groups);
         const int64_t ngrp = (L + spt - 1) / spt;
         const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), block, 0, s, make_hol(c), spt, vk, vprev, acc, g);
+        hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), block, 0, s, make_hol(c), spt, c.hol_remap, vk, vprev,
+                           acc, g);
         break;
     }
     default:
