@@ -9,7 +9,10 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchebtd.so")
+# CHEBTD_LIB names another build of the same library (the host-sanitizer
+# build of the tests); by default the in-tree one
+LIB_PATH = os.environ.get("CHEBTD_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                        "libchebtd.so")
 
 OK = 0
 E_ARG, E_HIP, E_DIVERGED, E_OOM, E_STATE, E_TIMEOUT = -1, -2, -3, -4, -5, -6
