@@ -239,6 +239,22 @@ int chebtd_set_check_tol(chebtd_ctx *ctx, double rel_tol);
 /* Observables (Sect. 3.1 densities, Fig. 3 polaron quantities)             */
 /* ======================================================================= */
 
+/* Allocation-free variant of chebtd_region_sum, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Needs no context: n sites of
+ * psi_dev (complex128[n]) and mask_dev (uint8[n], 0 or 1), sum into
+ * out_dev[0] (float64), enqueued on hip_stream (a hipStream_t of the current
+ * HIP device, NULL = null stream).  The per-block partial sums live in a
+ * fixed device array of the library, one per GPU, of 1 MB, held until the
+ * process ends; it allocates nothing and returns CHEBTD_E_ARG for n outside
+ * [1, CHEBTD_NOALLOC_MAX_SITES].  The same kernels as chebtd_region_sum:
+ * bit-identical results.  Calls that overlap on one GPU (other streams,
+ * other host threads) share that array and race; serialise them.  Errors
+ * are reported through chebtd_last_error(NULL). */
+#define CHEBTD_NOALLOC_MAX_SITES 16777216
+int chebtd_region_sum_noalloc(const double *psi_dev, const uint8_t *mask_dev, int64_t n,
+                              double *out_dev, void *hip_stream);
+
 /* rho_dev[i] = |psi_i|^2 (float64[n]). */
 int chebtd_density(chebtd_ctx *ctx, const double *psi_dev, double *rho_dev);
 

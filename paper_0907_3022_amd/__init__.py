@@ -8,10 +8,10 @@ from ._lib import (ADJ_REVERSE, ADJ_SQRTM, ADJ_STEP, ARMCHAIR, GRAPH, KEEP_CHECK
                    NO_PERSISTENT, SCHED_DEEP, SCHED_LEVELS, SCHED_PAIRS, SCHED_PERSISTENT, SINGLE_ORDER, ZIGZAG,
                    ChebError)
 from ._lib import lib as load_library
-from .api import Context, holstein_csr_host, holstein_occupations
+from .api import Context, holstein_csr_host, holstein_occupations, region_sum_noalloc
 
 __all__ = [
-    "Context", "ChebError", "load_library", "holstein_csr_host", "holstein_occupations",
+    "Context", "ChebError", "load_library", "holstein_csr_host", "holstein_occupations", "region_sum_noalloc",
     "ZIGZAG", "ARMCHAIR", "KEEP_CHECKPOINTS", "NO_CHECK", "GRAPH", "NO_PERSISTENT", "SINGLE_ORDER",
     "SCHED_LEVELS", "SCHED_PERSISTENT", "SCHED_PAIRS", "SCHED_DEEP", "ADJ_STEP", "ADJ_SQRTM", "ADJ_REVERSE",
 ]

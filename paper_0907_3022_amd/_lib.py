@@ -75,6 +75,7 @@ _SIGS = {
     "chebtd_set_check_tol": (C.c_int, [C.c_void_p, C.c_double]),
     "chebtd_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "chebtd_region_sum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chebtd_region_sum_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "chebtd_norm_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "chebtd_holstein_obs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),

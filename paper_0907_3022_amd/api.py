@@ -65,6 +65,23 @@ def holstein_occupations(L_sites: int, nph: int) -> np.ndarray:
     return occ.reshape(cnt.value, L_sites)
 
 
+def region_sum_noalloc(psi, mask, out, stream=None):
+    """sum_i mask_i |psi_i|^2 into out[0] without any device allocation (the
+    library's fixed per-GPU scratch; chebtd_region_sum_noalloc).  psi:
+    complex128, mask: uint8, out: float64 CUDA tensors the caller owns;
+    stream: a torch stream (default: the current one)."""
+    torch = _torch()
+    n = psi.numel()
+    p = _need(psi, torch.complex128, n, "psi")
+    m = _need(mask, torch.uint8, n, "mask")
+    o = _need(out, torch.float64, None, "out")
+    if out.numel() < 1:
+        raise ValueError("out must hold one value")
+    st = stream if stream is not None else torch.cuda.current_stream(psi.device)
+    L.check(L.lib().chebtd_region_sum_noalloc(p, m, n, o, C.c_void_p(st.cuda_stream)))
+    return out
+
+
 class Context:
     """A chebtd context on the current GPU and torch stream."""
 
