@@ -254,19 +254,49 @@ def bench_holstein(torch, P, K):
         ctx.propagate(psi, 5, None, None, P.NO_CHECK)
         psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
         t = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
-        ms_iter, kname, _ = ctx.time_recursion_kernel(100)
-        # matrix-free rows: the vectors plus the raise/lower tables (2 x int32),
-        # the occupation (uint8) and the configuration total (uint8 per L rows)
-        bytes_row = CSR_VEC_BYTES + 4 + 4 + 1 + 1.0 / p["L"]
+        ms_iter, kname, _ = ctx.time_recursion_kernel(300)
+        bytes_row, bytes_row_eager = hol_bytes(p["L"])
         n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
         out[f"g2={g2}"] = dict(n=n, M=M, steps=K, seconds=t, hv_per_s=K * M / t,
                                kernel=kname, kernel_ms=ms_iter,
                                kernel_GBs=bytes_row * n / (ms_iter * 1e-3) / 1e9,
-                               bytes_per_row_order=bytes_row,
+                               step_equivalent_GBs=bytes_row_eager * n / (ms_iter * 1e-3) / 1e9,
+                               bytes_per_row_order=bytes_row, bytes_per_row_order_acc_every_order=bytes_row_eager,
                                csr_bytes_per_row_order=HOL_CSR_BYTES,
                                total_phonons=float(nph_i.sum()), electron_density_sum=float(n_i.sum()))
         ctx.close()
+        # the same matrix stored as CSR, through the general CSR kernel
+        rowptr, col, val = P.holstein_csr_host(p["L"], p["nph"], p["t"], p["w0"], np.sqrt(g2), 0.0,
+                                               p["periodic"])
+        r_d, c_d, v_d = (torch.from_numpy(a).cuda() for a in (rowptr, col, val))
+        cs = P.Context()
+        cs.csr(r_d, c_d, v_d)
+        cs.set_bounds(lo, hi, 0.01)
+        cs.plan(p["dt"])
+        psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
+        cs.propagate(psi, 5, None, None, P.NO_CHECK)
+        psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
+        t_csr = timed(torch, lambda: cs.propagate(psi, K, None, None, P.NO_CHECK))
+        ms_csr, kname_csr, _ = cs.time_recursion_kernel(300)
+        csr_bytes = HOL_CSR_BYTES - 32 + 32.0 / 3.0  # acc on one order in three
+        out[f"g2={g2}"]["csr"] = dict(nnz=int(rowptr[-1]), seconds=t_csr, hv_per_s=K * M / t_csr,
+                                      kernel=kname_csr, kernel_ms=ms_csr, bytes_per_row_order=csr_bytes,
+                                      kernel_GBs=csr_bytes * n / (ms_csr * 1e-3) / 1e9,
+                                      step_equivalent_GBs=HOL_CSR_BYTES * n / (ms_csr * 1e-3) / 1e9)
+        cs.close()
     return out
+
+
+def hol_bytes(L):
+    """Algorithmic bytes per state and order of the matrix-free Holstein walk:
+    v_k, v_{k-1} read and v_{k+1} written (48), the raise/lower tables
+    (2 x int32), the occupation (uint8), the configuration total (uint8 per L
+    states), and acc read and written (32) on one order in three (the walk
+    adds three orders' weights at once); and the same with acc every order."""
+    tables = 4 + 4 + 1 + 1.0 / L
+    lazy = 48 + tables + 32.0 / 3.0
+    eager = 48 + tables + 32
+    return lazy, eager
 
 
 def bench_polaron_paper(torch, P):
@@ -304,15 +334,17 @@ def bench_polaron_paper(torch, P):
         n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
         snaps.append(dict(t=ts, n=n_i.round(6).tolist(), nph=nph_i.round(6).tolist(),
                           chi=chi.round(6).tolist(), sum_n=float(n_i.sum())))
-    ms_iter, kname, _ = ctx.time_recursion_kernel(10)
+    ms_iter, kname, _ = ctx.time_recursion_kernel(30)
     orders = int(round(p["snapshots"][-1] / p["dt"])) * M
-    bytes_row = CSR_VEC_BYTES + 4 + 4 + 1 + 1.0 / L
+    bytes_row, bytes_row_eager = hol_bytes(L)
     ctx.close()
     del psi
     torch.cuda.empty_cache()
     return dict(workload="polaron_L18_nph11", states=n, M=M, dt=p["dt"], build_seconds=build_s,
                 propagate_seconds=run_s, orders=orders, hv_per_s=orders / run_s,
                 kernel=kname, kernel_ms=ms_iter, kernel_GBs=bytes_row * n / (ms_iter * 1e-3) / 1e9,
+                step_equivalent_GBs=bytes_row_eager * n / (ms_iter * 1e-3) / 1e9,
+                bytes_per_row_order=bytes_row, bytes_per_row_order_acc_every_order=bytes_row_eager,
                 device_GB=(3 * 16 + 9) * n / 1e9, snapshots=snaps, max_norm_deviation=max(abs(x - 1) for x in norms))
 
 

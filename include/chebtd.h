@@ -410,7 +410,9 @@ int chebtd_adjoint_run(chebtd_ctx *ctx, int64_t run_id, double *gbar_dev, double
  * advances.  On the multi-order path that is the pass the step runs most
  * often after its head (chebtd_plan_passes; 2 for the two-orders kernel, 3..6
  * for the deep kernel), else 1; CHEBTD_SINGLE_ORDER in `flags` times the
- * one-order kernel.  Needs a plan.  Synchronises.
+ * one-order kernel.  The Holstein and CSR kernels are timed in the pattern a
+ * step runs them: two launches without the accumulator for every one that
+ * updates it with three orders.  Needs a plan.  Synchronises.
  * name_out and orders_out may be NULL. */
 int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, double *ms_per_launch,
                                  const char **name_out, int *orders_out);

@@ -432,7 +432,9 @@ int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0, cons
     // (the size-based choice groups sites only past 2^20 configurations)
     c->hol_spt = 0;
     if (const char *env = std::getenv("CHEBTD_HOL_SPT")) c->hol_spt = std::max(0, std::atoi(env));
-    c->hol_remap = 0;
+    // XCD-contiguous block order for the walk (measured on MI355X at the
+    // polaron size: 14.6 -> 13.6 ms per order); CHEBTD_HOL_REMAP=0 turns it off
+    c->hol_remap = 1;
     if (const char *env = std::getenv("CHEBTD_HOL_REMAP")) c->hol_remap = std::atoi(env) ? 1 : 0;
     return ensure_partials(c);
 }

@@ -189,7 +189,27 @@ struct CsrRow {
     {
         const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
         double sx = 0.0, sy = 0.0;
-        for (int64_t p = p0; p < p1; ++p) {
+        int64_t p = p0;
+        // four entries at a time: their values and columns, then the four
+        // gathered vector elements, are in flight together (rows of the
+        // Holstein matrix hold 3 to 5 entries); the sum keeps the entry order
+        for (; p + 4 <= p1; p += 4) {
+            double2 h[4], x[4];
+            int32_t cc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                h[q] = op.val[p + q];
+                cc[q] = op.col[p + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = v[cc[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sx = fma(h[q].x, x[q].x, fma(-h[q].y, x[q].y, sx));
+                sy = fma(h[q].x, x[q].y, fma(h[q].y, x[q].x, sy));
+            }
+        }
+        for (; p < p1; ++p) {
             const double2 h = op.val[p];
             const double2 x = v[op.col[p]];
             sx = fma(h.x, x.x, fma(-h.y, x.y, sx));

@@ -186,6 +186,11 @@ hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *
                        double2 g0, double2 g1, double2 *ckpt, double *partials);
 hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *vprev,
                        double2 *acc, double2 g);
+// Holstein or CSR order with the accumulator brought up to date for the
+// last nacc (0 .. 3) orders: acc += ga v_{k-1} + gb v_k + gc v_{k+1}, leading
+// terms dropped; nacc = 0 leaves acc untouched (kernels.hip)
+hipError_t launch_iter_lazy(const Ctx &c, hipStream_t s, const double2 *vk, double2 *vprev, double2 *acc, int nacc,
+                            double2 ga, double2 gb, double2 gc);
 hipError_t launch_finalize_ne(hipStream_t s, const double *partials, int nparts, double a, double b,
                               double *norm_out, double *energy_out, int64_t *step_counter,
                               double *dst2);

@@ -149,8 +149,16 @@ __global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2
 // load and store of a site is contiguous across the wavefront except the
 // phonon partners v(s, up_s(r)) and v(s, dn_s(r)).
 // Thread t = grp * nconf + r covers sites [grp*spt, min(grp*spt + spt, L)).
+//
+// The accumulator is brought up to date only every third order (and at the
+// step's last): the pass forming v_{k+1} holds v_{k-1} (read before v_{k+1}
+// overwrites it), v_k and v_{k+1}, so it can add the weights of up to those
+// three orders at once; the other passes neither read nor write acc (57 of
+// the 89 B per state).  nacc = 0..3 terms: acc += ga v_{k-1} + gb v_k +
+// gc v_{k+1} with the leading terms dropped.
 __global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int remap, const double2 *__restrict__ vk,
-                                                     double2 *vprev, double2 *__restrict__ acc, double2 g)
+                                                     double2 *vprev, double2 *__restrict__ acc, int nacc,
+                                                     double2 ga, double2 gb, double2 gc)
 {
     const uint32_t C = op.nconf, L = (uint32_t)op.L;
     const uint32_t ngrp = (L + (uint32_t)spt - 1) / (uint32_t)spt;
@@ -205,20 +213,39 @@ __global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int rema
         const double hx = left.x + right.x, hy = left.y + right.y;
         const double hvx = fma(d, cur.x, fma(-op.t, hx, -gw * px));
         const double hvy = fma(d, cur.y, fma(-op.t, hy, -gw * py));
-        iter_body((int64_t)i, make_double2(op.s2 * hvx, op.s2 * hvy), vprev, acc, g);
+        const double2 p = vprev[i];
+        const double2 nv = csub(make_double2(op.s2 * hvx, op.s2 * hvy), p);
+        vprev[i] = nv;
+        if (nacc > 0) {  // uniform across the launch
+            double2 a = acc[i];
+            if (nacc >= 3) a = cfma(ga, p, a);
+            if (nacc >= 2) a = cfma(gb, cur, a);
+            acc[i] = cfma(gc, nv, a);
+        }
         left = cur;
         cur = right;
     }
 }
 
+// The accumulator as in the Holstein walk: up to three orders' weights at
+// once (nacc terms), none on the other orders.
 __global__ __launch_bounds__(kBlock) void k_iter_csr(OpCsr op, const double2 *__restrict__ vk,
-                                                     double2 *vprev, double2 *__restrict__ acc,
-                                                     double2 g)
+                                                     double2 *vprev, double2 *__restrict__ acc, int nacc,
+                                                     double2 ga, double2 gb, double2 gc)
 {
     const int64_t i = CsrRow::row(op);
     if (i < 0) return;
     const double2 vi = vk[i];
-    iter_body(i, CsrRow::apply2(op, i, vk, vi), vprev, acc, g);
+    const double2 h2 = CsrRow::apply2(op, i, vk, vi);
+    const double2 p = vprev[i];
+    const double2 nv = csub(h2, p);
+    vprev[i] = nv;
+    if (nacc > 0) {  // uniform across the launch
+        double2 a = acc[i];
+        if (nacc >= 3) a = cfma(ga, p, a);
+        if (nacc >= 2) a = cfma(gb, vi, a);
+        acc[i] = cfma(gc, nv, a);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -591,27 +618,35 @@ hipError_t launch_iter(const Ctx &c, hipStream_t s, const double2 *vk, double2 *
                                vprev, acc, g);
         break;
     case HKind::Csr:
-        hipLaunchKernelGGL(k_iter_csr, grid, block, 0, s, make_csr(c), vk, vprev, acc, g);
-        break;
-    case HKind::Holstein: {
-        // sites per thread (measured on MI355X): all of them up to ~1M
-        // configurations (L = 10 ring, 185k: 27.9 us against 31.6 us for two
-        // per thread); beyond, groups of at most 9 sites keep the wavefronts
-        // in flight on fewer site blocks at a time (L = 18 polaron, 34.6M
-        // configurations: 12.0 ms against 14.7 ms for all 18)
-        const int64_t C = c.hol_nconf, L = c.hol_L;
-        const int64_t groups = C <= ((int64_t)1 << 20) ? 1 : (L + 8) / 9;
-        const int spt = c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, L)
-                                      : (int)((L + groups - 1) / groups);
-        const int64_t ngrp = (L + spt - 1) / spt;
-        const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), block, 0, s, make_hol(c), spt, c.hol_remap, vk, vprev,
-                           acc, g);
-        break;
-    }
+    case HKind::Holstein:
+        return launch_iter_lazy(c, s, vk, vprev, acc, 1, make_double2(0.0, 0.0), make_double2(0.0, 0.0), g);
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_iter_lazy(const Ctx &c, hipStream_t s, const double2 *vk, double2 *vprev, double2 *acc, int nacc,
+                            double2 ga, double2 gb, double2 gc)
+{
+    if ((c.kind != HKind::Holstein && c.kind != HKind::Csr) || nacc < 0 || nacc > 3) return hipErrorInvalidValue;
+    if (c.kind == HKind::Csr) {
+        hipLaunchKernelGGL(k_iter_csr, dim3((unsigned)grid_blocks(c)), dim3(kBlock), 0, s, make_csr(c), vk, vprev, acc,
+                           nacc, ga, gb, gc);
+        return hipGetLastError();
+    }
+    // sites per thread (measured on MI355X): all of them up to ~1M
+    // configurations (L = 10 ring, 185k: 27.9 us against 31.6 us for two
+    // per thread); beyond, groups of at most 9 sites keep the wavefronts
+    // in flight on fewer site blocks at a time (L = 18 polaron, 34.6M
+    // configurations: 12.0 ms against 14.7 ms for all 18)
+    const int64_t C = c.hol_nconf, L = c.hol_L;
+    const int64_t groups = C <= ((int64_t)1 << 20) ? 1 : (L + 8) / 9;
+    const int spt = c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, L) : (int)((L + groups - 1) / groups);
+    const int64_t ngrp = (L + spt - 1) / spt;
+    const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), dim3(kBlock), 0, s, make_hol(c), spt, c.hol_remap, vk, vprev,
+                       acc, nacc, ga, gb, gc);
     return hipGetLastError();
 }
 

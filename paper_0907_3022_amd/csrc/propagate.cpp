@@ -143,10 +143,22 @@ hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, doubl
                                static_cast<int64_t *>(c->counter.p), nullptr);
         if (e != hipSuccess) return e;
     }
+    // the Holstein and CSR operators add the weighted orders to acc every
+    // third order and at the step's last (acc holds orders 0 .. done); the
+    // stencils every order
+    int done = 1;
+    const bool lazy = c->kind == HKind::Holstein || c->kind == HKind::Csr;
     for (int k = 1; k <= c->M - 1; ++k) {
         double2 *vk = (k & 1) ? A : cur;
         double2 *vprev = (k & 1) ? cur : A;
-        e = launch_iter(*c, s, vk, vprev, nxt, weight(c, k + 1));
+        if (lazy) {
+            const int pend = k + 1 - done;  // orders done+1 .. k+1 not yet in acc
+            const int nacc = (pend == 3 || k + 1 == c->M) ? pend : 0;
+            e = launch_iter_lazy(*c, s, vk, vprev, nxt, nacc, weight(c, k - 1), weight(c, k), weight(c, k + 1));
+            if (nacc) done = k + 1;
+        } else {
+            e = launch_iter(*c, s, vk, vprev, nxt, weight(c, k + 1));
+        }
         if (e != hipSuccess) return e;
     }
     if (ends && c->M >= 1) {
@@ -457,6 +469,9 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
                                          weight(c, 1), weight(c, 2), nullptr, nullptr)
                            : launch_pair(*c, s, c->pair_rows, false, V0, V1, V2, V3, acc, make_double2(0, 0),
                                          weight(c, 1), weight(c, 2), nullptr, nullptr);
+        if (c->kind == HKind::Holstein || c->kind == HKind::Csr)  // the step's pattern: acc every third order
+            return launch_iter_lazy(*c, s, (i & 1) ? V1 : V0, (i & 1) ? V0 : V1, acc, i % 3 == 2 ? 3 : 0,
+                                    weight(c, 1), weight(c, 1), weight(c, 1));
         return launch_iter(*c, s, (i & 1) ? V1 : V0, (i & 1) ? V0 : V1, acc, weight(c, 1));
     };
     if (e == hipSuccess) e = one(0);  // untimed: pages in code and caches

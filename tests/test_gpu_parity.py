@@ -586,3 +586,29 @@ def test_full_holstein_ring(torch, cheb, g2, state):
     assert ctx.n == 1_847_560
     assert plan.M == (13 if g2 == 0.5 else 14)
     assert_state_close(psi, ref)
+
+
+@pytest.mark.parametrize("g2", [0.5, 2.0])
+def test_full_holstein_ring_as_general_csr(torch, cheb, g2):
+    # the L = 10, N_ph <= 10 ring (1,847,560 rows, 7.39M entries) through the
+    # general CSR kernel, from the library's host-built CSR, against the
+    # oracle's own eq. (ghm) matrix, from a dense state
+    p = W.HOLSTEIN.params
+    case = holstein_case(p["L"], p["nph"], g2, p["periodic"], state="dense")
+    rowptr, col, val = cheb.holstein_csr_host(p["L"], p["nph"], 1.0, 1.0, math.sqrt(g2), 0.0, p["periodic"])
+    assert rowptr[-1] == 4 * 1_847_560
+    ctx = cheb.Context()
+    r_d, c_d, v_d = dev(torch, rowptr), dev(torch, col), dev(torch, val)
+    ctx.csr(r_d, c_d, v_d)
+    emin, emax = case["H"].gershgorin()
+    ctx.set_bounds(emin, emax)
+    plan = O.Plan(emin, emax, p["dt"])
+    assert ctx.plan(p["dt"]) == plan.M
+    psi = dev(torch, case["psi0"])
+    nrm = torch.zeros(3, dtype=torch.float64, device="cuda")
+    say(f"[gpu] Holstein ring as CSR, g2={g2}, M={plan.M}")
+    ctx.propagate(psi, 3, nrm)
+    torch.cuda.synchronize()
+    ref, rn, _ = O.propagate(case["H"], plan, case["psi0"], 3, want_obs=True)
+    assert_state_close(host(psi), ref)
+    np.testing.assert_allclose(host(nrm), rn, rtol=1e-12)
