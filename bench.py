@@ -51,11 +51,12 @@ def log(msg):
 
 
 def source_hash():
-    """Hash of the recursion kernels' source with comments and whitespace
+    """Hash of the multi-order kernels' source (the deep and pair walks, their
+    launchers and the shared device helpers) with comments and whitespace
     removed: what the committed byte counters were measured on."""
     import re
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_ops.h", "pair.hip", "pair_walk.h", "deep_walk.h", "pair.h"):
+    for f in ("device_ops.h", "pair.hip", "pair_walk.h", "deep_walk.h", "pair.h"):
         with open(os.path.join(ROOT, "paper_0907_3022_amd", "csrc", f), encoding="utf-8") as fh:
             code = fh.read()
         code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
