@@ -717,6 +717,13 @@ def main():
     if "sweep" in sections:
         log("[bench] ribbon size sweep")
         extra["sweep"] = bench_sweep(torch, P, [(128, 8192), (256, 16384), (512, 32768), (1024, 65536)])
+        # the same pass where its working set streams HBM (the headline's fits
+        # the last-level cache): the sweep's points from 16M sites
+        hbm = [r for r in extra["sweep"] if r["sites"] >= (16 << 20)]
+        line["roofline"]["hbm_regime"] = [
+            {"shape": r["shape"], "kernel": r["kernel"], "kernel_ms_per_launch": r["kernel_ms"],
+             "achieved": r["GBs"], "frac": r["GBs"] / HBM_PEAK_GBS,
+             "frac_of_measured_ceiling": r["GBs"] / tri_hbm if tri_hbm > 0 else None} for r in hbm]
     if "shard" in sections:
         log("[bench] one GPU's share of a ribbon cut into 2, 4, 8 slabs")
         extra["shard"] = bench_shard(torch, P)
