@@ -621,6 +621,73 @@ def cpu_baseline(target_seconds=12.0):
                        f"serial C oracle, {t:.1f} s; host CPU: {cpu}")
 
 
+def _oracle_batch_system(args):
+    """One batched ribbon through the serial oracle for `steps` steps (a
+    worker of cpu_other_workloads' process pool): (site-orders, seconds)."""
+    width, length, Wd, seed, dt, steps = args
+    import oracle as O
+    eps, psi0 = W.ribbon_inputs(width, length, Wd, seed)
+    H = O.honeycomb(width, length, eps)
+    plan = O.Plan(float(eps.min()) - 3.0, float(eps.max()) + 3.0, dt)
+    t0 = time.perf_counter()
+    O.propagate(H, plan, psi0, steps)
+    return width * length * plan.M * steps, time.perf_counter() - t0
+
+
+def cpu_other_workloads(gpu_extra):
+    """The serial oracle on bounded samples of the other workloads, beside the
+    GPU's rate for the same work: the double well and the Holstein ring on one
+    core, and one step of all 256 batched ribbons over a pool of host cores."""
+    import multiprocessing as mp
+
+    import oracle as O
+    out = {}
+    # double well (config 1): a few steps of M = 7256
+    p = W.DOUBLE_WELL.params
+    x, dx, V, psi0 = W.double_well_inputs(p["n"], p["xmin"], p["xmax"], p["a"], p["b"], p["x0"],
+                                          p["sigma"], p["k0"])
+    H = O.chain1d(V, dx)
+    lo, hi = H.gershgorin()
+    plan = O.Plan(lo, hi, p["dt"])
+    t0 = time.perf_counter()
+    O.propagate(H, plan, psi0, 4)
+    t = time.perf_counter() - t0
+    row = dict(cores=1, sample=f"4 steps, M = {plan.M}", oracle_orders_per_s=4 * plan.M / t)
+    if "double_well" in gpu_extra:
+        row["gpu_orders_per_s"] = gpu_extra["double_well"]["orders_per_s"]
+    out["double_well"] = row
+    # Holstein ring (config 3), g^2 = 2
+    p = W.HOLSTEIN.params
+    H = O.holstein(p["L"], p["nph"], p["t"], p["w0"], np.sqrt(2.0), 0.0, p["periodic"])
+    lo, hi = H.gershgorin()
+    plan = O.Plan(lo, hi, p["dt"])
+    psi0 = W.holstein_vacuum_site(p["L"], 0, O.holstein_nconf(p["L"], p["nph"]))
+    t0 = time.perf_counter()
+    O.propagate(H, plan, psi0, 2)
+    t = time.perf_counter() - t0
+    row = dict(cores=1, sample=f"2 steps, M = {plan.M}, D = {H.n}", oracle_hv_per_s=2 * plan.M / t)
+    if "holstein" in gpu_extra:
+        row["gpu_hv_per_s"] = gpu_extra["holstein"]["g2=2.0"]["hv_per_s"]
+    out["holstein_ring"] = row
+    # batched (config 4): one step of every ribbon, the systems spread over
+    # a pool of host processes
+    pb = W.BATCHED.params
+    descs = W.batched_ribbons(pb["nsys"], pb["seed_base"])
+    cores = max(1, min(16, os.cpu_count() or 1))
+    jobs = [(d.width, d.length, d.W, d.seed, pb["dt"], 1) for d in descs]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_batch_system, jobs, chunksize=4)
+    t = time.perf_counter() - t0
+    row = dict(cores=cores, sample=f"1 step of all {len(descs)} ribbons, {cores} processes (pool start included)",
+               oracle_site_orders_per_s=sum(r[0] for r in res) / t,
+               oracle_site_orders_per_s_per_core=sum(r[0] for r in res) / sum(r[1] for r in res))
+    if "batched" in gpu_extra:
+        row["gpu_site_orders_per_s"] = gpu_extra["batched"]["site_orders_per_s"]
+    out["batched"] = row
+    return out
+
+
 # ---------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
@@ -733,6 +800,8 @@ def main():
     if "cpu" in sections:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()
+        log("[bench] CPU oracle on the other workloads")
+        extra["cpu_other_workloads"] = cpu_other_workloads(extra)
     else:
         line["cpu_baseline"] = None
     line["extra"] = extra
