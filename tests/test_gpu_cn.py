@@ -5,6 +5,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from test_gpu_parity import assert_state_close
 
 pytestmark = pytest.mark.gpu
 
@@ -40,12 +41,15 @@ def run(torch, cheb, V, dx, psi0, dt, S):
 # that (two per thread), partly filled chunks, the 4096 maximum
 @pytest.mark.parametrize("n", [2, 37, 64, 256, 257, 1000, 2048, 4095, 4096])
 @pytest.mark.parametrize("S", [1, 7])
-def test_cn_matches_oracle(torch, cheb, n, S):
+@pytest.mark.parametrize("state", ["packet", "dense"])
+def test_cn_matches_oracle(torch, cheb, n, S, state):
     x, dx, V, psi0 = W.double_well_inputs(n)
+    if state == "dense":  # every site of every thread's chunk carries amplitude
+        psi0 = W.random_state(n, 300 + n)
     dt = 0.05
     ref = O.crank_nicolson_1d(V, dx, psi0, dt, S)
     got = run(torch, cheb, V, dx, psi0, dt, S)
-    assert rel_l2(got, ref) <= 1e-10
+    assert_state_close(got, ref)
 
 
 def test_cn_double_well_workload(torch, cheb):

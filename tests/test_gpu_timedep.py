@@ -6,6 +6,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from test_gpu_parity import assert_state_close
 
 pytestmark = pytest.mark.gpu
 
@@ -28,11 +29,12 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+@pytest.mark.parametrize("state", ["packet", "dense"])
 @pytest.mark.parametrize("n", [300, 5003])
-def test_chain_driven(torch, cheb, n):
+def test_chain_driven(torch, cheb, n, state):
     x, dx = W.chain_grid(n, -8.0, 8.0)
     V0 = W.quartic_well(x, 0.05, 3.0)
-    psi0 = W.gaussian_1d(x, -3.0, 0.7, 1.0)
+    psi0 = W.gaussian_1d(x, -3.0, 0.7, 1.0) if state == "packet" else W.random_state(n, 90 + n)
     E, w, dt, K = 0.5, 2.0, 0.01, 9
     sched = np.stack([V0 + E * np.sin(w * (s + 0.5) * dt) * x for s in range(K)])
     lo, hi = O.chain1d(V0, dx).gershgorin()
@@ -49,7 +51,7 @@ def test_chain_driven(torch, cheb, n):
     psi = torch.from_numpy(psi0.copy()).cuda()
     ctx.propagate_td(psi, torch.from_numpy(sched).cuda())
     torch.cuda.synchronize()
-    assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+    assert_state_close(psi.cpu().numpy(), ref)
     # the built Hamiltonian is restored: a plain step uses V0 again
     p2 = torch.from_numpy(psi0.copy()).cuda()
     ctx.propagate(p2, 2)
@@ -57,9 +59,12 @@ def test_chain_driven(torch, cheb, n):
     assert rel_l2(p2.cpu().numpy(), O.propagate(O.chain1d(V0, dx), plan, psi0, 2)) <= 1e-10
 
 
-def test_ribbon_ramped_disorder(torch, cheb):
+@pytest.mark.parametrize("state", ["packet", "dense"])
+def test_ribbon_ramped_disorder(torch, cheb, state):
     w, l, K, dt = 12, 333, 7, 1.0
     eps0, psi0 = W.ribbon_inputs(w, l, 0.5, 3)
+    if state == "dense":
+        psi0 = W.random_state(w * l, 93)
     sched = np.stack([eps0 * (1.0 + 0.1 * s) + 0.05 * s for s in range(K)])
     lo = min(O.honeycomb(w, l, e).gershgorin()[0] for e in sched)
     hi = max(O.honeycomb(w, l, e).gershgorin()[1] for e in sched)
@@ -77,7 +82,7 @@ def test_ribbon_ramped_disorder(torch, cheb):
     en = torch.zeros(K, dtype=torch.float64, device="cuda")
     ctx.propagate_td(psi, torch.from_numpy(sched).cuda(), nrm, en)
     torch.cuda.synchronize()
-    assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+    assert_state_close(psi.cpu().numpy(), ref)
     # energy of the state entering step s under that step's H
     p = psi0.copy()
     for s in range(K):
@@ -87,7 +92,8 @@ def test_ribbon_ramped_disorder(torch, cheb):
         p = O.propagate(Hs, plan, p, 1)
 
 
-def test_holstein_biased_barrier(torch, cheb):
+@pytest.mark.parametrize("state", ["packet", "dense"])
+def test_holstein_biased_barrier(torch, cheb, state):
     L, nph, K, dt = 6, 4, 8, 0.2
     g = np.full(L, np.sqrt(0.5))
     D0 = np.zeros(L)
@@ -96,6 +102,8 @@ def test_holstein_biased_barrier(torch, cheb):
     hi = max(O.holstein(L, nph, 1.0, 1.0, g, d, False).gershgorin()[1] for d in sched)
     plan = O.Plan(lo, hi, dt)
     psi0 = W.holstein_packet(L, O.holstein_nconf(L, nph), 2.0, 1.0, 0.4)
+    if state == "dense":
+        psi0 = W.random_state(psi0.size, 94)
     ref = psi0.copy()
     for s in range(K):
         ref = O.propagate(O.holstein(L, nph, 1.0, 1.0, g, sched[s], False), plan, ref, 1)
@@ -106,7 +114,7 @@ def test_holstein_biased_barrier(torch, cheb):
     psi = torch.from_numpy(psi0.copy()).cuda()
     ctx.propagate_td(psi, torch.from_numpy(sched).cuda())
     torch.cuda.synchronize()
-    assert rel_l2(psi.cpu().numpy(), ref) <= 1e-10
+    assert_state_close(psi.cpu().numpy(), ref)
 
 
 def test_td_rejects_short_stride_and_checkpoints(torch, cheb):
