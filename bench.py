@@ -256,7 +256,7 @@ def bench_holstein(torch, P, K):
         psi = torch.from_numpy(W.holstein_vacuum_site(p["L"], 0, nconf)).cuda()
         t = timed(torch, lambda: ctx.propagate(psi, K, None, None, P.NO_CHECK))
         ms_iter, kname, _ = ctx.time_recursion_kernel(300)
-        bytes_row, bytes_row_eager = hol_bytes(p["L"])
+        bytes_row, bytes_row_eager = hol_bytes(p["L"], kname)
         n_i, nph_i, chi = (v.cpu().numpy() for v in ctx.holstein_obs(psi))
         out[f"g2={g2}"] = dict(n=n, M=M, steps=K, seconds=t, hv_per_s=K * M / t,
                                kernel=kname, kernel_ms=ms_iter,
@@ -288,14 +288,17 @@ def bench_holstein(torch, P, K):
     return out
 
 
-def hol_bytes(L):
-    """Algorithmic bytes per state and order of the matrix-free Holstein walk:
-    v_k, v_{k-1} read and v_{k+1} written (48), the raise/lower tables
-    (2 x int32), the occupation (uint8), the configuration total (uint8 per L
-    states), and acc read and written (32) on one order in three (the walk
-    adds three orders' weights at once); and the same with acc every order."""
+def hol_bytes(L, kname):
+    """Algorithmic bytes per state and order of the matrix-free Holstein walk
+    as it runs: v_k, v_{k-1} read and v_{k+1} written (48), acc read and
+    written (32) on one order in three (the walk adds three orders' weights at
+    once), and, in the walk that reads them (k_iter_hol<false>, chosen where
+    the last-level cache holds them), the raise/lower tables (2 x int32), the
+    occupation (uint8) and the configuration total (uint8 per L states); the
+    walk that ranks the phonon partners itself (k_iter_hol<true>) reads no
+    table.  Second: the table walk updating acc every order, for comparison."""
     tables = 4 + 4 + 1 + 1.0 / L
-    lazy = 48 + tables + 32.0 / 3.0
+    lazy = 48 + 32.0 / 3.0 + (0.0 if kname.endswith("<true>") else tables)
     eager = 48 + tables + 32
     return lazy, eager
 
@@ -337,7 +340,7 @@ def bench_polaron_paper(torch, P):
                           chi=chi.round(6).tolist(), sum_n=float(n_i.sum())))
     ms_iter, kname, _ = ctx.time_recursion_kernel(30)
     orders = int(round(p["snapshots"][-1] / p["dt"])) * M
-    bytes_row, bytes_row_eager = hol_bytes(L)
+    bytes_row, bytes_row_eager = hol_bytes(L, kname)
     ctx.close()
     del psi
     torch.cuda.empty_cache()

@@ -252,7 +252,7 @@ int chebtd_destroy(chebtd_ctx *ctx)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : {&c->vA, &c->vB, &c->vC, &c->vD, &c->partials, &c->results, &c->counter, &c->gamma_dev,
                       &c->hol_occ, &c->hol_up, &c->hol_dn,
-                      &c->hol_tot, &c->hol_site})
+                      &c->hol_tot, &c->hol_site, &c->hol_binom})
         release(*b);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->ev_a) (void)hipEventDestroy(c->ev_a);
@@ -428,8 +428,39 @@ int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0, cons
     c->hol_t = t;
     c->hol_w0 = w0;
     c->hol_periodic = periodic ? 1 : 0;
+    // binomials for the walk's own partner ranks (C(a, m) < 2^31 here since
+    // the largest, C(nph + L, L - 1), is below L * nconf).  The walk ranks the
+    // partners itself where the tables would stream from HBM (measured on
+    // MI355X: the L = 18 polaron, 6.2e8 states, 10.6 -> 9.4 ms per order),
+    // and reads the tables where the last-level cache holds them (the L = 10
+    // ring, 1.85M states: 23.2 us against 30.8 us ranking); CHEBTD_HOL_RANK=1
+    // or 0 forces either
+    c->hol_brows = 0;
+    {
+        const int brows = nph + L + 2, bcols = L + 1;
+        const char *renv = std::getenv("CHEBTD_HOL_RANK");
+        const bool want = renv ? std::atoi(renv) != 0 : h.n > ((int64_t)8 << 20);
+        if (want && (size_t)brows * bcols * sizeof(int32_t) <= (size_t)kHolBinomBytes) {
+            // Pascal's rule in 64 bits, stored saturated: the walk reads no
+            // entry past C(nph + L, L) = nconf
+            std::vector<int64_t> c64((size_t)brows * bcols, 0);
+            std::vector<int32_t> cb((size_t)brows * bcols, 0);
+            for (int a = 0; a < brows; ++a) {
+                c64[(size_t)a * bcols] = 1;
+                for (int m = 1; m <= std::min(a, L); ++m)
+                    c64[(size_t)a * bcols + m] = std::min<int64_t>(
+                        c64[(size_t)(a - 1) * bcols + m - 1] + (m <= a - 1 ? c64[(size_t)(a - 1) * bcols + m] : 0),
+                        INT32_MAX);
+            }
+            for (size_t q = 0; q < cb.size(); ++q) cb[q] = (int32_t)c64[q];
+            if ((rc = ensure(c, c->hol_binom, cb.size() * sizeof(int32_t), "holstein binomials"))) return rc;
+            e = hipMemcpy(c->hol_binom.p, cb.data(), cb.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(c, e, "chebtd_h_holstein binomials");
+            c->hol_brows = brows;
+        }
+    }
     // tuning and test override: electron sites per thread of the order walk
-    // (the size-based choice groups sites only past 2^20 configurations)
+    // (0: all L sites per thread)
     c->hol_spt = 0;
     if (const char *env = std::getenv("CHEBTD_HOL_SPT")) c->hol_spt = std::max(0, std::atoi(env));
     // XCD-contiguous block order for the walk (measured on MI355X at the

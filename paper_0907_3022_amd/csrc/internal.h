@@ -109,8 +109,13 @@ struct Ctx {
     int hol_periodic = 0;
     double hol_t = 0.0, hol_w0 = 0.0;
     const double *hol_delta = nullptr;  // per-step Delta_i during a time-dependent run
-    int hol_spt = 0;    // electron sites per thread of the walk; 0: chosen by size
+    int hol_spt = 0;    // electron sites per thread of the walk; 0: all L
     int hol_remap = 0;  // 1: XCD-contiguous configuration ranges in the walk
+    // binomial table C(a, m), a <= nph + L + 1, m <= L (row-major, L + 1 per
+    // row) from which the walk ranks the phonon partners itself; empty when
+    // it would not fit the walk's LDS budget (the walk then reads the tables)
+    DevBuf hol_binom;
+    int hol_brows = 0;
 
     // bounds and plan
     bool has_bounds = false;
@@ -180,6 +185,9 @@ int holstein_build(int L, int nph, double t, double w0, const double *g, const d
 // Kernel launchers (kernels.hip).  All enqueue on `s` and return hipError_t.
 // ---------------------------------------------------------------------------
 constexpr int kBlock = 256;
+// LDS the Holstein walk may give its binomial table (beyond it, the walk
+// reads the per-state partner tables instead)
+constexpr int kHolBinomBytes = 16384;
 int64_t grid_blocks(const Ctx &c);
 
 hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *v1, double2 *acc,

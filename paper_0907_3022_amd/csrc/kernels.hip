@@ -156,12 +156,37 @@ __global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2
 // three orders at once; the other passes neither read nor write acc (57 of
 // the 89 B per state).  nacc = 0..3 terms: acc += ga v_{k-1} + gb v_k +
 // gc v_{k+1} with the leading terms dropped.
-__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int remap, const double2 *__restrict__ vk,
-                                                     double2 *vprev, double2 *__restrict__ acc, int nacc,
-                                                     double2 ga, double2 gb, double2 gc)
+//
+// RANK: the thread ranks the partners itself instead of reading the
+// per-state tables (9 B per state fewer).  Configurations of total T are
+// ranked by the combinatorial number system,
+//   rank(n) = C(T-1+L, L) + sum_{j<L-1} t_j,
+//   t_j = C(l_j + m_j, m_j) - C(l_j - n_j + m_j, m_j),
+// with l_j = T - n_0 - .. - n_{j-1} phonons left and m_j = L-1-j parts after
+// j.  n + e_s changes l_j by +1 for j <= s and leaves the terms past s
+// alone, so rank(n + e_s) = r + C(T+L-1, L-1) + sum_{j<s} (u_j - t_j)
+// + x_s - t_s, with u_j, x_s the terms at l_j + 1 (and n_s + 1 at s); and
+// rank(n - e_s) = r - C(T+L-2, L-1) + sum_{j<s} (d_j - t_j) + y_s - t_s at
+// l_j - 1.  Walking the sites in order, the thread takes the digits n_s
+// from r as it goes (unranking) and carries the two prefix sums.
+template <bool RANK>
+__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int remap, const int32_t *binom,
+                                                     int brows, const double2 *__restrict__ vk, double2 *vprev,
+                                                     double2 *__restrict__ acc, int nacc, double2 ga, double2 gb,
+                                                     double2 gc)
 {
-    const uint32_t C = op.nconf, L = (uint32_t)op.L;
-    const uint32_t ngrp = (L + (uint32_t)spt - 1) / (uint32_t)spt;
+    extern __shared__ int32_t sbin[];
+    const int32_t L = op.L, K = L + 1;  // binomial table: brows x (L + 1)
+    if constexpr (RANK) {
+        for (int q = threadIdx.x; q < brows * K; q += blockDim.x) sbin[q] = binom[q];
+        __syncthreads();
+    }
+    // C(a, m) from the table; zero outside it
+    auto cb = [&](int32_t a, int32_t m) -> int32_t {
+        return (a < 0 || a >= brows || m < 0 || m > L) ? 0 : sbin[a * K + m];
+    };
+    const uint32_t C = op.nconf, Lu = (uint32_t)L;
+    const uint32_t ngrp = (Lu + (uint32_t)spt - 1) / (uint32_t)spt;
     // remap: each XCD takes one contiguous range of configurations, so the
     // phonon partners that neighbouring wavefronts share meet in one L2
     const uint32_t lb = (uint32_t)logical_block(remap);
@@ -175,25 +200,89 @@ __global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int rema
         r -= C;
         ++grp;
     }
-    const uint32_t s0 = grp * (uint32_t)spt, s1 = min(s0 + (uint32_t)spt, L);
+    const uint32_t s0 = grp * (uint32_t)spt, s1 = min(s0 + (uint32_t)spt, Lu);
     const double2 zero = make_double2(0.0, 0.0);
-    const double wt = op.w0 * (double)op.tot[r] - op.b;
+    // RANK state: total T, phonons left, rank within the shell still to
+    // account for, and the two prefix sums of the partner ranks
+    int32_t T = 0, left = 0;
+    uint32_t within = 0;
+    int64_t dup = 0, ddn = 0;
+    // digit s of the configuration (unranking) and its term t_s; the prefix
+    // sums then take site s
+    auto digit = [&](int32_t s, int32_t &ns, int32_t &ts) {
+        if (s + 1 < L) {
+            const int32_t m = L - 1 - s;
+            const int32_t all = cb(left + m, m);
+            int32_t v = 0;
+            while (v < left && (uint32_t)(all - cb(left - (v + 1) + m, m)) <= within) ++v;
+            ts = all - cb(left - v + m, m);
+            within -= (uint32_t)ts;
+            ns = v;
+        } else {
+            ns = left;
+            ts = 0;
+        }
+    };
+    auto advance = [&](int32_t s, int32_t ns, int32_t ts) {
+        if (s + 1 < L) {
+            const int32_t m = L - 1 - s;
+            dup += (int64_t)(cb(left + 1 + m, m) - cb(left + 1 - ns + m, m)) - ts;
+            ddn += (int64_t)(cb(left - 1 + m, m) - cb(left - 1 - ns + m, m)) - ts;
+        }
+        left -= ns;
+    };
+    double wt;
+    if constexpr (RANK) {
+        while (T < (int32_t)brows - L - 2 && (uint32_t)cb(T + L, L) <= r) ++T;  // brows - L - 2 = nph
+        within = r - (T == 0 ? 0u : (uint32_t)cb(T - 1 + L, L));
+        left = T;
+        for (int32_t s = 0; s < (int32_t)s0; ++s) {  // digits before the group
+            int32_t ns, ts;
+            digit(s, ns, ts);
+            advance(s, ns, ts);
+        }
+        wt = op.w0 * (double)T - op.b;
+    } else {
+        wt = op.w0 * (double)op.tot[r] - op.b;
+    }
+    const bool can_up = RANK && T < (int32_t)brows - L - 2;
+    const int64_t up0 = RANK ? (int64_t)r + cb(T + L - 1, L - 1) : 0;
+    const int64_t dn0 = RANK ? (int64_t)r - cb(T + L - 2, L - 1) : 0;
     // v_k at sites s-1, s, s+1 of configuration r
-    double2 left = zero;
+    double2 left_v = zero;
     if (s0 > 0)
-        left = vk[(size_t)(s0 - 1) * C + r];
+        left_v = vk[(size_t)(s0 - 1) * C + r];
     else if (op.periodic)
-        left = vk[(size_t)(L - 1) * C + r];
+        left_v = vk[(size_t)(Lu - 1) * C + r];
     double2 cur = vk[(size_t)s0 * C + r];
     for (uint32_t s = s0; s < s1; ++s) {
         const size_t i = (size_t)s * C + r;
         double2 right = zero;
-        if (s + 1 < L)
+        if (s + 1 < Lu)
             right = vk[i + C];
         else if (op.periodic)
             right = vk[r];
-        const int32_t ru = op.up[i], rd = op.dn[i];
-        const uint32_t ni = op.occ[i];
+        int32_t ru, rd;
+        uint32_t ni;
+        if constexpr (RANK) {
+            int32_t ns, ts;
+            const int32_t si = (int32_t)s;
+            digit(si, ns, ts);
+            int64_t xs = 0, ys = 0;
+            if (si + 1 < L) {
+                const int32_t m = L - 1 - si;
+                xs = (int64_t)(cb(left + 1 + m, m) - cb(left - ns + m, m)) - ts;
+                ys = (int64_t)(cb(left - 1 + m, m) - cb(left - ns + m, m)) - ts;
+            }
+            ru = can_up ? (int32_t)(up0 + dup + xs) : -1;
+            rd = ns > 0 ? (int32_t)(dn0 + ddn + ys) : -1;
+            ni = (uint32_t)ns;
+            advance(si, ns, ts);
+        } else {
+            ru = op.up[i];
+            rd = op.dn[i];
+            ni = op.occ[i];
+        }
         const size_t base = (size_t)s * C;
         double px = 0.0, py = 0.0;
         if (ru >= 0) {
@@ -210,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int rema
         }
         const double d = op.Delta[s] + wt, gw = op.gw0[s];
         // hops: left and right are zero where an open chain ends
-        const double hx = left.x + right.x, hy = left.y + right.y;
+        const double hx = left_v.x + right.x, hy = left_v.y + right.y;
         const double hvx = fma(d, cur.x, fma(-op.t, hx, -gw * px));
         const double hvy = fma(d, cur.y, fma(-op.t, hy, -gw * py));
         const double2 p = vprev[i];
@@ -222,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int rema
             if (nacc >= 2) a = cfma(gb, cur, a);
             acc[i] = cfma(gc, nv, a);
         }
-        left = cur;
+        left_v = cur;
         cur = right;
     }
 }
@@ -635,18 +724,23 @@ hipError_t launch_iter_lazy(const Ctx &c, hipStream_t s, const double2 *vk, doub
                            nacc, ga, gb, gc);
         return hipGetLastError();
     }
-    // sites per thread (measured on MI355X): all of them up to ~1M
-    // configurations (L = 10 ring, 185k: 27.9 us against 31.6 us for two
-    // per thread); beyond, groups of at most 9 sites keep the wavefronts
-    // in flight on fewer site blocks at a time (L = 18 polaron, 34.6M
-    // configurations: 12.0 ms against 14.7 ms for all 18)
+    // sites per thread (measured on MI355X with the XCD-contiguous order and
+    // acc every third order): all of them (L = 10 ring: 23.2 us per order
+    // against 24.4 for groups of five; L = 18 polaron: 10.60 ms against 10.82
+    // for groups of nine and 10.88 for six); hol_spt > 0 groups them
     const int64_t C = c.hol_nconf, L = c.hol_L;
-    const int64_t groups = C <= ((int64_t)1 << 20) ? 1 : (L + 8) / 9;
-    const int spt = c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, L) : (int)((L + groups - 1) / groups);
+    const int spt = c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, L) : (int)L;
     const int64_t ngrp = (L + spt - 1) / spt;
     const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_iter_hol, dim3((unsigned)nb), dim3(kBlock), 0, s, make_hol(c), spt, c.hol_remap, vk, vprev,
-                       acc, nacc, ga, gb, gc);
+    if (c.hol_brows > 0) {
+        const size_t lds = (size_t)c.hol_brows * (size_t)(L + 1) * sizeof(int32_t);
+        hipLaunchKernelGGL(k_iter_hol<true>, dim3((unsigned)nb), dim3(kBlock), lds, s, make_hol(c), spt,
+                           c.hol_remap, static_cast<const int32_t *>(c.hol_binom.p), c.hol_brows, vk, vprev, acc,
+                           nacc, ga, gb, gc);
+    } else {
+        hipLaunchKernelGGL(k_iter_hol<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, make_hol(c), spt,
+                           c.hol_remap, nullptr, 0, vk, vprev, acc, nacc, ga, gb, gc);
+    }
     return hipGetLastError();
 }
 

@@ -426,7 +426,7 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
     // the multi-order kernel the step spends most of its passes in
     const int dp = pairs ? dominant_pass(*c) : 2;
     static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr",
-                                  "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol"};
+                                  "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol<true>", "k_iter_hol<false>"};
     // [edge][streaming stores][orders per pass]
     static const char *deep_names[2][2][kMaxDepth + 1] = {
         {{"", "", "", "k_deep<0,3,false,false>", "k_deep<0,4,false,false>", "k_deep<0,5,false,false>",
@@ -442,7 +442,7 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
                      : pairs ? (arm ? names[5] : names[4])
                      : c->kind == HKind::Chain    ? names[0]
                      : c->kind == HKind::Csr      ? names[3]
-                     : c->kind == HKind::Holstein ? names[6]
+                     : c->kind == HKind::Holstein ? names[c->hol_brows > 0 ? 6 : 7]
                      : (c->edge == CHEBTD_ZIGZAG ? names[1] : names[2]);
     if (name_out) *name_out = nm;
     if (orders_out) *orders_out = pairs ? dp : 1;

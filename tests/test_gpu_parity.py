@@ -222,8 +222,12 @@ def test_table2_ribbon_single_site(torch, cheb, dt):
 @pytest.mark.parametrize("L,nph,g2,periodic", [(4, 3, 0.5, True), (6, 4, 2.0, True), (5, 5, 0.5, False),
                                                (3, 6, 2.0, True), (1, 7, 0.5, False), (2, 5, 0.5, False)])
 @pytest.mark.parametrize("state", ["vacuum", "dense"])
-def test_holstein_parity_and_observables(torch, cheb, L, nph, g2, periodic, state):
+@pytest.mark.parametrize("rank", [None, True])
+def test_holstein_parity_and_observables(torch, cheb, hol_spt_env, L, nph, g2, periodic, state, rank):
+    # rank True: the walk ranks the phonon partners itself (its default
+    # only past 8M states); None: the size rule (the partner tables here)
     case = holstein_case(L, nph, g2, periodic, Delta=np.linspace(0, 0.5, L), state=state)
+    hol_spt_env(None, rank)
     ctx, psi, ref, nrm, rn, en, re, _ = run_both(torch, cheb, case, 0.1, 8)
     assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
@@ -258,16 +262,27 @@ def test_polaron_figure3_parameters_reduced(torch, cheb):
 
 @pytest.fixture
 def hol_spt_env():
+    """setter(spt, rank=None): sites per thread of the Holstein walk (None:
+    its default) and whether it ranks the phonon partners itself (True) or
+    reads the per-state partner tables (False); None: its size rule."""
     import os
-    saved = os.environ.get("CHEBTD_HOL_SPT")
+    saved = {k: os.environ.get(k) for k in ("CHEBTD_HOL_SPT", "CHEBTD_HOL_RANK")}
 
-    def setter(spt):
+    def setter(spt, rank=None):
         if spt is None:
             os.environ.pop("CHEBTD_HOL_SPT", None)
         else:
             os.environ["CHEBTD_HOL_SPT"] = str(spt)
+        if rank is None:
+            os.environ.pop("CHEBTD_HOL_RANK", None)
+        else:
+            os.environ["CHEBTD_HOL_RANK"] = "1" if rank else "0"
     yield setter
-    setter(saved)
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
 
 
 def _polaron_fig3(L, nph, barrier_site, periodic, state):
@@ -288,12 +303,16 @@ def _polaron_fig3(L, nph, barrier_site, periodic, state):
 # the grouping here runs that code at oracle size: group boundaries inside
 # the chain (left neighbour from the previous group), groups that do not
 # divide L, the ring's wrap from the last group to the first
-@pytest.mark.parametrize("spt", [1, 2, 3, 5, 7, 9, 12])
+@pytest.mark.parametrize("spt,rank", [(1, True), (2, True), (3, True), (5, True), (7, True), (9, True),
+                                      (12, True), (1, False), (5, False), (12, False)])
 @pytest.mark.parametrize("periodic,state", [(False, "packet"), (False, "dense"), (True, "dense")])
-def test_holstein_grouped_walk_matches_oracle(torch, cheb, hol_spt_env, spt, periodic, state):
+def test_holstein_grouped_walk_matches_oracle(torch, cheb, hol_spt_env, spt, rank, periodic, state):
+    # rank: the walk ranks the phonon partners itself (combinatorial number
+    # system, digit by digit as it walks the sites; a group starting past
+    # site 0 first takes the digits before it) or reads the partner tables
     L, nph = 12, 5
     p, g, Delta, H, psi0 = _polaron_fig3(L, nph, 8, periodic, state)
-    hol_spt_env(spt)
+    hol_spt_env(spt, rank)
     ctx = cheb.Context()
     ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, periodic)
     hol_spt_env(None)
@@ -313,28 +332,32 @@ def test_holstein_grouped_walk_matches_oracle(torch, cheb, hol_spt_env, spt, per
         np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
 
 
-def test_holstein_grouped_walk_by_size_matches_oracle(torch, cheb, hol_spt_env):
+def test_holstein_open_chain_16M_states_matches_oracle(torch, cheb, hol_spt_env):
     # 12 open sites with up to 11 phonons: 1,352,078 configurations (16.2M
-    # states), past 2^20, so the walk groups sites by its own choice (two
-    # groups of six) exactly as the Fig. 3 polaron run does
+    # states, past 2^20 like the Fig. 3 polaron), in the walk's default
+    # layout (every site in one thread) and grouped by five
     L, nph = 12, 11
-    hol_spt_env(None)
     p, g, Delta, H, psi0 = _polaron_fig3(L, nph, 8, False, "packet")
     assert O.holstein_nconf(L, nph) == 1_352_078
-    ctx = cheb.Context()
-    ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, False)
     emin, emax = H.gershgorin()
-    ctx.set_bounds(emin, emax)
     plan = O.Plan(emin, emax, p["dt"])
-    assert ctx.plan(p["dt"]) == plan.M
-    psi = dev(torch, psi0)
-    say(f"[gpu] Holstein L=12 nph=11 (16.2M states), grouped by size, M={plan.M}")
-    ctx.propagate(psi, 2)
-    torch.cuda.synchronize()
     ref = O.propagate(H, plan, psi0, 2)
-    assert_state_close(host(psi), ref)
-    for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
-        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+    ref_obs = O.holstein_obs(L, nph, ref)
+    for spt, rank in ((None, None), (5, True), (None, False)):
+        hol_spt_env(spt, rank)
+        ctx = cheb.Context()
+        ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, False)
+        hol_spt_env(None)
+        ctx.set_bounds(emin, emax)
+        assert ctx.plan(p["dt"]) == plan.M
+        psi = dev(torch, psi0)
+        say(f"[gpu] Holstein L=12 nph=11 (16.2M states), sites per thread {spt or L}, own ranks {rank}")
+        ctx.propagate(psi, 2)
+        torch.cuda.synchronize()
+        assert_state_close(host(psi), ref)
+        for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), ref_obs):
+            np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+        ctx.close()
 
 
 def test_holstein_matrix_free_matches_csr_path(torch, cheb):
