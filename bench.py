@@ -292,13 +292,14 @@ def hol_bytes(L, kname):
     """Algorithmic bytes per state and order of the matrix-free Holstein walk
     as it runs: v_k, v_{k-1} read and v_{k+1} written (48), acc read and
     written (32) on one order in three (the walk adds three orders' weights at
-    once), and, in the walk that reads them (k_iter_hol<false>, chosen where
-    the last-level cache holds them), the raise/lower tables (2 x int32), the
-    occupation (uint8) and the configuration total (uint8 per L states); the
-    walk that ranks the phonon partners itself (k_iter_hol<true>) reads no
-    table.  Second: the table walk updating acc every order, for comparison."""
+    once), and, in the walk that reads them (k_iter_hol<false, ...>, chosen
+    where the last-level cache holds them), the raise/lower tables (2 x
+    int32), the occupation (uint8) and the configuration total (uint8 per L
+    states); the walk that ranks the phonon partners itself
+    (k_iter_hol<true, ...>) reads no table.  Second: the table walk updating
+    acc every order, for comparison."""
     tables = 4 + 4 + 1 + 1.0 / L
-    lazy = 48 + 32.0 / 3.0 + (0.0 if kname.endswith("<true>") else tables)
+    lazy = 48 + 32.0 / 3.0 + (0.0 if kname.startswith("k_iter_hol<true") else tables)
     eager = 48 + tables + 32
     return lazy, eager
 

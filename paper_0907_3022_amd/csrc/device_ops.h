@@ -220,13 +220,8 @@ struct CsrRow {
     }
 };
 
-// Matrix-free Holstein rows (eq. (ghm)); state i = site * nconf + r.
+// Matrix-free Holstein states (eq. (ghm)): state i = site * nconf + r.
 struct HolRow {
-    __device__ static __forceinline__ int64_t row(const OpHol &op)
-    {
-        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        return i < op.n ? i : -1;
-    }
     // state i = site * nconf + r, for i = blockIdx.x * blockDim.x + threadIdx.x:
     // one division per wavefront (the block's first state), then a step or
     // two for threads past a site boundary (n < 2^31: 32-bit arithmetic)
@@ -241,52 +236,6 @@ struct HolRow {
         }
         site = s;
         r = rr;
-    }
-    __device__ static __forceinline__ double2 apply2(const OpHol &op, int64_t i, const double2 *v, double2 vi)
-    {
-        uint32_t site, r;
-        split(op, i, site, r);
-        const uint32_t L = (uint32_t)op.L, C = op.nconf;
-        const double diag = op.Delta[site] + op.w0 * (double)op.tot[r];
-        // electron hops to the neighbouring sites: same configuration, the
-        // neighbouring site's block of states
-        double hx = 0.0, hy = 0.0;
-        const bool has_l = op.periodic || site > 0, has_r = op.periodic || site + 1 < L;
-        const uint32_t sl = site == 0 ? L - 1 : site - 1, sr = site + 1 == L ? 0 : site + 1;
-        if (has_l) {
-            const double2 u = v[sl * C + r];
-            hx += u.x;
-            hy += u.y;
-        }
-        if (has_r) {
-            const double2 u = v[sr * C + r];
-            hx += u.x;
-            hy += u.y;
-        }
-        // phonon creation/annihilation at the electron's site: the partner
-        // configurations in the same site's block
-        const int32_t ru = op.up[i], rd = op.dn[i];
-        const uint32_t ni = op.occ[i];
-        const uint32_t base = site * C;
-        double px = 0.0, py = 0.0;
-        if (ru >= 0) {
-            const double2 u = v[base + (uint32_t)ru];
-            const double w = op.sq[ni + 1];
-            px = fma(w, u.x, px);
-            py = fma(w, u.y, py);
-        }
-        if (rd >= 0) {
-            const double2 u = v[base + (uint32_t)rd];
-            const double w = op.sq[ni];
-            px = fma(w, u.x, px);
-            py = fma(w, u.y, py);
-        }
-        const double gw = op.gw0[site];
-        // (H v)_i = diag v_i - t (hops) - g_i w0 (phonon terms); return (2/a)(H - b) v
-        const double d = diag - op.b;
-        const double hvx = fma(d, vi.x, fma(-op.t, hx, -gw * px));
-        const double hvy = fma(d, vi.y, fma(-op.t, hy, -gw * py));
-        return make_double2(op.s2 * hvx, op.s2 * hvy);
     }
 };
 

@@ -189,6 +189,8 @@ constexpr int kBlock = 256;
 // reads the per-state partner tables instead)
 constexpr int kHolBinomBytes = 16384;
 int64_t grid_blocks(const Ctx &c);
+// blocks (one partial pair each) of the single-order step head
+int64_t head_blocks(const Ctx &c);
 
 hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *v1, double2 *acc,
                        double2 g0, double2 g1, double2 *ckpt, double *partials);

@@ -79,20 +79,6 @@ __global__ __launch_bounds__(kBlock) void k_head_honey(OpHoney op, const double2
     head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_head_hol(OpHol op, const double2 *__restrict__ v0,
-                                                     double2 *__restrict__ v1,
-                                                     double2 *__restrict__ acc, double2 g0,
-                                                     double2 g1, double2 *ckpt, double *partials)
-{
-    const int64_t i = HolRow::row(op);
-    double2 vi = make_double2(0.0, 0.0), h2 = vi;
-    if (i >= 0) {
-        vi = v0[i];
-        h2 = HolRow::apply2(op, i, v0, vi);
-    }
-    head_body(i, i >= 0, vi, h2, v1, acc, g0, g1, ckpt, partials);
-}
-
 __global__ __launch_bounds__(kBlock) void k_head_csr(OpCsr op, const double2 *__restrict__ v0,
                                                      double2 *__restrict__ v1,
                                                      double2 *__restrict__ acc, double2 g0,
@@ -169,31 +155,23 @@ __global__ __launch_bounds__(kBlock) void k_iter_honey(OpHoney op, const double2
 // rank(n - e_s) = r - C(T+L-2, L-1) + sum_{j<s} (d_j - t_j) + y_s - t_s at
 // l_j - 1.  Walking the sites in order, the thread takes the digits n_s
 // from r as it goes (unranking) and carries the two prefix sums.
-template <bool RANK>
-__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int remap, const int32_t *binom,
-                                                     int brows, const double2 *__restrict__ vk, double2 *vprev,
-                                                     double2 *__restrict__ acc, int nacc, double2 ga, double2 gb,
-                                                     double2 gc)
+//
+// hol_walk is one thread's walk: configuration r, sites [s0, s1).
+template <bool RANK, bool HEAD>
+__device__ __forceinline__ void hol_walk(const OpHol &op, int spt, int brows, const int32_t *sbin, uint32_t lb,
+                                         uint32_t C, const double2 *__restrict__ vk, double2 *vprev,
+                                         double2 *__restrict__ acc, int nacc, double2 ga, double2 gb, double2 gc,
+                                         double2 *ckpt, double &nrm, double &en)
 {
-    extern __shared__ int32_t sbin[];
     const int32_t L = op.L, K = L + 1;  // binomial table: brows x (L + 1)
-    if constexpr (RANK) {
-        for (int q = threadIdx.x; q < brows * K; q += blockDim.x) sbin[q] = binom[q];
-        __syncthreads();
-    }
     // C(a, m) from the table; zero outside it
     auto cb = [&](int32_t a, int32_t m) -> int32_t {
         return (a < 0 || a >= brows || m < 0 || m > L) ? 0 : sbin[a * K + m];
     };
-    const uint32_t C = op.nconf, Lu = (uint32_t)L;
-    const uint32_t ngrp = (Lu + (uint32_t)spt - 1) / (uint32_t)spt;
-    // remap: each XCD takes one contiguous range of configurations, so the
-    // phonon partners that neighbouring wavefronts share meet in one L2
-    const uint32_t lb = (uint32_t)logical_block(remap);
-    const uint64_t t = (uint64_t)lb * blockDim.x + threadIdx.x;
-    if (t >= (uint64_t)C * ngrp) return;
+    const uint32_t Lu = (uint32_t)L;
     // (grp, r) from t: one division per wavefront, then at most a few steps
     const uint32_t b0 = lb * blockDim.x;
+    const uint64_t t = (uint64_t)b0 + threadIdx.x;
     uint32_t grp = __builtin_amdgcn_readfirstlane(b0 / C);
     uint32_t r = (uint32_t)t - grp * C;
     while (r >= C) {
@@ -302,17 +280,64 @@ __global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int rema
         const double hx = left_v.x + right.x, hy = left_v.y + right.y;
         const double hvx = fma(d, cur.x, fma(-op.t, hx, -gw * px));
         const double hvy = fma(d, cur.y, fma(-op.t, hy, -gw * py));
-        const double2 p = vprev[i];
-        const double2 nv = csub(make_double2(op.s2 * hvx, op.s2 * hvy), p);
-        vprev[i] = nv;
-        if (nacc > 0) {  // uniform across the launch
-            double2 a = acc[i];
-            if (nacc >= 3) a = cfma(ga, p, a);
-            if (nacc >= 2) a = cfma(gb, cur, a);
-            acc[i] = cfma(gc, nv, a);
+        if constexpr (HEAD) {
+            const double2 h = make_double2(0.5 * (op.s2 * hvx), 0.5 * (op.s2 * hvy));
+            if (vprev) {  // null: reduction only (norm and energy of v0)
+                vprev[i] = h;
+                acc[i] = cfma(gb, h, cfma(ga, cur, zero));
+            }
+            if (ckpt) ckpt[i] = cur;
+            nrm += cur.x * cur.x + cur.y * cur.y;
+            en += cur.x * h.x + cur.y * h.y;
+        } else {
+            const double2 p = vprev[i];
+            const double2 nv = csub(make_double2(op.s2 * hvx, op.s2 * hvy), p);
+            vprev[i] = nv;
+            if (nacc > 0) {  // uniform across the launch
+                double2 a = acc[i];
+                if (nacc >= 3) a = cfma(ga, p, a);
+                if (nacc >= 2) a = cfma(gb, cur, a);
+                acc[i] = cfma(gc, nv, a);
+            }
         }
         left_v = cur;
         cur = right;
+    }
+}
+
+// HEAD: the same walk as the step head, v1 = H~ v0 (into vprev, which is not
+// read; null: reduction only), acc = ga v0 + gb v1, ckpt = v0 (if given),
+// and per block the partial sums <v0|v0>, <v0|H~ v0> into partials (one
+// pair per block: the sum over a block's configurations and their sites).
+template <bool RANK, bool HEAD>
+__global__ __launch_bounds__(kBlock) void k_iter_hol(OpHol op, int spt, int remap, const int32_t *binom,
+                                                     int brows, const double2 *__restrict__ vk, double2 *vprev,
+                                                     double2 *__restrict__ acc, int nacc, double2 ga, double2 gb,
+                                                     double2 gc, double2 *ckpt, double *partials)
+{
+    extern __shared__ int32_t sbin[];
+    __shared__ double red[2 * (kBlock / 64)];
+    const int32_t L = op.L, K = L + 1;  // binomial table: brows x (L + 1)
+    if constexpr (RANK) {
+        for (int q = threadIdx.x; q < brows * K; q += blockDim.x) sbin[q] = binom[q];
+        __syncthreads();
+    }
+    const uint32_t C = op.nconf, Lu = (uint32_t)L;
+    const uint32_t ngrp = (Lu + (uint32_t)spt - 1) / (uint32_t)spt;
+    // remap: each XCD takes one contiguous range of configurations, so the
+    // phonon partners that neighbouring wavefronts share meet in one L2
+    const uint32_t lb = (uint32_t)logical_block(remap);
+    const uint64_t t = (uint64_t)lb * blockDim.x + threadIdx.x;
+    double nrm = 0.0, en = 0.0;  // HEAD: this thread's share of <v0|v0>, <v0|H~ v0>
+    if (t < (uint64_t)C * ngrp) {
+        hol_walk<RANK, HEAD>(op, spt, brows, sbin, lb, C, vk, vprev, acc, nacc, ga, gb, gc, ckpt, nrm, en);
+    }
+    if constexpr (HEAD) {
+        block_sum2(nrm, en, red);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = nrm;
+            partials[2 * blockIdx.x + 1] = en;
+        }
     }
 }
 
@@ -659,9 +684,58 @@ int64_t grid_blocks(const Ctx &c)
     return (c.n + kBlock - 1) / kBlock;
 }
 
+// Electron sites per thread of the Holstein walk (measured on MI355X with the
+// XCD-contiguous order and acc every third order): all of them (L = 10 ring:
+// 23.2 us per order against 24.4 for groups of five; L = 18 polaron: 10.60 ms
+// against 10.82 for groups of nine and 10.88 for six); hol_spt > 0 groups them
+static int hol_sites_per_thread(const Ctx &c)
+{
+    return c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, c.hol_L) : (int)c.hol_L;
+}
+
+static int64_t hol_walk_blocks(const Ctx &c)
+{
+    const int64_t L = c.hol_L, spt = hol_sites_per_thread(c);
+    return (c.hol_nconf * ((L + spt - 1) / spt) + kBlock - 1) / kBlock;
+}
+
+// The Holstein walk, as an order of the recursion or (head) as the step head.
+static hipError_t launch_hol_walk(const Ctx &c, hipStream_t s, bool head, const double2 *vk, double2 *vprev,
+                                  double2 *acc, int nacc, double2 ga, double2 gb, double2 gc, double2 *ckpt,
+                                  double *partials)
+{
+    const int spt = hol_sites_per_thread(c);
+    const dim3 grid((unsigned)hol_walk_blocks(c)), block(kBlock);
+    if (c.hol_brows > 0) {
+        const size_t lds = (size_t)c.hol_brows * (size_t)(c.hol_L + 1) * sizeof(int32_t);
+        const int32_t *bin = static_cast<const int32_t *>(c.hol_binom.p);
+        if (head)
+            hipLaunchKernelGGL((k_iter_hol<true, true>), grid, block, lds, s, make_hol(c), spt, c.hol_remap, bin,
+                               c.hol_brows, vk, vprev, acc, 0, ga, gb, gc, ckpt, partials);
+        else
+            hipLaunchKernelGGL((k_iter_hol<true, false>), grid, block, lds, s, make_hol(c), spt, c.hol_remap, bin,
+                               c.hol_brows, vk, vprev, acc, nacc, ga, gb, gc, nullptr, nullptr);
+    } else {
+        if (head)
+            hipLaunchKernelGGL((k_iter_hol<false, true>), grid, block, 0, s, make_hol(c), spt, c.hol_remap, nullptr,
+                               0, vk, vprev, acc, 0, ga, gb, gc, ckpt, partials);
+        else
+            hipLaunchKernelGGL((k_iter_hol<false, false>), grid, block, 0, s, make_hol(c), spt, c.hol_remap,
+                               nullptr, 0, vk, vprev, acc, nacc, ga, gb, gc, nullptr, nullptr);
+    }
+    return hipGetLastError();
+}
+
+int64_t head_blocks(const Ctx &c)
+{
+    return c.kind == HKind::Holstein ? hol_walk_blocks(c) : grid_blocks(c);
+}
+
 hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *v1, double2 *acc,
                        double2 g0, double2 g1, double2 *ckpt, double *partials)
 {
+    if (c.kind == HKind::Holstein)
+        return launch_hol_walk(c, s, true, v0, v1, acc, 0, g0, g1, make_double2(0.0, 0.0), ckpt, partials);
     const dim3 grid((unsigned)grid_blocks(c)), block(kBlock);
     switch (c.kind) {
     case HKind::Chain:
@@ -678,10 +752,6 @@ hipError_t launch_head(const Ctx &c, hipStream_t s, const double2 *v0, double2 *
         break;
     case HKind::Csr:
         hipLaunchKernelGGL(k_head_csr, grid, block, 0, s, make_csr(c), v0, v1, acc, g0, g1, ckpt,
-                           partials);
-        break;
-    case HKind::Holstein:
-        hipLaunchKernelGGL(k_head_hol, grid, block, 0, s, make_hol(c), v0, v1, acc, g0, g1, ckpt,
                            partials);
         break;
     default:
@@ -724,24 +794,7 @@ hipError_t launch_iter_lazy(const Ctx &c, hipStream_t s, const double2 *vk, doub
                            nacc, ga, gb, gc);
         return hipGetLastError();
     }
-    // sites per thread (measured on MI355X with the XCD-contiguous order and
-    // acc every third order): all of them (L = 10 ring: 23.2 us per order
-    // against 24.4 for groups of five; L = 18 polaron: 10.60 ms against 10.82
-    // for groups of nine and 10.88 for six); hol_spt > 0 groups them
-    const int64_t C = c.hol_nconf, L = c.hol_L;
-    const int spt = c.hol_spt > 0 ? (int)std::min<int64_t>(c.hol_spt, L) : (int)L;
-    const int64_t ngrp = (L + spt - 1) / spt;
-    const int64_t nb = (C * ngrp + kBlock - 1) / kBlock;
-    if (c.hol_brows > 0) {
-        const size_t lds = (size_t)c.hol_brows * (size_t)(L + 1) * sizeof(int32_t);
-        hipLaunchKernelGGL(k_iter_hol<true>, dim3((unsigned)nb), dim3(kBlock), lds, s, make_hol(c), spt,
-                           c.hol_remap, static_cast<const int32_t *>(c.hol_binom.p), c.hol_brows, vk, vprev, acc,
-                           nacc, ga, gb, gc);
-    } else {
-        hipLaunchKernelGGL(k_iter_hol<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, make_hol(c), spt,
-                           c.hol_remap, nullptr, 0, vk, vprev, acc, nacc, ga, gb, gc);
-    }
-    return hipGetLastError();
+    return launch_hol_walk(c, s, false, vk, vprev, acc, nacc, ga, gb, gc, nullptr, nullptr);
 }
 
 hipError_t launch_finalize_ne(hipStream_t s, const double *partials, int nparts, double a, double b,

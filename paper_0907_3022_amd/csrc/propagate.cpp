@@ -67,7 +67,7 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
     const int h = P[0];
     double2 g[kMaxDepth + 1];
     hipError_t e;
-    int64_t head_blocks;
+    int64_t nhead;  // blocks of the head pass (one partial pair each)
     // the last multi-order pass writes its two orders, v_{M-1} and v_M, into
     // ends; without ends nothing reads them (the next step starts from acc),
     // so a deep last pass writes acc alone (32 of its 104 B per site fewer)
@@ -77,16 +77,16 @@ hipError_t enqueue_step_pairs(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt,
     if (h > 2) {
         for (int j = 0; j <= h; ++j) g[j] = weight(c, j);
         e = launch_deep(*c, s, h, c->deep_rows[h], true, nullptr, cur, h1, h2, nxt, g, ckpt, partials, nullptr);
-        head_blocks = deep_grid_blocks(*c, c->deep_rows[h], h);
+        nhead = deep_grid_blocks(*c, c->deep_rows[h], h);
     } else {
         e = launch_pair(*c, s, c->pair_rows, true, nullptr, cur, h1, h2, nxt, weight(c, 0), weight(c, 1),
                         weight(c, 2), ckpt, partials);
-        head_blocks = pair_grid_blocks(*c, c->pair_rows);
+        nhead = pair_grid_blocks(*c, c->pair_rows);
     }
     if (e != hipSuccess) return e;
     // the step's norm and energy: finished by block 0 of the next multi-order
     // pass when there is one (no extra launch), else by their own kernel
-    const NeFinal fin{partials, (int)head_blocks, c->a, c->b, norm_out, energy_out,
+    const NeFinal fin{partials, (int)nhead, c->a, c->b, norm_out, energy_out,
                       static_cast<int64_t *>(c->counter.p)};
     const bool want_ne = norm_out || energy_out;
     const bool has_next = P.size() > 1 && P[1] >= 2;
@@ -139,7 +139,7 @@ hipError_t enqueue_step(Ctx *c, hipStream_t s, double2 *cur, double2 *nxt, doubl
     hipError_t e = launch_head(*c, s, cur, A, nxt, weight(c, 0), weight(c, 1), ckpt, partials);
     if (e != hipSuccess) return e;
     if (norm_out || energy_out) {
-        e = launch_finalize_ne(s, partials, (int)grid_blocks(*c), c->a, c->b, norm_out, energy_out,
+        e = launch_finalize_ne(s, partials, (int)head_blocks(*c), c->a, c->b, norm_out, energy_out,
                                static_cast<int64_t *>(c->counter.p), nullptr);
         if (e != hipSuccess) return e;
     }
@@ -395,7 +395,7 @@ int chebtd_norm_energy(chebtd_ctx *ctx, const double *psi_dev, double *out2_dev)
     hipError_t e = launch_head(*c, c->stream, reinterpret_cast<const double2 *>(psi_dev), nullptr,
                                nullptr, make_double2(0, 0), make_double2(0, 0), nullptr, partials);
     if (e == hipSuccess)
-        e = launch_finalize_ne(c->stream, partials, (int)grid_blocks(*c), c->a, c->b, nullptr, nullptr,
+        e = launch_finalize_ne(c->stream, partials, (int)head_blocks(*c), c->a, c->b, nullptr, nullptr,
                                nullptr, out2_dev);
     return e == hipSuccess ? CHEBTD_OK : hip_fail(c, e, "chebtd_norm_energy");
 }
@@ -426,7 +426,7 @@ int chebtd_time_recursion_kernel(chebtd_ctx *ctx, int launches, unsigned flags, 
     // the multi-order kernel the step spends most of its passes in
     const int dp = pairs ? dominant_pass(*c) : 2;
     static const char *names[] = {"k_iter_chain", "k_iter_honey<0>", "k_iter_honey<1>", "k_iter_csr",
-                                  "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol<true>", "k_iter_hol<false>"};
+                                  "k_pair<0,false>", "k_pair<1,false>", "k_iter_hol<true, false>", "k_iter_hol<false, false>"};
     // [edge][streaming stores][orders per pass]
     static const char *deep_names[2][2][kMaxDepth + 1] = {
         {{"", "", "", "k_deep<0,3,false,false>", "k_deep<0,4,false,false>", "k_deep<0,5,false,false>",
