@@ -245,7 +245,7 @@ int chebtd_set_check_tol(chebtd_ctx *ctx, double rel_tol);
  * psi_dev (complex128[n]) and mask_dev (uint8[n], 0 or 1), sum into
  * out_dev[0] (float64), enqueued on hip_stream (a hipStream_t of the current
  * HIP device, NULL = null stream).  The per-block partial sums live in a
- * fixed device array of the library, one per GPU, of 1 MB, held until the
+ * fixed device array of the library, one per GPU, of 33 KB, held until the
  * process ends; it allocates nothing and returns CHEBTD_E_ARG for n outside
  * [1, CHEBTD_NOALLOC_MAX_SITES].  The same kernels as chebtd_region_sum:
  * bit-identical results.  Calls that overlap on one GPU (other streams,

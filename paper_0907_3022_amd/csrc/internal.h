@@ -189,6 +189,14 @@ constexpr int kBlock = 256;
 // reads the per-state partner tables instead)
 constexpr int kHolBinomBytes = 16384;
 int64_t grid_blocks(const Ctx &c);
+// blocks of the norm and region sums (grid-stride: one partial pair per
+// block, at most kReduceBlocks of them whatever n is)
+constexpr int64_t kReduceBlocks = 2048;
+inline int64_t reduce_blocks(int64_t n)
+{
+    const int64_t nb = (n + kBlock - 1) / kBlock;
+    return nb < kReduceBlocks ? (nb > 0 ? nb : 1) : kReduceBlocks;
+}
 // blocks (one partial pair each) of the single-order step head
 int64_t head_blocks(const Ctx &c);
 

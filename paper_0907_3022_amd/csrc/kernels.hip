@@ -379,15 +379,18 @@ __global__ __launch_bounds__(256) void k_finalize_ne(const double *__restrict__ 
 
 __global__ void k_reset_counter(int64_t *counter) { counter[0] = 0; }
 
+// Norm and region sums: each thread sums the sites i = t, t + stride, ... in
+// order (stride = the grid's thread count, at most kReduceBlocks blocks), so
+// the final one-block sum reads few partials whatever n is; fixed order.
 __global__ __launch_bounds__(kBlock) void k_norm(const double2 *__restrict__ psi, int64_t n,
                                                  double *partials)
 {
     __shared__ double red[2 * (kBlock / 64)];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     double s = 0.0, z = 0.0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double2 v = psi[i];
-        s = v.x * v.x + v.y * v.y;
+        s += v.x * v.x + v.y * v.y;
     }
     block_sum2(s, z, red);
     if (threadIdx.x == 0) {
@@ -401,11 +404,13 @@ __global__ __launch_bounds__(kBlock) void k_region(const double2 *__restrict__ p
                                                    double *partials)
 {
     __shared__ double red[2 * (kBlock / 64)];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     double s = 0.0, z = 0.0;
-    if (i < n && mask[i]) {
-        const double2 v = psi[i];
-        s = v.x * v.x + v.y * v.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (mask[i]) {
+            const double2 v = psi[i];
+            s += v.x * v.x + v.y * v.y;
+        }
     }
     block_sum2(s, z, red);
     if (threadIdx.x == 0) {
@@ -814,7 +819,7 @@ hipError_t launch_reset_counter(hipStream_t s, int64_t *counter)
 
 hipError_t launch_norm(const Ctx &c, hipStream_t s, const double2 *psi, double *partials)
 {
-    const int64_t nb = (c.n + kBlock - 1) / kBlock;
+    const int64_t nb = reduce_blocks(c.n);
     hipLaunchKernelGGL(k_norm, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, c.n, partials);
     return hipGetLastError();
 }
@@ -849,7 +854,7 @@ hipError_t launch_density(hipStream_t s, const double2 *psi, double *rho, int64_
 hipError_t launch_region(hipStream_t s, const double2 *psi, const uint8_t *mask, int64_t n,
                          double *partials, double *out)
 {
-    const int64_t nb = (n + kBlock - 1) / kBlock;
+    const int64_t nb = reduce_blocks(n);
     hipLaunchKernelGGL(k_region, dim3((unsigned)nb), dim3(kBlock), 0, s, psi, mask, n, partials);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, (int)nb, out);
     return hipGetLastError();

@@ -22,7 +22,7 @@ namespace {
 
 // Result pair first, then two doubles per block of the region kernel.
 constexpr int64_t kResultDoubles = 32;  // 256 B, keeps the partials aligned
-constexpr int64_t kMaxBlocks = (CHEBTD_NOALLOC_MAX_SITES + kBlock - 1) / kBlock;
+constexpr int64_t kMaxBlocks = kReduceBlocks;  // reduce_blocks(n) <= kReduceBlocks for every n
 constexpr int64_t kScratchDoubles = kResultDoubles + 2 * kMaxBlocks;
 
 // One copy per GPU, held until the process ends.  Host code never passes

@@ -176,7 +176,7 @@ hipError_t enqueue_norm(Ctx *c, hipStream_t s, const double2 *psi, int slot)
     double *partials = static_cast<double *>(c->partials.p);
     hipError_t e = launch_norm(*c, s, psi, partials);
     if (e != hipSuccess) return e;
-    return launch_sum_partials(s, partials, (int)((c->n + kBlock - 1) / kBlock), 2,
+    return launch_sum_partials(s, partials, (int)reduce_blocks(c->n), 2,
                                static_cast<double *>(c->results.p) + slot);
 }
 
