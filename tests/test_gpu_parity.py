@@ -220,7 +220,8 @@ def test_table2_ribbon_single_site(torch, cheb, dt):
 
 
 @pytest.mark.parametrize("L,nph,g2,periodic", [(4, 3, 0.5, True), (6, 4, 2.0, True), (5, 5, 0.5, False),
-                                               (3, 6, 2.0, True), (1, 7, 0.5, False), (2, 5, 0.5, False)])
+                                               (3, 6, 2.0, True), (1, 7, 0.5, False), (2, 5, 0.5, False),
+                                               (5, 0, 2.0, True)])
 @pytest.mark.parametrize("state", ["vacuum", "dense"])
 @pytest.mark.parametrize("rank", [None, True])
 def test_holstein_parity_and_observables(torch, cheb, hol_spt_env, L, nph, g2, periodic, state, rank):
