@@ -299,11 +299,11 @@ def _polaron_fig3(L, nph, barrier_site, periodic, state):
     return p, g, Delta, H, psi0
 
 
-# the walk groups at most 9 electron sites per thread past 2^20 phonon
-# configurations (the Sect. 3.3 / Fig. 3 polaron takes that branch); forcing
-# the grouping here runs that code at oracle size: group boundaries inside
-# the chain (left neighbour from the previous group), groups that do not
-# divide L, the ring's wrap from the last group to the first
+# the walk takes every electron site of a configuration in one thread by
+# default; CHEBTD_HOL_SPT groups them instead, which exercises group
+# boundaries inside the chain (left neighbour from the previous group),
+# groups that do not divide L and the ring's wrap from the last group to the
+# first, for both walks (partner ranks formed in the walk or read)
 @pytest.mark.parametrize("spt,rank", [(1, True), (2, True), (3, True), (5, True), (7, True), (9, True),
                                       (12, True), (1, False), (5, False), (12, False)])
 @pytest.mark.parametrize("periodic,state", [(False, "packet"), (False, "dense"), (True, "dense")])
@@ -335,8 +335,9 @@ def test_holstein_grouped_walk_matches_oracle(torch, cheb, hol_spt_env, spt, ran
 
 def test_holstein_open_chain_16M_states_matches_oracle(torch, cheb, hol_spt_env):
     # 12 open sites with up to 11 phonons: 1,352,078 configurations (16.2M
-    # states, past 2^20 like the Fig. 3 polaron), in the walk's default
-    # layout (every site in one thread) and grouped by five
+    # states, past 8M: the defaults of the Fig. 3 polaron's size, every site
+    # in one thread and the partner ranks formed in the walk), then grouped
+    # by five, and reading the partner tables
     L, nph = 12, 11
     p, g, Delta, H, psi0 = _polaron_fig3(L, nph, 8, False, "packet")
     assert O.holstein_nconf(L, nph) == 1_352_078
