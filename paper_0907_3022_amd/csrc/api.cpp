@@ -428,21 +428,22 @@ int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0, cons
     c->hol_t = t;
     c->hol_w0 = w0;
     c->hol_periodic = periodic ? 1 : 0;
-    // binomials for the walk's own partner ranks (C(a, m) < 2^31 here since
-    // the largest, C(nph + L, L - 1), is below L * nconf).  The walk ranks the
-    // partners itself where the tables would stream from HBM (measured on
-    // MI355X: the L = 18 polaron, 6.2e8 states, 10.6 -> 9.4 ms per order),
-    // and reads the tables where the last-level cache holds them (the L = 10
-    // ring, 1.85M states: 23.2 us against 30.8 us ranking); CHEBTD_HOL_RANK=1
-    // or 0 forces either
+    // binomials C(a, m), a <= nph + L + 1, m <= L, for the walk's own partner
+    // ranks.  The entries it reads are at most C(nph + L, L) = nconf and
+    // C(nph + L, L - 1) = nconf L / (nph + 1), both below the dimension
+    // L nconf < 2^31; the last row may exceed 2^31 and is stored saturated.
+    // The walk ranks the partners itself where the tables would stream from
+    // HBM (measured on MI355X: the L = 18 polaron, 6.2e8 states, 10.6 -> 9.4
+    // ms per order), and reads the tables where the last-level cache holds
+    // them (the L = 10 ring, 1.85M states: 23.2 us against 30.8 us ranking);
+    // CHEBTD_HOL_RANK=1 or 0 forces either
     c->hol_brows = 0;
     {
         const int brows = nph + L + 2, bcols = L + 1;
         const char *renv = std::getenv("CHEBTD_HOL_RANK");
         const bool want = renv ? std::atoi(renv) != 0 : h.n > ((int64_t)8 << 20);
         if (want && (size_t)brows * bcols * sizeof(int32_t) <= (size_t)kHolBinomBytes) {
-            // Pascal's rule in 64 bits, stored saturated: the walk reads no
-            // entry past C(nph + L, L) = nconf
+            // Pascal's rule in 64 bits, stored saturated at INT32_MAX
             std::vector<int64_t> c64((size_t)brows * bcols, 0);
             std::vector<int32_t> cb((size_t)brows * bcols, 0);
             for (int a = 0; a < brows; ++a) {
