@@ -3,9 +3,11 @@
 // The hot loop is the fused recursion step of Sect. 2.2 (arXiv:0907.3022):
 //   v_{k+1} = 2 H~ v_k - v_{k-1}   (written over v_{k-1}),
 //   acc    += gamma_{k+1} v_{k+1},
-// one row per thread, complex128 throughout.  Per row it moves 88 bytes for
-// the stencils (v_k, v_{k-1}, v_{k+1}, acc read and write, on-site term) and
-// the neighbour values of v_k come from the caches.  Reductions (norm,
+// complex128 throughout.  The stencil and CSR kernels take one row per
+// thread; per row a stencil moves 88 bytes (v_k, v_{k-1}, v_{k+1}, acc read
+// and write, on-site term) and the neighbour values of v_k come from the
+// caches.  The matrix-free Holstein walk takes one phonon configuration per
+// thread across its electron sites (eq. (ghm)).  Reductions (norm,
 // energy, region sums, bounds) are deterministic: a fixed butterfly inside
 // each wavefront, fixed-order sums across wavefronts and blocks, no
 // floating-point atomics.
