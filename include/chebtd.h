@@ -130,7 +130,11 @@ int chebtd_h_csr(chebtd_ctx *ctx, int64_t n, int64_t nnz, const int64_t *rowptr_
  * scheme of Sect. 3.3): the context builds on the host, and owns on the
  * device, per-state tables of the raised and lowered phonon configuration
  * and the site occupation (9 B per state) instead of the matrix; these also
- * serve chebtd_holstein_obs.  L * C(L+nph, nph) must stay below 2^31. */
+ * serve chebtd_holstein_obs.  Past 8M states the recursion forms the raised
+ * and lowered configurations' ranks itself from a small table of binomials
+ * and reads none of the per-state tables (environment CHEBTD_HOL_RANK=1 or
+ * 0, read here, forces either way).  L * C(L+nph, nph) must stay below
+ * 2^31. */
 int chebtd_h_holstein(chebtd_ctx *ctx, int L, int nph, double t, double w0,
                       const double *g_host, const double *Delta_host, int periodic);
 
