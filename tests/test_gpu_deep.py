@@ -276,3 +276,57 @@ def test_deep_64M_sites_sampled(torch, cheb, depth_env, edge):
     assert plan.M == M
     ref = ribbon_sites(w, l, edge, eps, psi0, plan, 2, sites)
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("edge", ["zigzag", "armchair"])
+def test_deep_at_the_offset_limit_sampled(torch, cheb, depth_env, edge):
+    # the largest ribbon the deep walk's 32-bit buffer offsets allow:
+    # (W + 14) L 16 B = 2^31 exactly at 2034 x 65536 (133M sites), where the
+    # rows past the lattice that the border walks address reach the top of
+    # the offset range; two steps from a dense state in the passes the plan
+    # picks, sampled sites (the last rows among them) against the oracle on
+    # windows around each. One row more and the plan keeps to two-order passes.
+    w, l = 2034, 65536
+    assert (w + 14) * l * 16 == 1 << 31
+    depth_env(None)
+    eps = W.anderson_disorder(w, l, 0.5, 7)
+    psi0 = W.random_state(w * l, 707)
+    ctx = cheb.Context()
+    eps_d = torch.from_numpy(eps).cuda()
+    ctx.honeycomb(w, l, eps_d, edge=edge)
+    lo, hi = ctx.gershgorin()
+    ctx.set_bounds(lo, hi, 0.01)
+    M = ctx.plan(1.0)
+    passes = ctx.plan_passes()
+    assert max(passes) >= 3 and sum(passes) == M
+    psi = torch.from_numpy(psi0).cuda()
+    nrm = torch.zeros(2, dtype=torch.float64, device="cuda")
+    say(f"[gpu] 2034x65536 (offset limit) {edge} dense, passes {passes}")
+    ctx.propagate(psi, 2, nrm, None, 0)
+    torch.cuda.synchronize()
+    n2 = host(nrm)
+    assert abs(n2[0] - 1.0) < 1e-12 and abs(n2[1] - 1.0) < 1e-12
+    sites = set(ribbon_sample_sites(w, l, 32, 23))
+    u = W.uniform01(29, 12)
+    for k in range(6):  # the last six rows, where the offsets are largest
+        sites.add((w - 1 - k, int(u[2 * k] * l)))
+        sites.add((w - 1 - k, l - 1 - int(u[2 * k + 1] * 64)))
+    sites = sorted(sites)
+    idx = np.array([y * l + x for y, x in sites])
+    got = host(psi)[idx]
+    del psi
+    ctx.close()
+    plan = O.Plan(lo, hi, 1.0)
+    assert plan.M == M
+    ref = ribbon_sites(w, l, edge, eps, psi0, plan, 2, sites)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    # one row more: past the limit the plan keeps to two-order passes
+    del eps_d
+    torch.cuda.empty_cache()
+    eps1 = torch.zeros((w + 1) * l, dtype=torch.float64, device="cuda")
+    ctx = cheb.Context()
+    ctx.honeycomb(w + 1, l, eps1, edge=edge)
+    ctx.set_bounds(-3.0, 3.0, 0.01)
+    assert ctx.plan(1.0) == 20
+    assert set(ctx.plan_passes()) <= {1, 2}
+    ctx.close()
