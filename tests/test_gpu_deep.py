@@ -8,7 +8,7 @@ import pytest
 import oracle as O
 import workloads as W
 from test_gpu_parity import (assert_state_close, chain_case, dev, gpu_context, honey_case, host,
-                             rel_l2, say)
+                             rel_l2, run_both, say)
 from windows import chain_sites, ribbon_sample_sites, ribbon_sites
 
 pytestmark = pytest.mark.gpu
@@ -81,6 +81,22 @@ def test_deep_ribbon_matches_oracle(torch, cheb, depth_env, depth, shape, M, sta
     say(f"[gpu] deep D={depth} ribbon {w}x{l} {edge} M={M} {state}")
     _, psi, nrm, en, plan = run(torch, cheb, case, 1.0, 3, M=M)
     ref, rn, re = O.propagate(case["H"], plan, case["psi0"], 3, want_obs=True)
+    assert_state_close(psi, ref)
+    np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    np.testing.assert_allclose(en, re, rtol=1e-10, atol=1e-12)
+
+
+# degenerate ribbons: one site, one row or one column, a 2 x 2 cell, fewer
+# columns or rows than any strip's or chunk's halo, at every pass depth
+@pytest.mark.parametrize("depth", [None, 2, 3, 6])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (2, 1), (5, 1), (2, 2), (64, 3), (3, 64)])
+@pytest.mark.parametrize("edge", ["zigzag", "armchair"])
+def test_degenerate_ribbons_match_oracle(torch, cheb, depth_env, depth, shape, edge):
+    w, l = shape
+    depth_env(depth)
+    case = honey_case(w, l, edge, state="dense")
+    say(f"[gpu] degenerate ribbon {w}x{l} {edge} D={depth}")
+    _, psi, ref, nrm, rn, en, re, plan = run_both(torch, cheb, case, 1.0, 3)
     assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
     np.testing.assert_allclose(en, re, rtol=1e-10, atol=1e-12)
