@@ -84,6 +84,34 @@ def test_batch_matches_oracle(torch, cheb, mode, tile, block, wg, graph):
         assert_state_close(s["psi"].cpu().numpy(), ref)
 
 
+# degenerate systems beside ordinary ones: a single site (its bounds widened
+# around its one eigenvalue), single columns and rows, a 2 x 2 cell; M differs
+# between them, so the schedules' per-system pass counts differ too
+DEGENERATE = [(1, 1, 0.4, 21, "zigzag"), (6, 1, 1.0, 22, "zigzag"), (5, 1, 1.0, 23, "armchair"),
+              (1, 3, 0.8, 24, "armchair"), (2, 2, 1.3, 25, "zigzag"), (40, 300, 0.5, 26, "zigzag")]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batch_degenerate_systems_match_oracle(torch, cheb, mode):
+    systems = make_systems(DEGENERATE, torch)
+    for s in systems:
+        if s["emax"] == s["emin"]:
+            s["emin"], s["emax"] = s["emin"] - 1.0, s["emax"] + 1.0
+    ctx = cheb.Context()
+    dt, K = 1.0, 4
+    ctx.batch_create(systems, dt)
+    ctx.batch_set_schedule(mode, 1024, 256, 1)
+    say(f"[gpu] batch of degenerate systems, mode={mode}")
+    ctx.batch_propagate(K, cheb.GRAPH)
+    torch.cuda.synchronize()
+    Ms = ctx.batch_info()
+    for s, M in zip(systems, Ms):
+        plan = O.Plan(s["emin"], s["emax"], dt)
+        assert M == plan.M
+        ref = O.propagate(s["H"], plan, s["psi0"], K)
+        assert_state_close(s["psi"].cpu().numpy(), ref)
+
+
 def test_batch_packets_match_oracle(torch, cheb):
     # the injected packets of the batched workload through the default deep
     # schedule
