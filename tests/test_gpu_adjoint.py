@@ -102,6 +102,40 @@ def test_adjoint_matches_oracle(torch, cheb, case, mode, dense):
     assert_state_close(u0, ur)
 
 
+# degenerate lattices: one site (bounds widened around its one eigenvalue),
+# two and three chain sites, single rows and columns of a ribbon, a 2 x 2 cell
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("kind,size", [("chain", 1), ("chain", 2), ("chain", 3), ("honeycomb", (1, 1)),
+                                       ("honeycomb", (1, 5)), ("honeycomb", (5, 1)), ("honeycomb", (2, 2))])
+def test_adjoint_degenerate_lattices_match_oracle(torch, cheb, kind, size, mode):
+    if kind == "chain":
+        n, dx = size, 1.0
+        V = W.uniform01(900 + n, n) - 0.5
+        H = O.chain1d(V, dx)
+        geom = dict(dx=dx)
+    else:
+        w, l = size
+        n = w * l
+        V = W.anderson_disorder(w, l, 0.5, 9)
+        H = O.honeycomb(w, l, V, edge="zigzag")
+        geom = dict(width=w, length=l, edge="zigzag")
+    psi0, mask = W.random_state(n, 950 + n), W.random_weights(n, 960 + n)
+    lo, hi = H.gershgorin()
+    if hi == lo:
+        lo, hi = lo - 1.0, hi + 1.0
+    dt, K = 2.0, 3
+    Lg, g, u0, prop = gpu_adjoint(torch, cheb, kind, geom, V, psi0, mask, (lo, hi), dt, K, mode)
+    plan = O.Plan(lo, hi, dt)
+    assert prop.M == plan.M
+    Lr, gr, ur = O.adjoint(H, plan, psi0, K, mask)
+    assert Lg == pytest.approx(Lr, rel=1e-10)
+    if n == 1:  # |psi|^2 of one site does not depend on V: dL/dV is zero up to rounding
+        assert abs(g).max() <= 1e-13 and abs(gr).max() <= 1e-13
+    else:
+        assert_grad_close(g, gr)
+    assert_state_close(u0, ur)
+
+
 # z = a dt from 1e-9 to 0.3 gives M = 1, 2, 3, 4, 5, 6, 10: the reverse sweep
 # pairs levels two by two where it can and leaves single levels (odd counts,
 # level 0, the level next to u_M) to the one-level kernel; the downward
