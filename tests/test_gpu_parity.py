@@ -425,6 +425,72 @@ def test_generic_csr_parity(torch, cheb):
     assert_state_close(host(psi), O.propagate(H, plan, psi0, 5))
 
 
+def _hermitian_csr(A):
+    n = A.shape[0]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i in range(n):
+        nz = np.nonzero(A[i])[0]
+        cols += list(nz)
+        vals += list(A[i, nz])
+        rowptr[i + 1] = len(cols)
+    return rowptr, np.array(cols, dtype=np.int32), np.array(vals, dtype=np.complex128)
+
+
+# CSR edge cases: a single entry, empty rows (eigenvalue 0, no neighbours),
+# and rows with 1 .. 13 entries (the kernel takes entries four at a time, so
+# every remainder of that loop), under lazy accumulation over 7 steps
+@pytest.mark.parametrize("case", ["single", "empty_rows", "ragged_rows"])
+def test_csr_edge_cases_match_oracle(torch, cheb, case):
+    rng = np.random.default_rng(17)
+    if case == "single":
+        A = np.array([[0.3 + 0.0j]])
+    else:
+        n = 60
+        A = np.zeros((n, n), dtype=np.complex128)
+        if case == "empty_rows":
+            live = np.arange(10, n)  # rows 0 .. 9 stay empty
+            for i in live:
+                j = rng.choice(live)
+                v = rng.normal() + 1j * rng.normal()
+                A[i, j] += v
+                A[j, i] += np.conj(v)
+        else:  # row 0 holds its diagonal alone
+            for i in range(1, n):
+                for j in rng.choice(np.arange(1, n), 1 + i % 7, replace=False):
+                    if j != i:
+                        v = rng.normal() + 1j * rng.normal()
+                        A[i, j] += v
+                        A[j, i] += np.conj(v)
+            A[np.diag_indices(n)] = rng.normal(size=n)
+        counts = np.count_nonzero(A, axis=1)
+        if case == "ragged_rows":
+            assert counts[0] == 1 and counts.max() >= 9 and set((counts % 4).tolist()) == {0, 1, 2, 3}
+        else:
+            assert (counts[:10] == 0).all()
+    rowptr, cols, vals = _hermitian_csr(A)
+    H = O.import_csr(rowptr, cols.astype(np.int64), vals)
+    emin, emax = H.gershgorin()
+    if emax == emin:
+        emin, emax = emin - 1.0, emax + 1.0
+    n = A.shape[0]
+    psi0 = W.random_state(n, 77 + n)
+    plan = O.Plan(emin, emax, 0.9)
+    ctx = cheb.Context()
+    r_d, c_d, v_d = dev(torch, rowptr), dev(torch, cols), dev(torch, vals)
+    ctx.csr(r_d, c_d, v_d)
+    ctx.set_bounds(emin, emax)
+    assert ctx.plan(0.9) == plan.M
+    psi = dev(torch, psi0)
+    nrm = torch.zeros(7, dtype=torch.float64, device="cuda")
+    say(f"[gpu] CSR edge case {case}, n={n}, nnz={len(vals)}, M={plan.M}")
+    ctx.propagate(psi, 7, nrm)
+    torch.cuda.synchronize()
+    ref, rn, _ = O.propagate(H, plan, psi0, 7, want_obs=True)
+    assert_state_close(host(psi), ref)
+    np.testing.assert_allclose(host(nrm), rn, rtol=1e-12)
+
+
 @pytest.mark.parametrize("M", [0, 1, 2, 3])
 def test_low_orders(torch, cheb, M):
     for case in (chain_case(300, state="dense"), chain_case(9000, state="dense"),
