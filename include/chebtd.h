@@ -384,7 +384,8 @@ int chebtd_reserve_adjoint(chebtd_ctx *ctx, int64_t max_steps, int mode);
 
 /* After chebtd_propagate(..., K, ..., CHEBTD_KEEP_CHECKPOINTS): gbar_dev
  * (complex128[n]) holds dL/dpsi_K on entry and the adjoint of psi_0 on
- * return; dLdV_dev (float64[n]) is accumulated into (+=).  On ribbons the
+ * return; dLdV_dev (float64[n]) is accumulated into (+=).  After a run of
+ * K = 0 steps both are left as they are.  On ribbons the
  * reverse sweep runs several levels per pass over memory and CHEBTD_ADJ_STEP
  * recomputes several orders per pass; CHEBTD_ADJ_REVERSE regenerates the
  * forward vectors downwards.  The modes group the levels differently and

@@ -86,7 +86,7 @@ int64_t adj_current_run(const Ctx *c)
 {
     const AdjState *a = c->adj;
     if (!a || !c->has_plan || a->plan_version != c->plan_version || a->ckpt_version != c->plan_version ||
-        a->last_K < 1)
+        a->ckpt_run == 0)
         return 0;
     return a->ckpt_run;
 }
@@ -502,6 +502,9 @@ int chebtd_adjoint_run(chebtd_ctx *ctx, int64_t run_id, double *gbar_dev, double
         return fail(c, CHEBTD_E_STATE,
                     "chebtd_adjoint: the checkpoints of run " + std::to_string(run_id) +
                         " were overwritten (the stored run is " + std::to_string(cur) + ")");
+    // a run of zero steps: psi_K = psi_0, so gbar passes through and dL/dV
+    // gains nothing
+    if (a->last_K == 0) return CHEBTD_OK;
     hipStream_t s = c->stream;
     const int M = c->M;
     const int64_t n = c->n;

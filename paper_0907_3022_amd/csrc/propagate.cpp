@@ -230,11 +230,13 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
     Ctx *c = static_cast<Ctx *>(ctx);
     if (!c->has_plan) return fail(c, CHEBTD_E_STATE, "chebtd_propagate: no plan");
     if (!psi_dev || K < 0) return fail(c, CHEBTD_E_ARG, "chebtd_propagate: need psi and K >= 0");
-    if (K == 0) return CHEBTD_OK;
     const bool keep = (flags & CHEBTD_KEEP_CHECKPOINTS) != 0;
+    // a checkpointing run of zero steps is a run too (its adjoint is the
+    // identity), so that no earlier trajectory stays current after it
     if (keep && !adj_begin_run(c, K))
         return fail(c, CHEBTD_E_STATE,
                     "chebtd_propagate: checkpoints need chebtd_reserve_adjoint with max_steps >= K");
+    if (K == 0) return CHEBTD_OK;
     const bool check = (flags & CHEBTD_NO_CHECK) == 0;
     hipStream_t s = c->stream;
     double2 *P = reinterpret_cast<double2 *>(psi_dev);

@@ -437,6 +437,40 @@ def test_adjoint_refuses_overwritten_run(torch, cheb):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_zero_step_run_replaces_the_stored_run(torch, cheb, mode):
+    # a checkpointing run of K = 0 steps is a run of its own: it becomes the
+    # stored run (the earlier one's adjoint is refused) and its adjoint is the
+    # identity (gbar passes through, dL/dV gains nothing)
+    w, l = 9, 70
+    V, psi0, _ = ribbon_inputs(w, l, dense=True)
+    lo, hi = O.honeycomb(w, l, V).gershgorin()
+    ctx = cheb.Context()
+    Vd = torch.from_numpy(V.copy()).cuda()
+    ctx.honeycomb(w, l, Vd)
+    ctx.set_bounds(lo, hi)
+    ctx.plan(1.3)
+    ctx.reserve_adjoint(3, mode)
+    psi = torch.from_numpy(psi0.copy()).cuda()
+    ctx.propagate(psi, 3, flags=cheb.KEEP_CHECKPOINTS)
+    run3 = ctx.checkpoint_run()
+    before = psi.clone()
+    ctx.propagate(psi, 0, flags=cheb.KEEP_CHECKPOINTS)
+    run0 = ctx.checkpoint_run()
+    assert 0 < run3 < run0
+    assert torch.equal(psi, before)
+    gbar = torch.from_numpy(W.random_state(w * l, 4321)).cuda()
+    g0 = gbar.clone()
+    dV = torch.full((w * l,), 0.25, dtype=torch.float64, device="cuda")
+    with pytest.raises(cheb.ChebError) as err:
+        ctx.adjoint(gbar, dV, run=run3)
+    assert err.value.code == -5  # CHEBTD_E_STATE
+    ctx.adjoint(gbar, dV, run=run0)
+    torch.cuda.synchronize()
+    assert torch.equal(gbar, g0) and bool((dV == 0.25).all())
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode", [None, 0, 1])
 def test_autograd_two_applies_before_backward(torch, cheb, mode):
     # one Propagator applied to two disorder realisations before one backward
