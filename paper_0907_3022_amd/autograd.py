@@ -31,6 +31,8 @@ class Propagator:
                  t=1.0, alpha=0.01, tol=1e-15, adjoint_mode=None, context=None):
         if kind not in ("chain", "honeycomb"):
             raise ValueError("kind must be 'chain' or 'honeycomb'")
+        if int(K) < 0:
+            raise ValueError("K must be >= 0")
         self.kind, self.dt, self.K = kind, float(dt), int(K)
         self.bounds = (float(bounds[0]), float(bounds[1]))
         self.dx, self.width, self.length, self.edge, self.t = dx, width, length, edge, t
@@ -51,15 +53,16 @@ class Propagator:
         """psi after K steps; with keep, the trajectory is stored for one
         backward and self.run numbers that run."""
         self._setup(V)
+        steps = max(self.K, 1)  # storage for at least one step (K = 0 stores none)
         if keep and self.adjoint_mode is None:
             try:
-                self.ctx.reserve_adjoint(self.K, L.ADJ_REVERSE)
+                self.ctx.reserve_adjoint(steps, L.ADJ_REVERSE)
             except L.ChebError as err:  # past the downward walk's offset limit
                 if err.code != L.E_ARG:
                     raise
-                self.ctx.reserve_adjoint(self.K, L.ADJ_STEP)
+                self.ctx.reserve_adjoint(steps, L.ADJ_STEP)
         elif keep:
-            self.ctx.reserve_adjoint(self.K, self.adjoint_mode)
+            self.ctx.reserve_adjoint(steps, self.adjoint_mode)
         psi = psi0.detach().clone().contiguous()
         self.ctx.propagate(psi, self.K, flags=L.KEEP_CHECKPOINTS if keep else 0)
         self.run = self.ctx.checkpoint_run() if keep else 0

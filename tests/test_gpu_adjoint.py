@@ -471,6 +471,18 @@ def test_zero_step_run_replaces_the_stored_run(torch, cheb, mode):
     ctx.close()
 
 
+def test_autograd_zero_steps_is_the_identity(torch, cheb):
+    # K = 0: psi_K = psi_0, so dL/dpsi_0 = dL/dpsi_K and dL/dV = 0
+    w, l = 9, 70
+    V, psi0, mask = ribbon_inputs(w, l, dense=True)
+    lo, hi = O.honeycomb(w, l, V).gershgorin()
+    L0, g, u0, _ = gpu_adjoint(torch, cheb, "honeycomb", dict(width=w, length=l), V, psi0, mask,
+                               (lo, hi), 1.3, 0, None)
+    assert L0 == pytest.approx(float((mask * np.abs(psi0) ** 2).sum()), rel=1e-14)
+    assert float(np.abs(g).max()) == 0.0
+    np.testing.assert_allclose(u0, 2.0 * mask * psi0, rtol=1e-13, atol=1e-300)
+
+
 @pytest.mark.parametrize("mode", [None, 0, 1])
 def test_autograd_two_applies_before_backward(torch, cheb, mode):
     # one Propagator applied to two disorder realisations before one backward
