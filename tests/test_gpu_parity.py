@@ -241,7 +241,8 @@ def test_holstein_parity_and_observables(torch, cheb, hol_spt_env, L, nph, g2, p
 
 def test_polaron_figure3_parameters_reduced(torch, cheb):
     # the Fig. 3 setting (open chain, barrier with extra local coupling, packet
-    # moving right with k = pi/9) on 12 sites with at most 5 phonons
+    # moving right with k = pi/9) on 12 sites with at most 5 phonons, to the
+    # figure's last time
     p = W.POLARON_PAPER.params
     L, nph = 12, 5
     g, Delta = W.polaron_couplings(L, p["w0"], p["eps_p"], p["eps_p_barrier"], 8, p["barrier"])
@@ -251,14 +252,19 @@ def test_polaron_figure3_parameters_reduced(torch, cheb):
     ctx = cheb.Context()
     ctx.holstein(L, nph, p["t"], p["w0"], g, Delta, False)
     ctx.set_bounds(emin, emax)
-    assert ctx.plan(p["dt"]) == O.Plan(emin, emax, p["dt"]).M
-    psi = dev(torch, psi0)
-    ctx.propagate(psi, 12)
-    torch.cuda.synchronize()
-    ref = O.propagate(H, O.Plan(emin, emax, p["dt"]), psi0, 12)
-    assert_state_close(host(psi), ref)
-    for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
-        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+    plan = O.Plan(emin, emax, p["dt"])
+    assert ctx.plan(p["dt"]) == plan.M
+    # the figure's times t = 6, 10, 14, reached step by step on both sides
+    psi, ref, t_prev = dev(torch, psi0), psi0, 0.0
+    for ts in p["snapshots"]:
+        K = int(round((ts - t_prev) / p["dt"]))
+        ctx.propagate(psi, K)
+        torch.cuda.synchronize()
+        ref = O.propagate(H, plan, ref, K)
+        assert_state_close(host(psi), ref)
+        for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), O.holstein_obs(L, nph, ref)):
+            np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
+        t_prev = ts
 
 
 @pytest.fixture
