@@ -410,14 +410,23 @@ def bench_batched(torch, P, K, seq_steps=10):
     seq_rate = site_orders * seq_steps / seq_t
     mode = ["levels", "persistent", "pairs", "deep"][best[0]]
     # algorithmic bytes of one step: 88 per site and order, or 104 per site
-    # and multi-order pass plus 88 for an odd tail (the deep schedule: M //
-    # depth passes of `depth` orders per system, then pairs)
+    # and multi-order pass plus 88 for an odd tail (the deep schedule: the
+    # fewest passes of `depth` or `depth` + 1 orders that cover M, else
+    # M // depth passes taking up to one extra order each, then pairs)
     if mode in ("pairs", "deep"):
         depth = int(os.environ.get("CHEBTD_BATCH_DEPTH", "5")) if mode == "deep" else 2
 
         def passes(M):
-            nd = M // depth if mode == "deep" else 0
-            rest = M - nd * depth
+            nd, ext = 0, 0
+            if mode == "deep":
+                E = depth + 1 if depth < 6 else 0
+                if E and depth * (-(-M // E)) <= M:
+                    nd = -(-M // E)
+                    ext = M - depth * nd
+                else:
+                    nd = M // depth
+                    ext = min(M - depth * nd, nd) if E else 0
+            rest = M - nd * depth - ext
             return nd + rest // 2, rest % 2
         step_bytes = sum(s["width"] * s["length"] * (PAIR_BYTES * passes(int(M))[0] + STENCIL_BYTES * passes(int(M))[1])
                          for s, M in zip(systems, Ms))

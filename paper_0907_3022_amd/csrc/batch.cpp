@@ -45,13 +45,19 @@ struct BatchState {
     std::vector<int64_t> pair_level_blocks;
     DevBuf pblk_sys, pblk_wave0, tblk_sys, tblk_tile;
     int64_t ntail_blocks = 0;
-    // deep schedule: each system takes M / deep_D passes of deep_D orders
-    // (pass p runs the systems with more than p of them: a prefix of
-    // `order`), then two-order passes while it has two or more orders left
-    // (explicit block lists, concatenated), then the tail if one is left
+    // deep schedule: each system takes the fewest passes of deep_D or
+    // deep_D + 1 orders that cover its M (deep_D + 1 first), then two-order
+    // passes while it has two or more orders left, then the tail if one is
+    // left; one launch per (pass, depth) over the systems it concerns, and
+    // one per two-order pass (explicit block lists, concatenated)
     bool deep_ok = false;
     int deep_D = 5;
-    std::vector<int64_t> deep_pass_blocks, deep_pair_off;
+    struct DeepLaunch {
+        int pass, depth;
+        int64_t off, count;
+    };
+    std::vector<DeepLaunch> deep_launches;
+    std::vector<int64_t> deep_pair_off;
     DevBuf dblk_sys, dblk_wave0, dpblk_sys, dpblk_wave0, dtblk_sys, dtblk_tile;
     int64_t ndtail_blocks = 0;
     DevBuf head, done, flag;
@@ -165,32 +171,40 @@ static int build_tables(Ctx *c, BatchState *b)
     b->ntail_blocks = (int64_t)tsys.size();
     // deep schedule tables
     std::vector<int32_t> dsys, dw0, dpsys, dpw0, dtsys, dttile;
-    b->deep_pass_blocks.clear();
+    b->deep_launches.clear();
     b->deep_pair_off.assign(1, 0);
     if (b->deep_ok) {
-        const int D = b->deep_D;
-        std::vector<int64_t> dprefix(ns + 1, 0);
-        for (int j = 0; j < ns; ++j) {
-            const SysDev &sd = b->sys[b->order[j]];
-            const int64_t nbk = ((int64_t)sd.dnstrips * sd.dnchunks + 3) / 4;
-            for (int64_t q = 0; q < nbk; ++q) {
-                dsys.push_back(b->order[j]);
-                dw0.push_back((int32_t)(4 * q));
+        const int D = b->deep_D, E = D + 1;
+        int maxpass = 0, maxrest = 0;
+        for (int s = 0; s < ns; ++s) {
+            maxpass = std::max(maxpass, b->sys[s].ndeep);
+            maxrest = std::max(maxrest, b->M[s] - b->sys[s].kdeep);
+        }
+        for (int p = 0; p < maxpass; ++p)
+            for (int depth : {E, D}) {
+                const int64_t off = (int64_t)dsys.size();
+                for (int j = 0; j < ns; ++j) {
+                    const int sid = b->order[j];
+                    const SysDev &sd = b->sys[sid];
+                    if (p >= sd.ndeep || (p < sd.ndeep_ext ? E : D) != depth) continue;
+                    const bool ext = depth != D;
+                    const int64_t nbk = ((int64_t)(ext ? sd.dnstrips_ext : sd.dnstrips) *
+                                             (ext ? sd.dnchunks_ext : sd.dnchunks) +
+                                         3) /
+                                        4;
+                    for (int64_t w = 0; w < nbk; ++w) {
+                        dsys.push_back(sid);
+                        dw0.push_back((int32_t)(4 * w));
+                    }
+                }
+                if ((int64_t)dsys.size() > off) b->deep_launches.push_back({p, depth, off, (int64_t)dsys.size() - off});
             }
-            dprefix[j + 1] = dprefix[j] + nbk;
-        }
-        if (dprefix[ns] > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many wavefronts");
-        for (int p = 0; (p + 1) * D <= Mmax; ++p) {
-            int cnt = 0;
-            for (int j = 0; j < ns; ++j)
-                if (b->M[b->order[j]] / D > p) ++cnt;
-            b->deep_pass_blocks.push_back(dprefix[cnt]);
-        }
-        for (int q = 0; 2 * q + 2 < D; ++q) {
+        if ((int64_t)dsys.size() > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many wavefronts");
+        for (int q = 0; 2 * q + 2 <= maxrest; ++q) {
             for (int j = 0; j < ns; ++j) {
                 const int sid = b->order[j];
-                if (b->M[sid] % D < 2 * q + 2) continue;
                 const SysDev &sd = b->sys[sid];
+                if (b->M[sid] - sd.kdeep < 2 * q + 2) continue;
                 const int64_t nbk = ((int64_t)sd.nstrips * sd.nchunks + 3) / 4;
                 for (int64_t w = 0; w < nbk; ++w) {
                     dpsys.push_back(sid);
@@ -201,7 +215,7 @@ static int build_tables(Ctx *c, BatchState *b)
         }
         if ((int64_t)dpsys.size() > INT32_MAX) return fail(c, CHEBTD_E_ARG, "batch: too many wavefronts");
         for (int s = 0; s < ns; ++s)
-            if ((b->M[s] % D) & 1)
+            if ((b->M[s] - b->sys[s].kdeep) & 1)
                 for (int64_t t = 0; t < tiles[s]; ++t) {
                     dtsys.push_back(s);
                     dttile.push_back((int32_t)t);
@@ -260,8 +274,8 @@ static hipError_t enqueue_step(Ctx *c, BatchState *b, hipStream_t s, int par)
         const int32_t *dsys = static_cast<const int32_t *>(b->dblk_sys.p);
         const int32_t *dw = static_cast<const int32_t *>(b->dblk_wave0.p);
         const int D = b->deep_D;
-        for (size_t p = 0; p < b->deep_pass_blocks.size(); ++p) {
-            hipError_t e = launch_batch_deep(s, D, sys, gam, dsys, dw, b->deep_pass_blocks[p], (int)p, (int)p * D,
+        for (const auto &dl : b->deep_launches) {
+            hipError_t e = launch_batch_deep(s, dl.depth, sys, gam, dsys + dl.off, dw + dl.off, dl.count, dl.pass, D,
                                              par);
             if (e != hipSuccess) return e;
         }
@@ -295,7 +309,7 @@ static hipError_t enqueue_step(Ctx *c, BatchState *b, hipStream_t s, int par)
 static int run_steps(Ctx *c, BatchState *b, int64_t K, bool use_graph)
 {
     hipStream_t s = c->stream;
-    hipError_t e = hipMemsetAsync(b->flag.p, 0, sizeof(int32_t), s);
+    hipError_t e = launch_batch_clear_flag(s, static_cast<int32_t *>(b->flag.p));
     if (e != hipSuccess) return hip_fail(c, e, "batch flag reset");
     if (use_graph && K >= 2) {
         if (!b->graph) {
@@ -464,12 +478,18 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
         if (b->M[s] < 2) b->pairs_ok = false;  // the head of a pair level computes two orders
         sd.npass_pairs = b->M[s] >> 1;
     }
-    // deep schedule: deep_D orders per pass (CHEBTD_BATCH_DEPTH, 4 .. 6,
-    // overrides), M / deep_D passes per system, so every system needs M >=
-    // deep_D; chunk heights as for one ribbon below 4M sites (the systems here
-    // are far smaller; on the 256-ribbon workload over 200 steps 10 rows ran
-    // 211 G site-orders/s, 16 rows 209 G, 22 rows 205 G); CHEBTD_BATCH_DEEP_ROWS
-    // overrides
+    // deep schedule: passes of D = deep_D (CHEBTD_BATCH_DEPTH, 4 .. 6,
+    // overrides) or D + 1 orders, so every system needs M >= D.  On these
+    // HBM-bound passes a pass costs about the same whatever its depth
+    // (measured on MI355X over the 256-ribbon workload: 1020, 1024 and 1062
+    // us for four, five and six orders; a two-order pass 1042 us over the
+    // same systems), so each system takes the fewest passes: P = ceil(M /
+    // (D + 1)) of them when P D <= M (M - P D of them with D + 1 orders),
+    // else M / D passes that take up to one extra order each, with pairs and
+    // the tail for what is left.  Chunk heights as for one ribbon below 4M
+    // sites (the systems here are far smaller; on the 256-ribbon workload
+    // over 200 steps 10 rows ran 211 G site-orders/s, 16 rows 209 G, 22 rows
+    // 205 G); CHEBTD_BATCH_DEEP_ROWS overrides
     if (const char *env = std::getenv("CHEBTD_BATCH_DEPTH")) b->deep_D = std::max(4, std::min(6, std::atoi(env)));
     b->deep_ok = b->pairs_ok;
     static const int drows_of[7] = {0, 0, 0, 8, 6, 10, 14};
@@ -477,13 +497,26 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
     if (const char *env = std::getenv("CHEBTD_BATCH_DEEP_ROWS")) drows_env = std::max(1, std::atoi(env));
     for (int s = 0; s < nsys; ++s) {
         SysDev &sd = b->sys[s];
-        const int D = b->deep_D;
-        if (b->M[s] < D || !deep_offsets_fit(sd.W, sd.L)) b->deep_ok = false;
+        const int D = b->deep_D, E = D + 1 <= kMaxDepth ? D + 1 : 0, M = b->M[s];
+        if (M < D || !deep_offsets_fit(sd.W, sd.L)) b->deep_ok = false;
         sd.drows = std::min<int32_t>(sd.W, drows_env ? drows_env : drows_of[D]);
         sd.dnstrips = (sd.L + deep_strip_cols(D) - 1) / deep_strip_cols(D);
         sd.dnchunks = (sd.W + sd.drows - 1) / sd.drows;
-        sd.ndeep = b->M[s] / D;
-        sd.npass_deep = sd.ndeep + (b->M[s] % D) / 2;
+        sd.drows_ext = E ? std::min<int32_t>(sd.W, drows_env ? drows_env : drows_of[E]) : sd.drows;
+        sd.dnstrips_ext = E ? (sd.L + deep_strip_cols(E) - 1) / deep_strip_cols(E) : sd.dnstrips;
+        sd.dnchunks_ext = (sd.W + sd.drows_ext - 1) / sd.drows_ext;
+        int npass = 0, next = 0;  // passes, of which with D + 1 orders
+        if (E && D * ((M + E - 1) / E) <= M) {
+            npass = (M + E - 1) / E;
+            next = M - D * npass;
+        } else {
+            npass = M / D;
+            next = E ? std::min(M - D * npass, npass) : 0;
+        }
+        sd.ndeep = npass;
+        sd.ndeep_ext = next;
+        sd.kdeep = D * npass + next;
+        sd.npass_deep = sd.ndeep + (M - sd.kdeep) / 2;
     }
     b->order.resize(nsys);
     for (int s = 0; s < nsys; ++s) b->order[s] = s;

@@ -135,9 +135,8 @@ __global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ s
 {
     const int32_t lb = logical_block(1);
     const SysDev sd = sys[blk_sys[lb]];
-    const int32_t base = deep_D > 0 ? sd.ndeep : 0;
-    const int pass = base + q;
-    const int k = base * deep_D + 2 * q;
+    const int pass = (deep_D > 0 ? sd.ndeep : 0) + q;
+    const int k = (deep_D > 0 ? sd.kdeep : 0) + 2 * q;
     const int32_t gw = __builtin_amdgcn_readfirstlane(blk_wave0[lb] + (int32_t)(threadIdx.x >> 6));
     const int32_t strip = gw % sd.nstrips;
     const int32_t chunk = gw / sd.nstrips;
@@ -185,18 +184,24 @@ __global__ __launch_bounds__(256) void k_batch_pair(const SysDev *__restrict__ s
 
 // D orders per pass over the batch (the deep walk of deep_walk.h, each
 // system with its own operator, grid and weights), buffers as k_batch_pair.
+// D is the batch's depth `base` or base + 1 (a system's first ndeep_ext
+// passes); the system's grid and first order follow from it.
 template <bool HEAD, int D>
 __global__ __launch_bounds__(256) void k_batch_deep(const SysDev *__restrict__ sys,
                                                     const double2 *__restrict__ gamma,
                                                     const int32_t *__restrict__ blk_sys,
-                                                    const int32_t *__restrict__ blk_wave0, int pass, int k, int par)
+                                                    const int32_t *__restrict__ blk_wave0, int pass, int base,
+                                                    int par)
 {
     const int32_t lb = logical_block(1);
     const SysDev sd = sys[blk_sys[lb]];
+    const bool ext = D != base;
+    const int32_t nstrips = ext ? sd.dnstrips_ext : sd.dnstrips, nchunks = ext ? sd.dnchunks_ext : sd.dnchunks;
     const int32_t gw = __builtin_amdgcn_readfirstlane(blk_wave0[lb] + (int32_t)(threadIdx.x >> 6));
-    const int32_t strip = gw % sd.dnstrips;
-    const int32_t chunk = gw / sd.dnstrips;
-    if (chunk >= sd.dnchunks) return;  // uniform per wavefront; the kernel has no barrier
+    const int32_t strip = gw % nstrips;
+    const int32_t chunk = gw / nstrips;
+    if (chunk >= nchunks) return;  // uniform per wavefront; the kernel has no barrier
+    const int k = (base + 1) * min(pass, sd.ndeep_ext) + base * max(0, pass - sd.ndeep_ext);
     OpPair op{};
     op.onsite = sd.eps;
     op.dshift = -sd.b;
@@ -204,9 +209,9 @@ __global__ __launch_bounds__(256) void k_batch_deep(const SysDev *__restrict__ s
     op.off2 = sd.off2;
     op.W = sd.W;
     op.L = sd.L;
-    op.rows = sd.drows;
-    op.nstrips = sd.dnstrips;
-    op.nchunks = sd.dnchunks;
+    op.rows = ext ? sd.drows_ext : sd.drows;
+    op.nstrips = nstrips;
+    op.nchunks = nchunks;
     double2 *cur = par ? sd.B : sd.psi;
     double2 *nxt = par ? sd.psi : sd.B;
     const double2 *g = gamma + sd.gamma_off;
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(256) void k_batch_deep(const SysDev *__restrict__ s
     A.acc = nxt;
     // the system's final pass (no pairs or tail after it): nothing reads its
     // two orders, so only acc is written
-    if (pass == sd.ndeep - 1 && sd.M == sd.ndeep * D) A.out1 = A.out2 = nullptr;
+    if (pass == sd.ndeep - 1 && sd.M == sd.kdeep) A.out1 = A.out2 = nullptr;
 #pragma unroll
     for (int j = 0; j <= D; ++j) A.w.g[j] = (HEAD || j > 0) ? ldg(g, k + j) : make_double2(0.0, 0.0);
     double nrm = 0.0, en = 0.0;
@@ -350,6 +355,10 @@ __global__ void k_batch_persistent(const SysDev *__restrict__ sys, const double2
     }
 }
 
+// the timeout flag cleared by a kernel (no memset node when a caller
+// captures the call into a graph)
+__global__ void k_batch_clear_flag(int32_t *flag) { flag[0] = 0; }
+
 __global__ void k_batch_reset(int64_t *queue_head, int32_t *done, int32_t nsys)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -404,29 +413,35 @@ hipError_t launch_batch_pair(hipStream_t s, const SysDev *sys, const double2 *ga
 namespace {
 template <int D>
 hipError_t launch_batch_deep_d(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,
-                               const int32_t *blk_wave0, int64_t nblocks, int pass, int k, int par)
+                               const int32_t *blk_wave0, int64_t nblocks, int pass, int base, int par)
 {
     if (pass == 0)
         hipLaunchKernelGGL((k_batch_deep<true, D>), dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma, blk_sys,
-                           blk_wave0, pass, k, par);
+                           blk_wave0, pass, base, par);
     else
         hipLaunchKernelGGL((k_batch_deep<false, D>), dim3((unsigned)nblocks), dim3(256), 0, s, sys, gamma,
-                           blk_sys, blk_wave0, pass, k, par);
+                           blk_sys, blk_wave0, pass, base, par);
     return hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_batch_deep(hipStream_t s, int D, const SysDev *sys, const double2 *gamma,
-                             const int32_t *blk_sys, const int32_t *blk_wave0, int64_t nblocks, int pass, int k,
+                             const int32_t *blk_sys, const int32_t *blk_wave0, int64_t nblocks, int pass, int base,
                              int par)
 {
     if (nblocks <= 0) return hipSuccess;
     switch (D) {
-        case 4: return launch_batch_deep_d<4>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, k, par);
-        case 5: return launch_batch_deep_d<5>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, k, par);
-        case 6: return launch_batch_deep_d<6>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, k, par);
+        case 4: return launch_batch_deep_d<4>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, base, par);
+        case 5: return launch_batch_deep_d<5>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, base, par);
+        case 6: return launch_batch_deep_d<6>(s, sys, gamma, blk_sys, blk_wave0, nblocks, pass, base, par);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_batch_clear_flag(hipStream_t s, int32_t *flag)
+{
+    hipLaunchKernelGGL(k_batch_clear_flag, dim3(1), dim3(1), 0, s, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_tail(hipStream_t s, const SysDev *sys, const double2 *gamma, const int32_t *blk_sys,

@@ -126,10 +126,11 @@ def test_batch_packets_match_oracle(torch, cheb):
         assert_state_close(s["psi"].cpu().numpy(), ref)
 
 
-def single_system(torch, cheb, s, K, depth):
+def single_system(torch, cheb, s, K, depth, passes=None):
     """One system through the single-system path; depth 2 keeps it on the
     two-orders and one-order kernels the batch shares, None lets the plan
-    split the orders as it does by default."""
+    split the orders as it does by default.  passes (a list) receives the
+    plan's orders per pass."""
     saved = os.environ.get("CHEBTD_DEPTH")
     if depth is None:
         os.environ.pop("CHEBTD_DEPTH", None)
@@ -140,6 +141,8 @@ def single_system(torch, cheb, s, K, depth):
         one.honeycomb(s["width"], s["length"], s["eps"], edge=s["edge"])
         one.set_bounds(s["emin"], s["emax"])
         one.plan(1.0)
+        if passes is not None:
+            passes.extend(one.plan_passes())
     finally:
         if saved is None:
             os.environ.pop("CHEBTD_DEPTH", None)
@@ -195,14 +198,30 @@ def test_batch_rejects_bad_schedule(torch, cheb):
         ctx.batch_set_schedule(5, 1024, 256, 2)
 
 
+def batch_deep_split(M, D=5):
+    """Orders per pass the batched deep schedule gives a system: the fewest
+    passes of D or D + 1 orders (D + 1 first) when they cover M exactly,
+    else M // D passes taking up to one extra order each, then two-order
+    passes and a one-order tail."""
+    E = D + 1 if D < 6 else 0
+    if E and D * (-(-M // E)) <= M:
+        npass = -(-M // E)
+        ext = M - D * npass
+    else:
+        npass = M // D
+        ext = min(M - D * npass, npass) if E else 0
+    rest = M - D * npass - ext
+    return [E] * ext + [D] * (npass - ext) + [2] * (rest // 2) + [1] * (rest % 2)
+
+
 @pytest.mark.parametrize("rows", [None, "3", "22", "40"])
 @pytest.mark.parametrize("K", [1, 2, 3])
 def test_batch_deep_equals_single_system_path_bitwise(torch, cheb, monkeypatch, K, rows):
-    # five orders per pass while every system has five left (M = 20 .. 22 here:
-    # four passes), then a two-order pass or the one-order tail; the single
-    # system restricted to passes of 1, 2 and 5 orders splits M the same way.
-    # A site's arithmetic does not depend on the chunk heights (the batch's
-    # default, overrides, the single system's own)
+    # the fewest passes of five or six orders per system (M = 17 .. 22 here:
+    # 6+6+5, 5+5+5+5, 6+5+5+5, 6+6+5+5), which is also how the single
+    # system's default plan splits these M: the same passes in the same
+    # order, hence the same bits.  A site's arithmetic does not depend on the
+    # chunk heights (the batch's default, overrides, the single system's own)
     if rows is not None:
         monkeypatch.setenv("CHEBTD_BATCH_DEEP_ROWS", rows)
     systems = make_systems(SMALL, torch)
@@ -212,9 +231,28 @@ def test_batch_deep_equals_single_system_path_bitwise(torch, cheb, monkeypatch, 
     ctx.batch_propagate(K, cheb.GRAPH)
     torch.cuda.synchronize()
     Ms = ctx.batch_info()
-    assert Ms.min() >= 5 and len(set(int(m) % 5 for m in Ms)) > 1
+    assert {6, 5} <= {d for M in Ms for d in batch_deep_split(int(M))}
+    for s, M in zip(systems, Ms):
+        passes = []
+        got = single_system(torch, cheb, s, K, None, passes)
+        assert passes == batch_deep_split(int(M))
+        np.testing.assert_array_equal(got, s["psi"].cpu().numpy())
+
+
+@pytest.mark.parametrize("depth", ["4", "6"])
+def test_batch_deep_other_depths_match_oracle(torch, cheb, monkeypatch, depth):
+    # CHEBTD_BATCH_DEPTH=4: passes of four or five orders; =6: passes of six
+    # orders only (no deeper walk), then two-order passes and the tail
+    monkeypatch.setenv("CHEBTD_BATCH_DEPTH", depth)
+    systems = make_systems(SMALL, torch)
+    ctx = cheb.Context()
+    ctx.batch_create(systems, 1.0)
+    ctx.batch_set_schedule(cheb.SCHED_DEEP, 1024, 256, 1)
+    ctx.batch_propagate(3, cheb.GRAPH)
+    torch.cuda.synchronize()
     for s in systems:
-        np.testing.assert_array_equal(single_system(torch, cheb, s, K, 5), s["psi"].cpu().numpy())
+        ref = O.propagate(s["H"], O.Plan(s["emin"], s["emax"], 1.0), s["psi0"], 3)
+        assert_state_close(s["psi"].cpu().numpy(), ref)
 
 
 @pytest.mark.parametrize("K", [1, 2, 3])
