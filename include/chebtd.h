@@ -308,10 +308,13 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
                                   /* over every system still active (needs  */
                                   /* M >= 2 everywhere), plus one tail      */
                                   /* launch for systems with odd M           */
-#define CHEBTD_SCHED_DEEP 3       /* one launch per D (4..6) orders over    */
-                                  /* every system while all have D left,    */
-                                  /* then the pairs schedule's launches for */
-                                  /* the rest (needs M >= D everywhere)     */
+#define CHEBTD_SCHED_DEEP 3       /* passes of D (5; 4..6 by environment  */
+                                  /* CHEBTD_BATCH_DEPTH) or D + 1 orders:   */
+                                  /* each system takes the fewest that     */
+                                  /* cover its M, one launch per pass and   */
+                                  /* depth, then two-order and one-order    */
+                                  /* passes for what is left (needs M >= D  */
+                                  /* everywhere)                            */
 
 /* Fix the schedule: mode, rows per tile (multiple of block, >= block),
  * threads per block (64..1024, multiple of 64), and for the persistent
