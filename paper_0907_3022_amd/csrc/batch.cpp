@@ -255,6 +255,26 @@ static int build_tables(Ctx *c, BatchState *b)
     return CHEBTD_OK;
 }
 
+// Passes of the batched deep schedule for M orders at depth D: npass passes,
+// the first next of them with D + 1 orders (D + 1 <= kMaxDepth), covering
+// D npass + next <= M orders; the rest goes to two-order passes and the
+// one-order tail.  The fewest passes that cover M exactly when there are
+// such (P = ceil(M / (D + 1)) passes with P D <= M), else M / D passes taking
+// one extra order each while orders are left.
+void batch_deep_split(int M, int D, int *npass, int *next)
+{
+    const int E = D + 1 <= kMaxDepth ? D + 1 : 0;
+    if (M < 1 || D < 1) {
+        *npass = *next = 0;
+    } else if (E && D * ((M + E - 1) / E) <= M) {
+        *npass = (M + E - 1) / E;
+        *next = M - D * *npass;
+    } else {
+        *npass = M / D;
+        *next = E ? std::min(M - D * *npass, *npass) : 0;
+    }
+}
+
 static hipError_t enqueue_step(Ctx *c, BatchState *b, hipStream_t s, int par)
 {
     const SysDev *sys = static_cast<const SysDev *>(b->sys_dev.p);
@@ -506,13 +526,7 @@ int chebtd_batch_create(chebtd_ctx *ctx, int nsys, const chebtd_sys_desc *descs,
         sd.dnstrips_ext = E ? (sd.L + deep_strip_cols(E) - 1) / deep_strip_cols(E) : sd.dnstrips;
         sd.dnchunks_ext = (sd.W + sd.drows_ext - 1) / sd.drows_ext;
         int npass = 0, next = 0;  // passes, of which with D + 1 orders
-        if (E && D * ((M + E - 1) / E) <= M) {
-            npass = (M + E - 1) / E;
-            next = M - D * npass;
-        } else {
-            npass = M / D;
-            next = E ? std::min(M - D * npass, npass) : 0;
-        }
+        batch_deep_split(M, D, &npass, &next);
         sd.ndeep = npass;
         sd.ndeep_ext = next;
         sd.kdeep = D * npass + next;

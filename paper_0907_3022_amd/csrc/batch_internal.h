@@ -70,6 +70,8 @@ hipError_t launch_batch_tail(hipStream_t s, const SysDev *sys, const double2 *ga
                              const int32_t *blk_tile, int64_t nblocks, int32_t tile, int par, int block,
                              int deep);
 hipError_t launch_batch_clear_flag(hipStream_t s, int32_t *flag);
+// the deep schedule's passes for M orders at depth D (batch.cpp)
+void batch_deep_split(int M, int D, int *npass, int *next);
 hipError_t launch_batch_copy_back(hipStream_t s, const SysDev *sys, const int32_t *blk_sys,
                                   const int32_t *blk_tile, int64_t nblocks, int32_t tile, int block);
 

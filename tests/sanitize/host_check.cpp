@@ -1,8 +1,9 @@
 // Host-side exercise of the library's runtime for the sanitizer build of the
 // tests: the plan helpers (Bessel values by Miller's backward recurrence,
 // truncation order, weights of eq. (U_1)), the Holstein basis tables and CSR
-// builder of eq. (ghm) (threaded), and the argument checks of the C ABI
-// entry points, none of which needs a GPU.  Built with AddressSanitizer and
+// builder of eq. (ghm) (threaded), the argument checks of the C ABI entry
+// points and the batched schedule's split of M into passes, none of which
+// needs a GPU.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer (host code only); any report aborts the run.
 // Exit status 0: every check passed.
 #include <cmath>
@@ -10,8 +11,13 @@
 #include <string>
 #include <vector>
 
+#include "batch_internal.h"
 #include "chebtd.h"
 #include "internal.h"
+
+namespace chebtd {
+std::vector<int> plan_passes(const Ctx &c, int M);  // api.cpp
+}
 
 using namespace chebtd;
 
@@ -86,6 +92,32 @@ int main()
     CHECK(chebtd_destroy(nullptr) == CHEBTD_OK);
     int64_t n = 0, nnz = 0;
     CHECK(chebtd_holstein_csr_host(2, 3, 1.0, 1.0, &d, &d, 1, &n, &nnz, nullptr, nullptr, nullptr) != CHEBTD_OK);
+    // the batched deep schedule's passes: they cover M with at most one
+    // extra order per pass, the fewest passes whenever passes of D and D + 1
+    // orders can cover M exactly, and (D = 5) the single-system plan's split
+    // of the same M on a small ribbon from 10 orders on
+    Ctx rib;
+    rib.kind = HKind::Honeycomb;
+    rib.W = 16;
+    rib.L = 64;
+    rib.n = rib.W * rib.L;
+    for (int D = 4; D <= 6; ++D)
+        for (int M = D; M <= 300; ++M) {
+            int np = -1, ne = -1;
+            batch_deep_split(M, D, &np, &ne);
+            const int kdeep = D * np + ne, rest = M - kdeep;
+            CHECK(np >= 1 && ne >= 0 && ne <= np && rest >= 0 && rest < D);
+            CHECK(ne == 0 || D + 1 <= kMaxDepth);
+            const int P = D + 1 <= kMaxDepth ? (M + D) / (D + 1) : 0;
+            if (P && D * P <= M) CHECK(rest == 0 && np == P);
+            if (D == 5 && M >= 10) {
+                std::vector<int> want(ne, D + 1);
+                want.insert(want.end(), np - ne, D);
+                want.insert(want.end(), rest / 2, 2);
+                if (rest & 1) want.push_back(1);
+                CHECK(plan_passes(rib, M) == want);
+            }
+        }
     std::printf("host_check: %d failures\n", failures);
     return failures == 0 ? 0 : 1;
 }
