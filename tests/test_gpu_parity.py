@@ -625,6 +625,58 @@ def test_density_region_norm_energy(torch, cheb):
     assert ne[1] == pytest.approx(np.vdot(case["psi0"], Hd @ case["psi0"]).real, rel=1e-12, abs=1e-13)
 
 
+@pytest.mark.parametrize("kind", ["chain", "csr", "holstein_tables", "holstein_ranks"])
+def test_norm_energy_of_every_operator(torch, cheb, hol_spt_env, kind):
+    # <psi|psi> and <psi|H|psi> of a dense state through chebtd_norm_energy:
+    # for the Holstein model the walk's head mode without outputs (partial
+    # sums only), with the partner tables and with the ranks formed in the walk
+    rank = None
+    if kind == "chain":
+        case = chain_case(777, state="dense")
+    elif kind == "csr":
+        case = holstein_case(5, 4, 2.0, True, state="dense")
+        rowptr, col, val = case["H"].csr()
+        case = dict(case, kind="csr", csr=(rowptr, col.astype(np.int32), val))
+    else:
+        case = holstein_case(6, 5, 0.5, False, Delta=np.linspace(0, 0.3, 6), state="dense")
+        rank = kind == "holstein_ranks"
+    hol_spt_env(None, rank)
+    emin, emax = case["H"].gershgorin()
+    if kind == "csr":
+        ctx = cheb.Context()
+        r_d, c_d, v_d = (dev(torch, a) for a in case["csr"])
+        ctx.csr(r_d, c_d, v_d)
+    else:
+        ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax)
+    psi0 = case["psi0"]
+    ne = host(ctx.norm_energy(dev(torch, psi0)))
+    e_ref = np.vdot(psi0, case["H"].dense() @ psi0).real
+    assert ne[0] == pytest.approx(float(np.vdot(psi0, psi0).real), rel=1e-13)
+    assert ne[1] == pytest.approx(e_ref, rel=1e-12, abs=1e-12 * (abs(emin) + abs(emax)))
+    ctx.close()
+
+
+def test_region_sum_and_norm_past_the_reduction_grid(torch, cheb):
+    # 1.5M sites: each thread of the norm and region sums walks several sites
+    # (at most 2048 blocks of 256 threads); both against numpy sums
+    n = 1_500_001
+    psi0 = W.random_state(n, 4242)
+    mask = (W.uniform01(77, n) < 0.3).astype(np.uint8)
+    x, dx = W.chain_grid(n, -30.0, 30.0)
+    ctx = cheb.Context()
+    V = torch.from_numpy(W.harmonic(x, 1e-3)).cuda()
+    ctx.chain1d(V, dx)
+    ctx.set_bounds(*ctx.gershgorin())
+    psi = dev(torch, psi0)
+    rho = np.abs(psi0) ** 2
+    got = host(ctx.region_sum(psi, dev(torch, mask)))[0]
+    assert got == pytest.approx(float(rho[mask == 1].sum()), rel=1e-12)
+    ne = host(ctx.norm_energy(psi))
+    assert ne[0] == pytest.approx(float(rho.sum()), rel=1e-12)
+    ctx.close()
+
+
 def test_divergence_is_reported(torch, cheb):
     # bounds that miss most of the spectrum make T_k(H~) grow: the end-of-call
     # check must report it instead of returning garbage
