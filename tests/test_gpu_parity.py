@@ -232,6 +232,8 @@ def test_holstein_parity_and_observables(torch, cheb, hol_spt_env, L, nph, g2, p
     ctx, psi, ref, nrm, rn, en, re, _ = run_both(torch, cheb, case, 0.1, 8)
     assert_state_close(psi, ref)
     np.testing.assert_allclose(nrm, rn, rtol=1e-12)
+    _, name, orders = ctx.time_recursion_kernel(1)  # the walk that ran
+    assert orders == 1 and name == ("k_iter_hol<true, false>" if rank else "k_iter_hol<false, false>")
     n_i, nph_i, chi = (host(t) for t in ctx.holstein_obs(dev(torch, ref)))
     rn_i, rnph_i, rchi = O.holstein_obs(L, nph, ref)
     np.testing.assert_allclose(n_i, rn_i, rtol=1e-12, atol=1e-15)
@@ -362,6 +364,8 @@ def test_holstein_open_chain_16M_states_matches_oracle(torch, cheb, hol_spt_env)
         say(f"[gpu] Holstein L=12 nph=11 (16.2M states), sites per thread {spt or L}, own ranks {rank}")
         ctx.propagate(psi, 2)
         torch.cuda.synchronize()
+        ranks = rank is None or rank  # past 8M states the default ranks the partners
+        assert ctx.time_recursion_kernel(1)[1].startswith("k_iter_hol<true" if ranks else "k_iter_hol<false")
         assert_state_close(host(psi), ref)
         for a, b in zip((host(t) for t in ctx.holstein_obs(psi)), ref_obs):
             np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-14)
