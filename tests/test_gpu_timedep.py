@@ -93,7 +93,11 @@ def test_ribbon_ramped_disorder(torch, cheb, state):
 
 
 @pytest.mark.parametrize("state", ["packet", "dense"])
-def test_holstein_biased_barrier(torch, cheb, state):
+@pytest.mark.parametrize("rank", ["0", "1"])
+def test_holstein_biased_barrier(torch, cheb, monkeypatch, state, rank):
+    # rank "1": the walk that forms the phonon partners' ranks itself (its
+    # default past 8M states) with the per-step Delta_i; "0": the table walk
+    monkeypatch.setenv("CHEBTD_HOL_RANK", rank)
     L, nph, K, dt = 6, 4, 8, 0.2
     g = np.full(L, np.sqrt(0.5))
     D0 = np.zeros(L)
