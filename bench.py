@@ -169,7 +169,7 @@ def bench_double_well(torch, P, K):
                 orders_per_s=iters / t, us_per_order=t / iters * 1e6, transmission_x_gt_0=T,
                 norm_drift=float(np.abs(nr - nr[0]).max()),
                 energy_rel_drift=float(np.abs(e - e[0]).max() / abs(e[0])),
-                bound="one workgroup: barrier latency + one CU's fp64 rate")
+                bound="one wavefront per workgroup: per-order fp64 issue, plus a halo exchange every H orders")
 
 
 def bench_table1(torch, P, t_end=40.0, target=1e-9, cn_dts=(2e-4, 1e-4), run_limit_s=30.0):

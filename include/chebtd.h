@@ -56,9 +56,9 @@ extern "C" {
                                    /* host synchronisation)                 */
 #define CHEBTD_GRAPH 4u            /* replay each pair of steps from a     */
                                    /* captured hipGraph                     */
-#define CHEBTD_NO_PERSISTENT 8u    /* small chains: one launch per          */
-                                   /* iteration instead of the one-         */
-                                   /* workgroup persistent kernel           */
+#define CHEBTD_NO_PERSISTENT 8u    /* chains of n <= 4096: passes launched  */
+                                   /* per step instead of the whole run in  */
+                                   /* one launch                            */
 #define CHEBTD_SINGLE_ORDER 16u    /* chains and ribbons: one recursion     */
                                    /* order per pass instead of two         */
 
@@ -185,7 +185,7 @@ int chebtd_get_plan(const chebtd_ctx *ctx, double *gamma_host, double *a, double
                     double *dt, int *M);
 
 /* The passes of one step on the multi-order path (1D chains longer than
- * the one-workgroup chain kernel, honeycomb ribbons; M >= 2): the Chebyshev
+ * the whole-run chain kernels, honeycomb ribbons; M >= 2): the Chebyshev
  * orders each pass advances, in launch order.  The first pass is the step
  * head (it also forms v_1 from psi); 2 runs the two-orders kernel, 3..6 the
  * deep kernel (that many orders of the recursion of Sect. 2.2 in one pass
@@ -210,7 +210,13 @@ int chebtd_plan_passes(const chebtd_ctx *ctx, int *passes_out, int capacity, int
  * tolerance (chebtd_set_check_tol, default 1e-6 relative).
  * CHEBTD_KEEP_CHECKPOINTS stores psi_s for the adjoint (CHEBTD_ADJ_REVERSE:
  * also v_{M-1} and v_M of every step); it needs chebtd_reserve_adjoint with
- * K <= its max_steps. */
+ * K <= its max_steps.
+ * A 1D chain of 129 .. 4096 sites runs the whole call in one launch over
+ * several workgroups that wait on each other (bounded to two seconds per
+ * wait): if a wait runs out (workgroups not all resident, e.g. beside other
+ * work filling the GPU) psi is left NaN and, unless CHEBTD_NO_CHECK is set,
+ * the call returns CHEBTD_E_TIMEOUT.  Environment CHEBTD_CHAIN_MULTI=0 keeps
+ * such runs in one workgroup. */
 int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_dev,
                      double *energy_dev, unsigned flags);
 

@@ -252,7 +252,7 @@ int chebtd_destroy(chebtd_ctx *ctx)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (DevBuf *b : {&c->vA, &c->vB, &c->vC, &c->vD, &c->partials, &c->results, &c->counter, &c->gamma_dev,
                       &c->hol_occ, &c->hol_up, &c->hol_dn,
-                      &c->hol_tot, &c->hol_site, &c->hol_binom})
+                      &c->hol_tot, &c->hol_site, &c->hol_binom, &c->chainx})
         release(*b);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->ev_a) (void)hipEventDestroy(c->ev_a);
@@ -531,6 +531,10 @@ static int plan_common(Ctx *c, double dt, int M)
         for (int d = 3; d <= kMaxDepth; ++d) c->deep_rows[d] = choose_deep_rows(*c, d);
     }
     if ((rc = ensure_partials(c))) return rc;
+    if (c->kind == HKind::Chain) {
+        const size_t xb = chain_multi_scratch_bytes(chain_multi_config(c->n));
+        if (xb && (rc = ensure(c, c->chainx, xb, "chain exchange scratch"))) return rc;
+    }
     c->dt = dt;
     c->M = M;
     c->has_plan = true;

@@ -140,6 +140,7 @@ struct Ctx {
     DevBuf partials;   // double[2 * max_blocks]
     DevBuf results;    // double[16]
     DevBuf counter;    // int64[4]
+    DevBuf chainx;     // exchange strips, flags and partials of the several-workgroup chain run
     double *pinned = nullptr;  // host pinned double[16]
     double check_tol = 1e-6;
     int64_t plan_version = 0;  // bumped by every plan
@@ -228,6 +229,19 @@ hipError_t launch_holstein_obs(hipStream_t s, const double2 *psi, const uint8_t 
 int holstein_obs_blocks(int64_t nconf);
 // one-workgroup persistent chain kernel: whole K-step run in one launch
 bool chain_small_fits(int64_t n);
+// The same run over several workgroups (chain.hip): R sites per thread, T
+// threads, H halo sites per side (orders between exchanges), S own sites per
+// workgroup (R T = S + 2 H), P workgroups; R = 0 when one workgroup runs it.
+constexpr int kChainRing = 128;  // steps of norm/energy partials in flight (>= P + 1)
+constexpr int kChainMaxWG = 64;  // most workgroups of one run
+struct ChainMultiCfg {
+    int R = 0, T = 0, H = 0;
+    int64_t S = 0, P = 0;
+};
+ChainMultiCfg chain_multi_config(int64_t n);
+size_t chain_multi_scratch_bytes(const ChainMultiCfg &cfg);
+// device address of that run's timeout flag (int32) when it runs for c, else null
+int32_t *chain_multi_timeout(const Ctx &c);
 hipError_t launch_chain_small(const Ctx &c, hipStream_t s, double2 *psi, double2 *out,
                               const double2 *gamma_dev, int64_t K, double *norm_out,
                               double *energy_out, double2 *ckpt);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 #include <string>
 
 #include "internal.h"
@@ -290,8 +291,18 @@ int chebtd_propagate(chebtd_ctx *ctx, double *psi_dev, int64_t K, double *norm_d
     e = enqueue_norm(c, s, P, 2);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->pinned, c->results.p, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+    // the several-workgroup chain run's wait limit
+    int32_t *tflag = small ? chain_multi_timeout(*c) : nullptr;
+    if (e == hipSuccess && tflag) e = hipMemcpyAsync(c->pinned + 8, tflag, sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "norm check");
+    if (tflag) {
+        int32_t timed_out = 0;
+        std::memcpy(&timed_out, c->pinned + 8, sizeof(int32_t));
+        if (timed_out)
+            return fail(c, CHEBTD_E_TIMEOUT,
+                        "chebtd_propagate: a chain workgroup's wait for its neighbours ran out; psi is invalid");
+    }
     const double n0 = c->pinned[0], n1 = c->pinned[2];
     if (!std::isfinite(n1) || !std::isfinite(n0) || std::fabs(n1 - n0) > c->check_tol * n0) {
         return fail(c, CHEBTD_E_DIVERGED,

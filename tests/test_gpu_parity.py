@@ -190,6 +190,100 @@ def test_chain_parity(torch, cheb, n, flags, state):
     np.testing.assert_allclose(en, re, rtol=1e-11, atol=1e-11 * plan.a)
 
 
+# Chains of 129 .. 4096 sites run in one launch over several one-wavefront
+# workgroups that swap halo strips every H orders; every site's arithmetic is
+# that of the one-workgroup kernel, so psi is bitwise equal to it (the step
+# norm and energy add the same terms in another order).  The shapes include an
+# exchange every two orders ("2,64,2"), a last workgroup owning fewer sites
+# than its halo (n = 129 with 128 own sites per workgroup; n = 777) and
+# workgroups of four wavefronts ("2,256,96").
+def _chain_run(torch, cheb, monkeypatch, case, env, K=3, dt=0.05):
+    if env is None:
+        monkeypatch.delenv("CHEBTD_CHAIN_MULTI", raising=False)
+    else:
+        monkeypatch.setenv("CHEBTD_CHAIN_MULTI", env)
+    emin, emax = case["H"].gershgorin()
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax, 0.01)
+    ctx.plan(dt)
+    psi = dev(torch, case["psi0"])
+    nrm = torch.zeros(K, dtype=torch.float64, device="cuda")
+    en = torch.zeros(K, dtype=torch.float64, device="cuda")
+    say(f"[gpu] chain n={case['n']} workgroups={env}")
+    ctx.propagate(psi, K, nrm, en, 0)
+    torch.cuda.synchronize()
+    out = host(psi), host(nrm), host(en)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [129, 385, 777, 1500, 4096])
+@pytest.mark.parametrize("cfg", ["default", "2,64,2", "4,64,64", "8,64,128", "2,256,96"])
+def test_chain_workgroups_equal_one_workgroup(torch, cheb, monkeypatch, n, cfg):
+    case = chain_case(n, state="dense")
+    one = _chain_run(torch, cheb, monkeypatch, case, "0")
+    many = _chain_run(torch, cheb, monkeypatch, case, None if cfg == "default" else cfg)
+    assert np.array_equal(many[0], one[0])
+    np.testing.assert_allclose(many[1], one[1], rtol=1e-13)
+    np.testing.assert_allclose(many[2], one[2], rtol=1e-12, atol=1e-12 * np.abs(one[2]).max())
+
+
+@pytest.mark.parametrize("mode", [1, 2])  # CHEBTD_ADJ_STEP, CHEBTD_ADJ_SQRTM: psi checkpoints from the chain run
+def test_chain_workgroups_keep_the_same_checkpoints(torch, cheb, monkeypatch, mode):
+    n, K = 1000, 3
+    case = chain_case(n, state="dense")
+    emin, emax = case["H"].gershgorin()
+
+    def grad(env):
+        if env is None:
+            monkeypatch.delenv("CHEBTD_CHAIN_MULTI", raising=False)
+        else:
+            monkeypatch.setenv("CHEBTD_CHAIN_MULTI", env)
+        ctx = gpu_context(torch, cheb, case)
+        ctx.set_bounds(emin, emax, 0.01)
+        ctx.plan(0.05)
+        ctx.reserve_adjoint(K, mode)
+        psi = dev(torch, case["psi0"])
+        ctx.propagate(psi, K, flags=cheb.KEEP_CHECKPOINTS)
+        gbar = torch.from_numpy(W.random_state(n, 77)).cuda()
+        dV = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.adjoint(gbar, dV)
+        torch.cuda.synchronize()
+        out = host(psi), host(gbar), host(dV)
+        ctx.close()
+        return out
+
+    one, many = grad("0"), grad(None)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
+
+
+def test_chain_workgroups_report_a_wait_that_runs_out(torch, cheb, monkeypatch):
+    # a wait limit of one clock tick, set from the host, makes the workgroup
+    # that reaches an exchange before its neighbours give up: the kernel still
+    # ends, leaves psi NaN and the call reports the time-out; the next call,
+    # with the normal limit, is right again
+    case = chain_case(4096, state="dense")
+    emin, emax = case["H"].gershgorin()
+    monkeypatch.delenv("CHEBTD_CHAIN_MULTI", raising=False)
+    monkeypatch.setenv("CHEBTD_CHAIN_SPIN", "1")
+    ctx = gpu_context(torch, cheb, case)
+    ctx.set_bounds(emin, emax, 0.01)
+    ctx.plan(0.5)
+    psi = dev(torch, case["psi0"])
+    with pytest.raises(cheb.ChebError) as err:
+        ctx.propagate(psi, 2)
+    assert err.value.code == -6  # CHEBTD_E_TIMEOUT
+    assert bool(torch.isnan(psi).any())
+    monkeypatch.delenv("CHEBTD_CHAIN_SPIN")
+    psi = dev(torch, case["psi0"])
+    ctx.propagate(psi, 2)
+    torch.cuda.synchronize()
+    ref = O.propagate(case["H"], O.Plan(emin, emax, 0.5), case["psi0"], 2)
+    assert_state_close(host(psi), ref)
+    ctx.close()
+
+
 @pytest.mark.parametrize("edge,width,length", [("zigzag", 6, 300), ("zigzag", 1, 513),
                                                ("zigzag", 31, 257), ("armchair", 6, 300),
                                                ("armchair", 10, 1000), ("zigzag", 128, 200)])
