@@ -290,8 +290,9 @@ __global__ __launch_bounds__(T) void k_chain_multi(OpChain op, const double2 *ps
     // once another workgroup has timed out
     auto wait_at_least = [&](int32_t *flag, int32_t need, int64_t t0) -> bool {
         int64_t spins = 0;
-        while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (wall_clock64() - t0 > x.spin_limit ||
+        // a limit of 0 gives up at once (set from the host to test the time-out path)
+        while (x.spin_limit <= 0 || __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (x.spin_limit <= 0 || wall_clock64() - t0 > x.spin_limit ||
                 ((++spins & 255) == 0 && __hip_atomic_load(timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                 __hip_atomic_store(timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return false;
@@ -543,8 +544,9 @@ hipError_t launch_chain_multi_rt(const Ctx &c, hipStream_t s, const OpChain &op,
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c.device) != hipSuccess || khz <= 0)
         khz = 100000;
     // two seconds per wait; CHEBTD_CHAIN_SPIN (wall-clock ticks) shortens it
+    // (0: every wait gives up at once)
     int64_t limit = (int64_t)khz * 1000 * 2;
-    if (const char *env = std::getenv("CHEBTD_CHAIN_SPIN")) limit = std::max<int64_t>(1, std::atoll(env));
+    if (const char *env = std::getenv("CHEBTD_CHAIN_SPIN")) limit = std::max<int64_t>(0, std::atoll(env));
     const ChainXDev x = chain_x_layout(c, cfg, limit);
     hipLaunchKernelGGL(k_chain_multi_clear, dim3(1), dim3(128), 0, s, x.flags, x.sync, x.P);
     const dim3 grid((unsigned)cfg.P), block(T);

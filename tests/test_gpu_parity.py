@@ -259,14 +259,13 @@ def test_chain_workgroups_keep_the_same_checkpoints(torch, cheb, monkeypatch, mo
 
 
 def test_chain_workgroups_report_a_wait_that_runs_out(torch, cheb, monkeypatch):
-    # a wait limit of one clock tick, set from the host, makes the workgroup
-    # that reaches an exchange before its neighbours give up: the kernel still
-    # ends, leaves psi NaN and the call reports the time-out; the next call,
-    # with the normal limit, is right again
+    # a wait limit of zero, set from the host, makes every workgroup give up at
+    # its first wait: the kernel still ends, leaves psi NaN and the call
+    # reports the time-out; the next call, with the normal limit, is right again
     case = chain_case(4096, state="dense")
     emin, emax = case["H"].gershgorin()
     monkeypatch.delenv("CHEBTD_CHAIN_MULTI", raising=False)
-    monkeypatch.setenv("CHEBTD_CHAIN_SPIN", "1")
+    monkeypatch.setenv("CHEBTD_CHAIN_SPIN", "0")
     ctx = gpu_context(torch, cheb, case)
     ctx.set_bounds(emin, emax, 0.01)
     ctx.plan(0.5)
@@ -274,7 +273,7 @@ def test_chain_workgroups_report_a_wait_that_runs_out(torch, cheb, monkeypatch):
     with pytest.raises(cheb.ChebError) as err:
         ctx.propagate(psi, 2)
     assert err.value.code == -6  # CHEBTD_E_TIMEOUT
-    assert bool(torch.isnan(psi).any())
+    assert bool(torch.isnan(psi).all())
     monkeypatch.delenv("CHEBTD_CHAIN_SPIN")
     psi = dev(torch, case["psi0"])
     ctx.propagate(psi, 2)
