@@ -277,8 +277,9 @@ __global__ __launch_bounds__(T) void k_chain_multi(OpChain op, const double2 *ps
         };
 #pragma unroll
         for (int r = 1; r + 1 < R; ++r) row(r, Y[r - 1], Y[r + 1]);
-        const double2 left = csel(lane == 0, wave > 0 ? el : zero, l0);
-        const double2 right = csel(lane == 63, wave < NW - 1 ? er : zero, rR);
+        // one wavefront: lanes 0 and 63 already read 0 from the shifts
+        const double2 left = NW > 1 ? csel(lane == 0, wave > 0 ? el : zero, l0) : l0;
+        const double2 right = NW > 1 ? csel(lane == 63, wave < NW - 1 ? er : zero, rR) : rR;
         if (R == 1) {
             row(0, left, right);
         } else {
