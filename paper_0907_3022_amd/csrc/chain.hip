@@ -453,16 +453,16 @@ bool chain_small_fits(int64_t n) { return n >= 1 && n <= 4096; }
 
 // Workgroups of one wavefront: an order then needs no barrier, only lane
 // shifts, and the run pays an exchange every H orders instead.  Measured on
-// MI355X (quartic well on [-20, 20], dt = 0.5): orders per second against the
-// one-workgroup kernel, 5.5M / 5.3M at n = 160, 5.6M / 4.1M at 512, 5.2M /
-// 3.0M at 1500 (two sites per lane, H = 32), 5.0M / 3.0M at 2048 and 4.7M /
-// 2.1M at 4096 (four sites per lane, H = 64; two per lane, or H = 32, ran
-// 10-20% slower there).  CHEBTD_CHAIN_MULTI = "R,T,H" overrides, "0" keeps
-// one workgroup.
+// MI355X (quartic well on [-20, 20], dt = 0.5), orders per second: 6.6M at
+// n = 400 and 5.6M at 1024 with two sites per lane and H = 40 (H = 32: 6.3M,
+// 5.2M); 5.6M at 1500, 5.4M at 2048 and 5.3M at 4096 with four sites per lane
+// and H = 80 (H = 64: 5.4M, 5.3M, 5.1M); the one-workgroup kernel runs 4.0M,
+// 3.8M, 3.0M, 3.0M and 2.1M there.  CHEBTD_CHAIN_MULTI = "R,T,H" overrides,
+// "0" keeps one workgroup.
 ChainMultiCfg chain_multi_config(int64_t n)
 {
     ChainMultiCfg cfg;
-    int R = n <= 1536 ? 2 : 4, T = 64, H = n <= 1536 ? 32 : 64;
+    int R = n <= 1024 ? 2 : 4, T = 64, H = n <= 1024 ? 40 : 80;
     if (const char *env = std::getenv("CHEBTD_CHAIN_MULTI"))
         if (std::sscanf(env, "%d,%d,%d", &R, &T, &H) != 3) R = 0;
     const bool shape = (R == 1 && T == 512) || (R == 2 && T == 256) || (R == 2 && T == 512) || (R == 4 && T == 256) ||
