@@ -467,7 +467,8 @@ ChainMultiCfg chain_multi_config(int64_t n)
         if (std::sscanf(env, "%d,%d,%d", &R, &T, &H) != 3) R = 0;
     const bool shape = (R == 1 && T == 512) || (R == 2 && T == 256) || (R == 2 && T == 512) || (R == 4 && T == 256) ||
                        (R == 2 && T == 64) || (R == 4 && T == 64) || (R == 8 && T == 64) || (R == 4 && T == 128);
-    if (!shape || H < 2 || (H & 1) || R * T < 3 * H || !chain_small_fits(n)) return cfg;
+    // from 129 sites (below that one workgroup holds the chain with one site per lane)
+    if (!shape || H < 2 || (H & 1) || R * T < 3 * H || n <= 128 || !chain_small_fits(n)) return cfg;
     const int64_t S = (int64_t)R * T - 2 * H, P = (n + S - 1) / S;
     if (P < 2 || P > kChainMaxWG) return cfg;
     cfg.R = R;

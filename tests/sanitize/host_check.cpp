@@ -2,8 +2,8 @@
 // tests: the plan helpers (Bessel values by Miller's backward recurrence,
 // truncation order, weights of eq. (U_1)), the Holstein basis tables and CSR
 // builder of eq. (ghm) (threaded), the argument checks of the C ABI entry
-// points and the batched schedule's split of M into passes, none of which
-// needs a GPU.  Built with AddressSanitizer and
+// points, the batched schedule's split of M into passes and the shapes of
+// the several-workgroup chain run, none of which needs a GPU.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer (host code only); any report aborts the run.
 // Exit status 0: every check passed.
 #include <cmath>
@@ -118,6 +118,23 @@ int main()
                 CHECK(plan_passes(rib, M) == want);
             }
         }
+    // the several-workgroup chain run's shapes: every chain site owned by
+    // exactly one workgroup, strips inside the own sites, halo depth even
+    // and at most a third of a workgroup's sites, the epoch ring deep
+    // enough, the scratch sized for the strips; one workgroup otherwise
+    for (int64_t n = 1; n <= 4200; ++n) {
+        const ChainMultiCfg cfg = chain_multi_config(n);
+        if (cfg.R == 0) {
+            CHECK(n <= 128 || n > 4096);
+            CHECK(chain_multi_scratch_bytes(cfg) == 0);
+            continue;
+        }
+        CHECK(n > 128 && n <= 4096 && cfg.T == 64);
+        CHECK((int64_t)cfg.R * cfg.T == cfg.S + 2 * cfg.H && cfg.S >= cfg.H && cfg.H >= 2 && cfg.H % 2 == 0);
+        CHECK(cfg.P >= 2 && cfg.P <= kChainMaxWG && kChainRing >= cfg.P + 1);
+        CHECK(cfg.P * cfg.S >= n && (cfg.P - 1) * cfg.S < n);
+        CHECK(chain_multi_scratch_bytes(cfg) >= (size_t)2 * cfg.P * 4 * cfg.H * 16);
+    }
     std::printf("host_check: %d failures\n", failures);
     return failures == 0 ? 0 : 1;
 }
