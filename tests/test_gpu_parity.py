@@ -258,6 +258,41 @@ def test_chain_workgroups_keep_the_same_checkpoints(torch, cheb, monkeypatch, mo
         assert np.array_equal(a, b)
 
 
+def test_chain_workgroups_two_streams_at_once(torch, cheb, monkeypatch):
+    # two contexts on two streams run the several-workgroup chain at the same
+    # time: each has its own exchange scratch and both fit the GPU together;
+    # each result equals the same run alone
+    monkeypatch.delenv("CHEBTD_CHAIN_MULTI", raising=False)
+    case = chain_case(4096, state="dense")
+    emin, emax = case["H"].gershgorin()
+    Vd = dev(torch, case["V"])
+    starts = [case["psi0"], W.random_state(4096, 5)]
+    ctxs = []
+    for st in (torch.cuda.Stream(), torch.cuda.Stream()):
+        ctx = cheb.Context(stream=st)
+        ctx.chain1d(Vd, case["dx"])
+        ctx.set_bounds(emin, emax, 0.01)
+        ctx.plan(0.5)
+        ctxs.append(ctx)
+    alone = []
+    for ctx, p0 in zip(ctxs, starts):
+        psi = dev(torch, p0)
+        torch.cuda.synchronize()
+        ctx.propagate(psi, 3, flags=cheb.NO_CHECK)
+        torch.cuda.synchronize()
+        alone.append(host(psi))
+    both = [dev(torch, p0) for p0 in starts]
+    torch.cuda.synchronize()
+    say("[gpu] two chain runs on two streams")
+    for ctx, psi in zip(ctxs, both):
+        ctx.propagate(psi, 3, flags=cheb.NO_CHECK)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, both):
+        assert np.array_equal(a, host(b))
+    for ctx in ctxs:
+        ctx.close()
+
+
 def test_chain_workgroups_report_a_wait_that_runs_out(torch, cheb, monkeypatch):
     # a wait limit of zero, set from the host, makes every workgroup give up at
     # its first wait: the kernel still ends, leaves psi NaN and the call
